@@ -1,0 +1,178 @@
+/*
+ * sc_lbm.h -- C ABI of the MI355X (gfx950) Shan-Chen pseudo-potential lattice
+ * Boltzmann hot path.
+ *
+ * Method: Peng, Ayala, Ayala & Wang, "Isotropy and spurious currents in
+ * pseudo-potential multiphase lattice Boltzmann models".
+ *   - interaction force   F(x) = -G psi(x) sum_a w_a psi(x + e_a) e_a     (Sec. 2, Eq. (1))
+ *     on the E4/E6/E8/E10 isotropic stencils (Sec. 2, around Eq. (2));
+ *     w_a = c0 * w_hat_a with w_hat normalised to sum w_hat e_x^2 = 1;
+ *   - Guo-forced lattice Boltzmann step with pull streaming               (Sec. 2, Eq. (3)-(4)),
+ *     u = (sum_b f_b c_b + F/2) / rho                                     (Sec. 4, Eq. (7));
+ *   - psi = psi0 (1 - exp(-rho / rho_psi)), or psi = rho for exact tests;
+ *   - pressure p = cs2 rho + G c0 psi^2 / 2 (the psi definition of Sec. 3);
+ *   - lattices D2Q9 (Table 1) and D3Q19 (Sec. 3); D3Q19 also with MRT
+ *     collision (rates grouped conserved / bulk / shear = 1/tau / ghost).
+ *
+ * Conventions
+ *   - Lattice units, dt = dx = 1, periodic in every axis.
+ *   - Node index i = x + nx (y + ny z).  Host field arrays passed to or
+ *     returned from this library use that order; vector fields are [D][N].
+ *   - State buffers hold the post-collision distributions minus w_b rho_ref,
+ *     [Q][N], velocities in this order (c_x, c_y[, c_z]):
+ *       D2Q9:  (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1)
+ *       D3Q19: (0,0,0) (1,0,0) (-1,0,0) (0,1,0) (0,-1,0) (0,0,1) (0,0,-1)
+ *              (1,1,0) (-1,-1,0) (1,-1,0) (-1,1,0) (1,0,1) (-1,0,-1)
+ *              (1,0,-1) (-1,0,1) (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1)
+ *     so the next step pulls f_b(x) = state_b(x - c_b) + w_b rho_ref.
+ *   - Every entry point returns SC_OK (0) or a negative SC_E_* code and
+ *     never aborts or throws.  sc_lbm_strerror() names the code.
+ *   - All host buffers are caller-owned; the library copies inputs and
+ *     never keeps a host pointer beyond the call.
+ *   - Work is enqueued on the stream given at creation (a hipStream_t; NULL
+ *     makes the library create its own).  sc_lbm_observe / sc_lbm_force and
+ *     every convergence check synchronise that stream.
+ *   - A handle may be used from one host thread at a time.
+ */
+#ifndef SC_LBM_H
+#define SC_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define SC_OK 0
+#define SC_E_INVAL (-1)        /* invalid argument or parameter set         */
+#define SC_E_NOMEM (-2)        /* device or host allocation failed          */
+#define SC_E_DEVICE (-3)       /* HIP runtime error (no GPU, launch failure) */
+#define SC_E_UNSUPPORTED (-4)  /* valid but not implemented combination     */
+#define SC_E_NONFINITE (-5)    /* a reduction saw a NaN / Inf node          */
+
+/* ---- enumerations ------------------------------------------------------ */
+#define SC_D2Q9 0
+#define SC_D3Q19 1
+
+#define SC_PSI_EXP 0           /* psi = psi0 (1 - exp(-rho / rho_psi))      */
+#define SC_PSI_IDENTITY 1      /* psi = rho                                 */
+
+#define SC_SRT 0
+#define SC_MRT 1               /* D3Q19 only                               */
+
+#define SC_FP32_SHIFTED 0      /* float state stored as f - w rho_ref       */
+#define SC_FP64 1              /* double state (same shift)                 */
+
+/* ---- problem statement -------------------------------------------------- */
+typedef struct sc_lbm_params {
+    int32_t lattice;      /* SC_D2Q9 or SC_D3Q19                                 */
+    int32_t nx, ny, nz;   /* grid; nz must be 1 for SC_D2Q9                       */
+    int32_t order;        /* force-stencil isotropy order: 4, 6, 8, 10 (2D);
+                             4, 6, 8 (3D)                                         */
+    int32_t psi_kind;     /* SC_PSI_EXP or SC_PSI_IDENTITY                        */
+    double G;             /* interaction strength (Eq. (1)); G < 0 attracts       */
+    double c0;            /* force-weight scale: w_a = c0 w_hat_a (1/3 for the
+                             classic nearest-neighbour weights 1/9, 1/36)         */
+    double psi0, rho_psi; /* psi = psi0 (1 - exp(-rho / rho_psi))                 */
+    double tau;           /* relaxation time (Eq. (3)), > 1/2                     */
+    int32_t collision;    /* SC_SRT or SC_MRT                                     */
+    int32_t precision;    /* SC_FP32_SHIFTED or SC_FP64                           */
+    double s_bulk;        /* MRT rate of the c^2 (bulk) moment                    */
+    double s_ghost;       /* MRT rate of all non-hydrodynamic moments             */
+    double rho_ref;       /* storage shift (normally 1)                           */
+    int32_t obs_every;    /* K: steps between convergence checks (default 100)    */
+    int32_t variant;      /* launch shape of the fused kernel; -1 = automatic     */
+} sc_lbm_params;
+
+/* Fills *p with the defaults: D2Q9 64x64, E4, G = -5, c0 = 1/3, exp psi with
+ * psi0 = rho_psi = 1, tau = 1, SRT, FP32 shifted, MRT rates 1.2, rho_ref = 1,
+ * K = 100, automatic variant. */
+void sc_lbm_default_params(sc_lbm_params* p);
+
+/* ---- observables (FP64 reductions) -------------------------------------- */
+typedef struct sc_lbm_obs {
+    int64_t step;         /* time step of the observed state                      */
+    double mass;          /* sum rho                                              */
+    double mom[3];        /* sum rho u                                            */
+    double max_u;         /* max |u|        (spurious-velocity maximum, Sec. 3)   */
+    double mean_u;        /* mean |u|       (field-averaged spurious velocity)    */
+    double l2_u;          /* sqrt(mean |u|^2)                                     */
+    double rho_in;        /* rho at the centre node (nx/2, ny/2, nz/2)            */
+    double rho_out;       /* rho at node 0                                        */
+    double p_in, p_out;   /* p = cs2 rho + G c0 psi^2 / 2 at those nodes           */
+    double dp;            /* p_in - p_out (Laplace pressure jump)                 */
+    double radius;        /* equivalent radius from sum (rho - rho_out) / (rho_in - rho_out) */
+    double d_max_u;       /* |max_u - max_u at the previous check|, or -1         */
+    int64_t nonfinite;    /* nodes with a non-finite rho or u                     */
+    int32_t converged_by; /* 0 no; 1 d_max_u < tol; 2 FP32 round-off floor        */
+    int32_t status;       /* SC_OK or SC_E_NONFINITE                              */
+} sc_lbm_obs;
+
+typedef struct sc_lbm sc_lbm;
+
+/* Bytes of one state buffer: Q * nx * ny * nz * (4 or 8); 0 if *p is invalid. */
+size_t sc_lbm_state_bytes(const sc_lbm_params* p);
+
+/* Validate *p, take the device buffers and initialise the state to
+ * f = feq(rho_init, u = 0) (the droplet test of Sec. 3 starts this way).
+ *   rho_init  host [N] doubles, or NULL for rho = 1 everywhere;
+ *   dev_a/b   two device buffers of sc_lbm_state_bytes(p) bytes each, owned
+ *             by the caller and kept until sc_lbm_destroy; both NULL makes
+ *             the library allocate (and free) its own;
+ *   hip_stream  the hipStream_t to enqueue on, or NULL.
+ * *out is written only on success.  Errors: SC_E_INVAL (bad parameters,
+ * non-finite rho_init, only one buffer given), SC_E_NOMEM, SC_E_DEVICE. */
+int sc_lbm_create(const sc_lbm_params* p, const double* rho_init, void* dev_a, void* dev_b,
+                  void* hip_stream, sc_lbm** out);
+
+/* Advance the state (Sec. 2, Eq. (1), (3), (4): psi, force, collision and
+ * pull streaming fused in one kernel per step).
+ *   max_steps  steps to run (>= 0);
+ *   tol        0: run exactly max_steps, asynchronously (nothing is read
+ *              back); > 0: every K = obs_every steps reduce max |u| and stop
+ *              once |max_u - previous max_u| < tol, or (FP32 state only)
+ *              once it stays within 4 ulp of max_u for 10 checks in a row;
+ *   steps_done  may be NULL; receives the steps actually taken.
+ * Returns SC_E_NONFINITE as soon as a check sees a non-finite node. */
+int sc_lbm_step(sc_lbm* h, int64_t max_steps, double tol, int64_t* steps_done);
+
+/* Interaction force of Eq. (1) with the handle's stencil, G and c0.
+ *   psi_in  host [N] psi field, or NULL to use psi(rho) of the current state;
+ *   F_out   host [D][N] doubles (caller-owned).
+ * Computed in the state precision; synchronous. */
+int sc_lbm_force(sc_lbm* h, const double* psi_in, double* F_out);
+
+/* FP64 reductions of the current state (see sc_lbm_obs) and optional host
+ * copies of its fields, each nullable: rho_out [N], u_out [D][N] doubles,
+ * f_out the raw state buffer (sc_lbm_state_bytes bytes: post-collision,
+ * shifted by w_b rho_ref, [Q][N] in the library's velocity order).
+ * Synchronous. */
+int sc_lbm_observe(sc_lbm* h, sc_lbm_obs* obs, double* rho_out, double* u_out, void* f_out);
+
+/* Restore a state written by sc_lbm_observe(f_out) (checkpoint / resume):
+ * f_in host buffer of sc_lbm_state_bytes bytes; step sets the step counter. */
+int sc_lbm_set_state(sc_lbm* h, const void* f_in, int64_t step);
+
+/* Device pointer of the buffer holding the current state (for callers that
+ * keep the data resident); NULL on a NULL handle. */
+void* sc_lbm_state_ptr(sc_lbm* h);
+
+/* Name of the launch shape in use and the number of shapes available for
+ * this lattice (for tuning sweeps through sc_lbm_params.variant). */
+const char* sc_lbm_variant_name(const sc_lbm* h);
+int sc_lbm_num_variants(int32_t lattice);
+
+void sc_lbm_destroy(sc_lbm* h);
+const char* sc_lbm_strerror(int code);
+
+/* Detail of the last HIP failure seen by this host thread (which call, the
+ * HIP error string and code); "" if none.  Valid until the next failure. */
+const char* sc_lbm_last_error_detail(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SC_LBM_H */

@@ -1,0 +1,241 @@
+// kernels.h -- device helpers and launcher declarations of the gfx950 path.
+//
+// State layout (both precisions): structure of arrays f[Q][N], node index
+// i = x + nx (y + ny z), velocity order of lattice.h.  The stored value is
+// the POST-collision distribution shifted by its rest weight,
+//     g_b(x) = f*_b(x) - w_b rho_ref,
+// so one step pulls f_b(x, t+1) = f*_b(x - c_b, t) (Sec. 2, Eq. (3)).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lattice.h"
+
+namespace sclbm {
+
+template <typename T>
+struct StepArgs {
+    const T* __restrict__ fin;   // state at t (post-collision, shifted)
+    T* __restrict__ fout;        // state at t+1
+    int nx, ny, nz;
+    int64_t n;                   // nx * ny * nz
+    T gc0;                       // G * c0 (force prefactor, Sec. 2 Eq. (1))
+    T omega;                     // 1 / tau
+    T guo;                       // 1 - 1 / (2 tau)   (Guo forcing, Eq. (4))
+    T rho_ref;                   // storage shift
+    T psi0, inv_rho_psi;         // psi = psi0 (1 - exp(-rho / rho_psi))
+    int psi_kind;                // 0 exp form, 1 psi = rho
+    T s_bulk, s_ghost;           // MRT rates (D3Q19)
+};
+
+template <typename T>
+__device__ __forceinline__ T psi_of(T rho, const StepArgs<T>& a)
+{
+    if (a.psi_kind == 1) return rho;
+    return a.psi0 * (T(1) - exp(-rho * a.inv_rho_psi));
+}
+
+__device__ __forceinline__ int wrap_any(int v, int n)
+{
+    int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+// ---------------------------------------------------------------- D2Q9 ----
+// Pull the nine shifted distributions of node (x, y): value b comes from
+// (x - cx_b, y - cy_b).  xm/xp/ym/yp are the wrapped neighbours.
+template <typename T>
+__device__ __forceinline__ void pull_d2q9(const T* __restrict__ f, int64_t n, int nx,
+                                          int x, int xm, int xp, int y, int ym, int yp, T (&g)[9])
+{
+    const int64_t r0 = (int64_t)y * nx, rm = (int64_t)ym * nx, rp = (int64_t)yp * nx;
+    g[0] = f[0 * n + r0 + x];
+    g[1] = f[1 * n + r0 + xm];
+    g[2] = f[2 * n + rm + x];
+    g[3] = f[3 * n + r0 + xp];
+    g[4] = f[4 * n + rp + x];
+    g[5] = f[5 * n + rm + xm];
+    g[6] = f[6 * n + rm + xp];
+    g[7] = f[7 * n + rp + xp];
+    g[8] = f[8 * n + rp + xm];
+}
+
+template <typename T>
+__device__ __forceinline__ T sum9(const T (&g)[9])
+{
+    return ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+}
+
+// Guo-forced BGK collision (Sec. 2, Eq. (3)-(4)) on shifted values.
+// drho = rho - rho_ref = sum_b g_b;  u = (sum_b g_b c_b + F/2) / rho.
+template <typename T>
+__device__ __forceinline__ void collide_d2q9_srt(T (&g)[9], T drho, T Fx, T Fy, const StepArgs<T>& a)
+{
+    const T rho = a.rho_ref + drho;
+    const T jx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
+    const T jy = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
+    const T inv = T(1) / rho;
+    const T ux = (jx + T(0.5) * Fx) * inv;
+    const T uy = (jy + T(0.5) * Fy) * inv;
+    const T usq = T(1.5) * (ux * ux + uy * uy);
+    const T uF = ux * Fx + uy * Fy;
+    const T om = a.omega, gu = a.guo;
+#pragma unroll
+    for (int b = 0; b < 9; ++b) {
+        const T cu = T(D2Q9::cx[b]) * ux + T(D2Q9::cy[b]) * uy;
+        const T cF = T(D2Q9::cx[b]) * Fx + T(D2Q9::cy[b]) * Fy;
+        const T w = T(D2Q9::w[b]);
+        const T geq = w * (drho + rho * (T(3) * cu + T(4.5) * cu * cu - usq));
+        const T phi = gu * w * (T(3) * (cF - uF) + T(9) * cu * cF);
+        g[b] = g[b] - om * (g[b] - geq) + phi;
+    }
+    // Collision conserves mass exactly; close the balance through the rest
+    // population so the rounding of feq and phi leaves no systematic drift.
+    g[0] = drho - (((g[1] + g[2]) + (g[3] + g[4])) + ((g[5] + g[6]) + (g[7] + g[8])));
+}
+
+// Sum of populations 1..18 in a fixed order (mass balance of the collision).
+template <typename T>
+__device__ __forceinline__ T sum19_moving(const T (&g)[19])
+{
+    T s0 = (g[1] + g[2]) + (g[3] + g[4]);
+    T s1 = (g[5] + g[6]) + (g[7] + g[8]);
+    T s2 = (g[9] + g[10]) + (g[11] + g[12]);
+    T s3 = (g[13] + g[14]) + (g[15] + g[16]);
+    return ((s0 + s1) + (s2 + s3)) + (g[17] + g[18]);
+}
+
+// --------------------------------------------------------------- D3Q19 ----
+template <typename T>
+__device__ __forceinline__ T sum19(const T (&g)[19])
+{
+    T s0 = (g[0] + g[1]) + (g[2] + g[3]);
+    T s1 = (g[4] + g[5]) + (g[6] + g[7]);
+    T s2 = (g[8] + g[9]) + (g[10] + g[11]);
+    T s3 = (g[12] + g[13]) + (g[14] + g[15]);
+    T s4 = (g[16] + g[17]) + g[18];
+    return ((s0 + s1) + (s2 + s3)) + s4;
+}
+
+// Guo-forced collision for D3Q19.  MRT is written as BGK at the ghost rate
+// plus corrections on the six viscous moments:
+//   f* = f - s_g n + (1 - s_g/2) phihat
+//        + sum_{k in bulk, shear} (s_g - s_k) [m_k . (n + phihat/2)] m_k / |m_k|^2
+// with n = f - feq and m_k the (mutually orthogonal) moment vectors
+//   bulk:  19 c^2 - 30                     (|m|^2 = 2394)
+//   shear: 2cx^2 - cy^2 - cz^2 (36), cy^2 - cz^2 (12), cx cy, cy cz, cx cz (4).
+// The conserved moments drop out because m.(n + phihat/2) = 0 for rho and j.
+// This equals M^-1 S M with the rates grouped as conserved / bulk / shear /
+// ghost; with all rates 1/tau it is exactly the BGK step.
+template <typename T, bool MRT>
+__device__ __forceinline__ void collide_d3q19(T (&g)[19], T drho, T Fx, T Fy, T Fz, const StepArgs<T>& a)
+{
+    using L = D3Q19;
+    const T rho = a.rho_ref + drho;
+    T jx = T(0), jy = T(0), jz = T(0);
+#pragma unroll
+    for (int b = 1; b < 19; ++b) {
+        if (L::cx[b] > 0) jx += g[b]; else if (L::cx[b] < 0) jx -= g[b];
+        if (L::cy[b] > 0) jy += g[b]; else if (L::cy[b] < 0) jy -= g[b];
+        if (L::cz[b] > 0) jz += g[b]; else if (L::cz[b] < 0) jz -= g[b];
+    }
+    const T inv = T(1) / rho;
+    const T ux = (jx + T(0.5) * Fx) * inv;
+    const T uy = (jy + T(0.5) * Fy) * inv;
+    const T uz = (jz + T(0.5) * Fz) * inv;
+    const T usq = T(1.5) * (ux * ux + uy * uy + uz * uz);
+    const T uF = ux * Fx + uy * Fy + uz * Fz;
+    if (!MRT) {
+        const T om = a.omega, gu = a.guo;
+#pragma unroll
+        for (int b = 0; b < 19; ++b) {
+            const T cu = T(L::cx[b]) * ux + T(L::cy[b]) * uy + T(L::cz[b]) * uz;
+            const T cF = T(L::cx[b]) * Fx + T(L::cy[b]) * Fy + T(L::cz[b]) * Fz;
+            const T w = T(L::w[b]);
+            const T geq = w * (drho + rho * (T(3) * cu + T(4.5) * cu * cu - usq));
+            const T phi = gu * w * (T(3) * (cF - uF) + T(9) * cu * cF);
+            g[b] = g[b] - om * (g[b] - geq) + phi;
+        }
+        g[0] = drho - sum19_moving(g);
+    } else {
+        const T sg = a.s_ghost;
+        const T gh = T(1) - T(0.5) * sg;
+        T v[19];
+        T mb = T(0), m1 = T(0), m2 = T(0), m3 = T(0), m4 = T(0), m5 = T(0);
+#pragma unroll
+        for (int b = 0; b < 19; ++b) {
+            const int cx = L::cx[b], cy = L::cy[b], cz = L::cz[b];
+            const T cu = T(cx) * ux + T(cy) * uy + T(cz) * uz;
+            const T cF = T(cx) * Fx + T(cy) * Fy + T(cz) * Fz;
+            const T w = T(L::w[b]);
+            const T geq = w * (drho + rho * (T(3) * cu + T(4.5) * cu * cu - usq));
+            const T ph = w * (T(3) * (cF - uF) + T(9) * cu * cF);   // phihat
+            const T ne = g[b] - geq;
+            v[b] = ne + T(0.5) * ph;
+            g[b] = g[b] - sg * ne + gh * ph;
+            const int c2 = cx * cx + cy * cy + cz * cz;
+            mb += T(19 * c2 - 30) * v[b];
+            const int p1 = 2 * cx * cx - cy * cy - cz * cz, p2 = cy * cy - cz * cz;
+            if (p1) m1 += T(p1) * v[b];
+            if (p2) m2 += T(p2) * v[b];
+            if (cx * cy) m3 += T(cx * cy) * v[b];
+            if (cy * cz) m4 += T(cy * cz) * v[b];
+            if (cx * cz) m5 += T(cx * cz) * v[b];
+        }
+        const T kb = (sg - a.s_bulk) * mb * T(1.0 / 2394.0);
+        const T ks = sg - a.omega;
+        const T k1 = ks * m1 * T(1.0 / 36.0), k2 = ks * m2 * T(1.0 / 12.0);
+        const T k3 = ks * m3 * T(0.25), k4 = ks * m4 * T(0.25), k5 = ks * m5 * T(0.25);
+#pragma unroll
+        for (int b = 0; b < 19; ++b) {
+            const int cx = L::cx[b], cy = L::cy[b], cz = L::cz[b];
+            const int c2 = cx * cx + cy * cy + cz * cz;
+            T d = kb * T(19 * c2 - 30);
+            const int p1 = 2 * cx * cx - cy * cy - cz * cz, p2 = cy * cy - cz * cz;
+            if (p1) d += k1 * T(p1);
+            if (p2) d += k2 * T(p2);
+            if (cx * cy) d += k3 * T(cx * cy);
+            if (cy * cz) d += k4 * T(cy * cz);
+            if (cx * cz) d += k5 * T(cx * cz);
+            g[b] += d;
+        }
+        g[0] = drho - sum19_moving(g);
+    }
+}
+
+// ------------------------------------------------------------ launchers ----
+// Fused force + collide + pull-stream step.  `variant` picks a launch shape
+// (see kernels_2d.hip / kernels_3d.hip); returns hipSuccess or an error.
+hipError_t launch_step_d2q9(const StepArgs<float>& a, int order, int variant, hipStream_t s);
+hipError_t launch_step_d2q9(const StepArgs<double>& a, int order, int variant, hipStream_t s);
+hipError_t launch_step_d3q19(const StepArgs<float>& a, int order, bool mrt, int variant, hipStream_t s);
+hipError_t launch_step_d3q19(const StepArgs<double>& a, int order, bool mrt, int variant, hipStream_t s);
+int num_variants_d2q9();
+int num_variants_d3q19();
+const char* variant_name_d2q9(int v);
+const char* variant_name_d3q19(int v);
+
+// Initial state: g_b(x) = w_b (rho0(x + c_b) - rho_ref), i.e. the pull of
+// the next step sees f = feq(rho0, u = 0) everywhere.
+hipError_t launch_init(int lattice, void* f, int precision, const double* rho0, int nx, int ny, int nz,
+                       double rho_ref, hipStream_t s);
+
+// Observables: macroscopic fields of the current state and FP64 reductions.
+struct ObsBuffers {
+    double* rho;      // [N]
+    void* psi;        // [N] in the state precision
+    double* j;        // [D][N] sum_b f_b c_b
+    double* F;        // [D][N]
+    double* u;        // [D][N]
+    double* partials; // [nblk][8]
+    double* result;   // [8]
+    int nblk;
+};
+hipError_t launch_macro(int lattice, int precision, const void* f, const void* args, ObsBuffers& ob,
+                        hipStream_t s);
+hipError_t launch_force(int lattice, int precision, int order, const void* args, ObsBuffers& ob,
+                        bool with_velocity, hipStream_t s);
+hipError_t launch_psi_from_host(int precision, const double* psi_dev_d, void* psi, int64_t n, hipStream_t s);
+hipError_t launch_reduce(int dim, ObsBuffers& ob, int64_t n, hipStream_t s);
+
+}  // namespace sclbm

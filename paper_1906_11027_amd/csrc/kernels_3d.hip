@@ -1,0 +1,218 @@
+// kernels_3d.hip -- fused D3Q19 step for gfx950 (SRT or MRT, E4/E6/E8
+// force stencil, Guo forcing, pull streaming).
+//
+// z-marching kernel: a block owns an x-y tile of TX x TY nodes (TX x TYB
+// threads, RPT rows per thread) and a z range [z0, z0 + H).  It walks the
+// planes z0 - R ... z0 + H + R - 1; for each plane it pulls the 19 values of
+// its tile nodes (kept in registers), writes psi for the tile plus a ring of
+// width R into a slot of an LDS ring buffer of 2R + 2 planes, and -- once
+// the psi planes z - R ... z + R are resident -- computes F, collides and
+// stores plane z = (current - R).  The f registers of the last R + 1 planes
+// rotate through a statically indexed window (the z loop is unrolled by
+// R + 1), so each tile node is read from HBM once per step; only the halo
+// ring and the 2R extra planes per block are pulled twice (L2 hits).
+// One barrier per plane: the 2R + 2 slots keep the next write away from the
+// 2R + 1 planes still being read.
+#include "kernels.h"
+
+namespace sclbm {
+
+template <typename T>
+__device__ __forceinline__ void pull_d3q19(const T* __restrict__ f, int64_t n, const int64_t (&zo)[3],
+                                           const int64_t (&yo)[3], const int (&xo)[3], T (&g)[19])
+{
+#pragma unroll
+    for (int b = 0; b < 19; ++b)
+        g[b] = f[b * n + zo[1 - D3Q19::cz[b]] + yo[1 - D3Q19::cy[b]] + xo[1 - D3Q19::cx[b]]];
+}
+
+template <typename T, int ORDER, bool MRT, int TX, int TYB, int RPT>
+__global__ void __launch_bounds__(TX* TYB)
+k_d3q19_march(StepArgs<T> a, int H)
+{
+    using ST = Stencil<3, ORDER>;
+    constexpr int R = ST::R;
+    constexpr int TY = TYB * RPT;
+    constexpr int LW = TX + 2 * R;
+    constexpr int LH = TY + 2 * R;
+    constexpr int PL = LW * LH;          // one psi plane
+    constexpr int NS = 2 * R + 2;        // psi ring slots
+    constexpr int NT = TX * TYB;
+    constexpr int W = R + 1;             // f register window
+    __shared__ T psi_s[NS * PL];
+
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int64_t n = a.n;
+    const int64_t nxy = (int64_t)nx * ny;
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int tid = ty * TX + tx;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * H;
+
+    const int xr = x0 + tx;
+    const bool xin = xr < nx;
+    const int x = xin ? xr : xr % nx;
+    int xo[3];
+    xo[0] = x == 0 ? nx - 1 : x - 1;
+    xo[1] = x;
+    xo[2] = x == nx - 1 ? 0 : x + 1;
+    int64_t yo[RPT][3];
+    bool yin[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int yr = y0 + ty * RPT + k;
+        yin[k] = yr < ny;
+        const int y = yr < ny ? yr : yr % ny;
+        yo[k][0] = (int64_t)(y == 0 ? ny - 1 : y - 1) * nx;
+        yo[k][1] = (int64_t)y * nx;
+        yo[k][2] = (int64_t)(y == ny - 1 ? 0 : y + 1) * nx;
+    }
+
+    T g[W][RPT][19];
+    T dr[W][RPT];
+    const int nplanes = H + 2 * R;
+
+    for (int j0 = 0; j0 < nplanes; j0 += W) {
+#pragma unroll
+        for (int s = 0; s < W; ++s) {
+            const int j = j0 + s;
+            if (j < nplanes) {   // uniform across the block
+                const int zc = wrap_any(z0 - R + j, nz);
+                int64_t zo[3];
+                zo[0] = (int64_t)(zc == 0 ? nz - 1 : zc - 1) * nxy;
+                zo[1] = (int64_t)zc * nxy;
+                zo[2] = (int64_t)(zc == nz - 1 ? 0 : zc + 1) * nxy;
+                T* slot = psi_s + (j % NS) * PL;
+#pragma unroll
+                for (int k = 0; k < RPT; ++k) {
+                    pull_d3q19(a.fin, n, zo, yo[k], xo, g[s][k]);
+                    dr[s][k] = sum19(g[s][k]);
+                    slot[(ty * RPT + k + R) * LW + tx + R] = psi_of(a.rho_ref + dr[s][k], a);
+                }
+                constexpr int RING = PL - TX * TY;
+                for (int i = tid; i < RING; i += NT) {
+                    int lx, ly;
+                    if (i < R * LW) {
+                        ly = i / LW;
+                        lx = i - ly * LW;
+                    } else if (i < 2 * R * LW) {
+                        const int jj = i - R * LW;
+                        ly = TY + R + jj / LW;
+                        lx = jj % LW;
+                    } else {
+                        const int jj = i - 2 * R * LW;
+                        ly = R + jj / (2 * R);
+                        const int c = jj % (2 * R);
+                        lx = c < R ? c : TX + c;
+                    }
+                    const int hx = wrap_any(x0 - R + lx, nx);
+                    const int hy = wrap_any(y0 - R + ly, ny);
+                    int hxo[3];
+                    int64_t hyo[3];
+                    hxo[0] = hx == 0 ? nx - 1 : hx - 1;
+                    hxo[1] = hx;
+                    hxo[2] = hx == nx - 1 ? 0 : hx + 1;
+                    hyo[0] = (int64_t)(hy == 0 ? ny - 1 : hy - 1) * nx;
+                    hyo[1] = (int64_t)hy * nx;
+                    hyo[2] = (int64_t)(hy == ny - 1 ? 0 : hy + 1) * nx;
+                    T h[19];
+                    pull_d3q19(a.fin, n, zo, hyo, hxo, h);
+                    slot[ly * LW + lx] = psi_of(a.rho_ref + sum19(h), a);
+                }
+                __syncthreads();
+
+                if (j >= 2 * R) {
+                    const int sc = (s + 1) % W;          // register slot of plane j - R (static after unrolling)
+                    const int zrel = j - 2 * R;          // 0 .. H-1
+                    const int zr = z0 + zrel;
+                    const int cs = (j - R) % NS;         // psi slot of the centre plane
+                    int sl[2 * R + 1];
+#pragma unroll
+                    for (int d = -R; d <= R; ++d) sl[d + R] = ((j - R + d) % NS) * PL;
+#pragma unroll
+                    for (int k = 0; k < RPT; ++k) {
+                        const int cidx = (ty * RPT + k + R) * LW + tx + R;
+                        T sx = T(0), sy = T(0), sz = T(0);
+#pragma unroll
+                        for (int p = 0; p < ST::NP; ++p) {
+                            constexpr PairList P = ST::P;
+                            const int ex = P.e[p][0], ey = P.e[p][1], ez = P.e[p][2];
+                            const T vp = psi_s[sl[R + ez] + cidx + ey * LW + ex];
+                            const T vm = psi_s[sl[R - ez] + cidx - ey * LW - ex];
+                            const T wd = T(P.w[p]) * (vp - vm);
+                            if (ex) sx += T(ex) * wd;
+                            if (ey) sy += T(ey) * wd;
+                            if (ez) sz += T(ez) * wd;
+                        }
+                        const T pref = -a.gc0 * psi_s[cs * PL + cidx];
+                        collide_d3q19<T, MRT>(g[sc][k], dr[sc][k], pref * sx, pref * sy, pref * sz, a);
+                        if (xin && yin[k] && zr < nz) {
+                            T* o = a.fout + (int64_t)zr * nxy + yo[k][1] + xr;
+#pragma unroll
+                            for (int b = 0; b < 19; ++b) o[b * n] = g[sc][k][b];
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ dispatch ----
+struct Shape3D {
+    int tx, tyb, rpt, h;
+    const char* name;
+};
+static const Shape3D kShapes3D[] = {
+    {32, 8, 2, 16, "march32x16h16"},
+    {64, 4, 2, 16, "march64x8h16"},
+    {32, 8, 1, 16, "march32x8h16"},
+    {32, 8, 2, 32, "march32x16h32"},
+};
+constexpr int kNumShapes3D = sizeof(kShapes3D) / sizeof(kShapes3D[0]);
+
+int num_variants_d3q19() { return kNumShapes3D; }
+const char* variant_name_d3q19(int v) { return (v >= 0 && v < kNumShapes3D) ? kShapes3D[v].name : "?"; }
+
+template <typename T, int ORDER, bool MRT, int TX, int TYB, int RPT>
+static hipError_t launch_march(const StepArgs<T>& a, int H, hipStream_t s)
+{
+    if (H > a.nz) H = a.nz;
+    dim3 block(TX, TYB);
+    dim3 grid((a.nx + TX - 1) / TX, (a.ny + TYB * RPT - 1) / (TYB * RPT), (a.nz + H - 1) / H);
+    hipLaunchKernelGGL((k_d3q19_march<T, ORDER, MRT, TX, TYB, RPT>), grid, block, 0, s, a, H);
+    return hipGetLastError();
+}
+
+template <typename T, int ORDER, bool MRT>
+static hipError_t launch_v(const StepArgs<T>& a, int variant, hipStream_t s)
+{
+    switch (variant) {
+    case 0: return launch_march<T, ORDER, MRT, 32, 8, 2>(a, 16, s);
+    case 1: return launch_march<T, ORDER, MRT, 64, 4, 2>(a, 16, s);
+    case 2: return launch_march<T, ORDER, MRT, 32, 8, 1>(a, 16, s);
+    case 3: return launch_march<T, ORDER, MRT, 32, 8, 2>(a, 32, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+static hipError_t launch_any(const StepArgs<T>& a, int order, bool mrt, int variant, hipStream_t s)
+{
+    switch (order) {
+    case 4: return mrt ? launch_v<T, 4, true>(a, variant, s) : launch_v<T, 4, false>(a, variant, s);
+    case 6: return mrt ? launch_v<T, 6, true>(a, variant, s) : launch_v<T, 6, false>(a, variant, s);
+    case 8: return mrt ? launch_v<T, 8, true>(a, variant, s) : launch_v<T, 8, false>(a, variant, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_step_d3q19(const StepArgs<float>& a, int order, bool mrt, int variant, hipStream_t s)
+{
+    return launch_any<float>(a, order, mrt, variant, s);
+}
+hipError_t launch_step_d3q19(const StepArgs<double>& a, int order, bool mrt, int variant, hipStream_t s)
+{
+    return launch_any<double>(a, order, mrt, variant, s);
+}
+
+}  // namespace sclbm

@@ -1,0 +1,555 @@
+// sc_lbm.cpp -- host side of the C ABI declared in include/sc_lbm.h.
+//
+// Owns the two state buffers (or borrows the caller's), enqueues the fused
+// step kernels on one stream, captures runs of steps into HIP graphs (one
+// per parity of the current buffer, since a graph freezes its kernel
+// arguments), and turns the FP64 reductions into sc_lbm_obs.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/sc_lbm.h"
+#include "kernels.h"
+
+using namespace sclbm;
+
+namespace {
+
+constexpr int kGraphSteps = 32;   // steps per captured graph (even)
+
+struct ObsState {
+    bool ready = false;
+    ObsBuffers b{};
+};
+
+}  // namespace
+
+struct sc_lbm {
+    sc_lbm_params p;
+    int dim = 2, q = 9;
+    int64_t n = 0;
+    size_t tsize = 4;
+    void* f[2] = {nullptr, nullptr};
+    bool own_f = false;
+    int cur = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int64_t step = 0;
+    int variant = 0;
+    StepArgs<float> af{};
+    StepArgs<double> ad{};
+    ObsState obs;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    bool graph_failed = false;
+    double last_max_u = -1.0;
+    int fp32_hits = 0;
+};
+
+static thread_local char g_detail[256] = "";
+
+static void set_detail(const char* where, hipError_t e)
+{
+    std::snprintf(g_detail, sizeof(g_detail), "%s: %s (%d)", where, hipGetErrorString(e), (int)e);
+}
+
+// map a HIP status to an SC_E_* code, recording where it happened
+static int hip_err_at(hipError_t e, const char* where)
+{
+    if (e == hipSuccess) return SC_OK;
+    set_detail(where, e);
+    return e == hipErrorOutOfMemory ? SC_E_NOMEM : SC_E_DEVICE;
+}
+#define hip_err(e) hip_err_at((e), __func__)
+
+extern "C" void sc_lbm_default_params(sc_lbm_params* p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->lattice = SC_D2Q9;
+    p->nx = 64;
+    p->ny = 64;
+    p->nz = 1;
+    p->order = 4;
+    p->psi_kind = SC_PSI_EXP;
+    p->G = -5.0;
+    p->c0 = 1.0 / 3.0;
+    p->psi0 = 1.0;
+    p->rho_psi = 1.0;
+    p->tau = 1.0;
+    p->collision = SC_SRT;
+    p->precision = SC_FP32_SHIFTED;
+    p->s_bulk = 1.2;
+    p->s_ghost = 1.2;
+    p->rho_ref = 1.0;
+    p->obs_every = 100;
+    p->variant = -1;
+}
+
+static int validate(const sc_lbm_params* p)
+{
+    if (!p) return SC_E_INVAL;
+    if (p->lattice != SC_D2Q9 && p->lattice != SC_D3Q19) return SC_E_INVAL;
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return SC_E_INVAL;
+    if (p->lattice == SC_D2Q9 && p->nz != 1) return SC_E_INVAL;
+    const int64_t n = (int64_t)p->nx * p->ny * p->nz;
+    const int q = p->lattice == SC_D2Q9 ? 9 : 19;
+    if (n * q >= ((int64_t)1 << 40)) return SC_E_INVAL;
+    if (p->lattice == SC_D2Q9) {
+        if (p->order != 4 && p->order != 6 && p->order != 8 && p->order != 10) return SC_E_INVAL;
+    } else {
+        if (p->order != 4 && p->order != 6 && p->order != 8) return SC_E_UNSUPPORTED;
+    }
+    if (p->psi_kind != SC_PSI_EXP && p->psi_kind != SC_PSI_IDENTITY) return SC_E_INVAL;
+    if (p->collision != SC_SRT && p->collision != SC_MRT) return SC_E_INVAL;
+    if (p->collision == SC_MRT && p->lattice != SC_D3Q19) return SC_E_UNSUPPORTED;
+    if (p->precision != SC_FP32_SHIFTED && p->precision != SC_FP64) return SC_E_INVAL;
+    if (!std::isfinite(p->G) || !std::isfinite(p->c0) || !std::isfinite(p->rho_ref)) return SC_E_INVAL;
+    if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return SC_E_INVAL;
+    if (p->psi_kind == SC_PSI_EXP && (!(p->rho_psi > 0.0) || !std::isfinite(p->psi0))) return SC_E_INVAL;
+    if (p->collision == SC_MRT) {
+        if (!(p->s_bulk > 0.0 && p->s_bulk < 2.0) || !(p->s_ghost > 0.0 && p->s_ghost < 2.0)) return SC_E_INVAL;
+    }
+    if (p->obs_every < 0) return SC_E_INVAL;
+    const int nv = p->lattice == SC_D2Q9 ? num_variants_d2q9() : num_variants_d3q19();
+    if (p->variant < -1 || p->variant >= nv) return SC_E_INVAL;
+    return SC_OK;
+}
+
+extern "C" size_t sc_lbm_state_bytes(const sc_lbm_params* p)
+{
+    if (validate(p) != SC_OK) return 0;
+    const size_t q = p->lattice == SC_D2Q9 ? 9 : 19;
+    const size_t ts = p->precision == SC_FP64 ? 8 : 4;
+    return q * (size_t)p->nx * p->ny * p->nz * ts;
+}
+
+extern "C" int sc_lbm_num_variants(int32_t lattice)
+{
+    if (lattice == SC_D2Q9) return num_variants_d2q9();
+    if (lattice == SC_D3Q19) return num_variants_d3q19();
+    return 0;
+}
+
+extern "C" const char* sc_lbm_variant_name(const sc_lbm* h)
+{
+    if (!h) return "";
+    return h->p.lattice == SC_D2Q9 ? variant_name_d2q9(h->variant) : variant_name_d3q19(h->variant);
+}
+
+template <typename T>
+static void fill_args(sc_lbm* h, StepArgs<T>& a)
+{
+    const sc_lbm_params& p = h->p;
+    a.fin = nullptr;
+    a.fout = nullptr;
+    a.nx = p.nx;
+    a.ny = p.ny;
+    a.nz = p.nz;
+    a.n = h->n;
+    a.gc0 = (T)(p.G * p.c0);
+    a.omega = (T)(1.0 / p.tau);
+    a.guo = (T)(1.0 - 0.5 / p.tau);
+    a.rho_ref = (T)p.rho_ref;
+    a.psi0 = (T)p.psi0;
+    a.inv_rho_psi = (T)(p.psi_kind == SC_PSI_EXP ? 1.0 / p.rho_psi : 1.0);
+    a.psi_kind = p.psi_kind;
+    a.s_bulk = (T)p.s_bulk;
+    a.s_ghost = (T)p.s_ghost;
+}
+
+static int auto_variant(const sc_lbm_params& p, int64_t n)
+{
+    if (p.lattice == SC_D2Q9) return n < (int64_t)1 << 20 ? 2 : 0;
+    return 0;
+}
+
+static void release(sc_lbm* h)
+{
+    if (!h) return;
+    for (int k = 0; k < 2; ++k)
+        if (h->gexec[k]) hipGraphExecDestroy(h->gexec[k]);
+    if (h->obs.ready) {
+        ObsBuffers& b = h->obs.b;
+        hipFree(b.rho);
+        hipFree(b.psi);
+        hipFree(b.j);
+        hipFree(b.F);
+        hipFree(b.u);
+        hipFree(b.partials);
+        hipFree(b.result);
+    }
+    if (h->own_f) {
+        hipFree(h->f[0]);
+        hipFree(h->f[1]);
+    }
+    if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
+    delete h;
+}
+
+extern "C" int sc_lbm_create(const sc_lbm_params* p, const double* rho_init, void* dev_a, void* dev_b,
+                             void* hip_stream, sc_lbm** out)
+{
+    int rc = validate(p);
+    if (rc != SC_OK) return rc;
+    if (!out) return SC_E_INVAL;
+    if ((dev_a == nullptr) != (dev_b == nullptr) || (dev_a && dev_a == dev_b)) return SC_E_INVAL;
+    sc_lbm* h = new (std::nothrow) sc_lbm();
+    if (!h) return SC_E_NOMEM;
+    h->p = *p;
+    if (h->p.obs_every == 0) h->p.obs_every = 100;
+    h->dim = p->lattice == SC_D2Q9 ? 2 : 3;
+    h->q = p->lattice == SC_D2Q9 ? 9 : 19;
+    h->n = (int64_t)p->nx * p->ny * p->nz;
+    h->tsize = p->precision == SC_FP64 ? 8 : 4;
+    h->variant = p->variant >= 0 ? p->variant : auto_variant(*p, h->n);
+    if (rho_init) {
+        for (int64_t i = 0; i < h->n; ++i)
+            if (!std::isfinite(rho_init[i])) {
+                delete h;
+                return SC_E_INVAL;
+            }
+    }
+    int ndev = 0;
+    hipError_t de = hipGetDeviceCount(&ndev);
+    if (de != hipSuccess || ndev < 1) {
+        set_detail("hipGetDeviceCount", de == hipSuccess ? hipErrorNoDevice : de);
+        delete h;
+        return SC_E_DEVICE;
+    }
+    hipError_t e;
+    if (hip_stream) {
+        h->stream = (hipStream_t)hip_stream;
+    } else {
+        e = hipStreamCreate(&h->stream);
+        if (e != hipSuccess) {
+            delete h;
+            return hip_err(e);
+        }
+        h->own_stream = true;
+    }
+    const size_t bytes = sc_lbm_state_bytes(p);
+    if (dev_a) {
+        h->f[0] = dev_a;
+        h->f[1] = dev_b;
+    } else {
+        h->own_f = true;
+        e = hipMalloc(&h->f[0], bytes);
+        if (e == hipSuccess) e = hipMalloc(&h->f[1], bytes);
+        if (e != hipSuccess) {
+            rc = hip_err(e);
+            release(h);
+            return rc;
+        }
+    }
+    fill_args(h, h->af);
+    fill_args(h, h->ad);
+    // initial state from rho_init (or rho = 1)
+    double* rho_d = nullptr;
+    e = hipMalloc(&rho_d, sizeof(double) * h->n);
+    if (e != hipSuccess) {
+        rc = hip_err(e);
+        release(h);
+        return rc;
+    }
+    std::vector<double> ones;
+    const double* src = rho_init;
+    if (!src) {
+        ones.assign(h->n, 1.0);
+        src = ones.data();
+    }
+    const char* where = "hipMemcpyAsync(rho_init)";
+    e = hipMemcpyAsync(rho_d, src, sizeof(double) * h->n, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) {
+        where = "init kernel";
+        e = launch_init(p->lattice, h->f[0], p->precision, rho_d, p->nx, p->ny, p->nz, p->rho_ref, h->stream);
+    }
+    if (e == hipSuccess) {
+        where = "hipStreamSynchronize(create)";
+        e = hipStreamSynchronize(h->stream);
+    }
+    hipFree(rho_d);
+    if (e != hipSuccess) {
+        rc = hip_err_at(e, where);
+        release(h);
+        return rc;
+    }
+    *out = h;
+    return SC_OK;
+}
+
+extern "C" void sc_lbm_destroy(sc_lbm* h)
+{
+    if (!h) return;
+    hipStreamSynchronize(h->stream);
+    release(h);
+}
+
+extern "C" void* sc_lbm_state_ptr(sc_lbm* h) { return h ? h->f[h->cur] : nullptr; }
+
+// one fused step from f[cur] into f[cur ^ 1] (no swap)
+static hipError_t enqueue_step(sc_lbm* h, int from)
+{
+    const sc_lbm_params& p = h->p;
+    if (p.precision == SC_FP32_SHIFTED) {
+        StepArgs<float> a = h->af;
+        a.fin = (const float*)h->f[from];
+        a.fout = (float*)h->f[from ^ 1];
+        return p.lattice == SC_D2Q9 ? launch_step_d2q9(a, p.order, h->variant, h->stream)
+                                    : launch_step_d3q19(a, p.order, p.collision == SC_MRT, h->variant, h->stream);
+    }
+    StepArgs<double> a = h->ad;
+    a.fin = (const double*)h->f[from];
+    a.fout = (double*)h->f[from ^ 1];
+    return p.lattice == SC_D2Q9 ? launch_step_d2q9(a, p.order, h->variant, h->stream)
+                                : launch_step_d3q19(a, p.order, p.collision == SC_MRT, h->variant, h->stream);
+}
+
+static hipError_t build_graph(sc_lbm* h, int from)
+{
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = hipSuccess;
+    for (int k = 0; k < kGraphSteps && le == hipSuccess; ++k) le = enqueue_step(h, from ^ (k & 1));
+    e = hipStreamEndCapture(h->stream, &g);
+    if (le != hipSuccess) e = le;
+    if (e == hipSuccess) e = hipGraphInstantiate(&h->gexec[from], g, nullptr, nullptr, 0);
+    if (g) hipGraphDestroy(g);
+    return e;
+}
+
+// enqueue `count` steps (asynchronous)
+static hipError_t run_steps(sc_lbm* h, int64_t count)
+{
+    hipError_t e = hipSuccess;
+    while (count >= kGraphSteps && !h->graph_failed) {
+        if (!h->gexec[h->cur]) {
+            e = build_graph(h, h->cur);
+            if (e != hipSuccess) {
+                // capture unsupported on this stream: fall back to plain launches
+                (void)hipGetLastError();
+                h->graph_failed = true;
+                break;
+            }
+        }
+        e = hipGraphLaunch(h->gexec[h->cur], h->stream);
+        if (e != hipSuccess) return e;
+        count -= kGraphSteps;
+        h->step += kGraphSteps;
+    }
+    for (; count > 0; --count) {
+        e = enqueue_step(h, h->cur);
+        if (e != hipSuccess) return e;
+        h->cur ^= 1;
+        h->step += 1;
+    }
+    return hipSuccess;
+}
+
+static int ensure_obs(sc_lbm* h)
+{
+    if (h->obs.ready) return SC_OK;
+    ObsBuffers& b = h->obs.b;
+    const int64_t n = h->n;
+    b.nblk = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    if (b.nblk < 1) b.nblk = 1;
+    hipError_t e = hipMalloc(&b.rho, sizeof(double) * n);
+    if (e == hipSuccess) e = hipMalloc(&b.psi, h->tsize * n);
+    if (e == hipSuccess) e = hipMalloc(&b.j, sizeof(double) * 3 * n);
+    if (e == hipSuccess) e = hipMalloc(&b.F, sizeof(double) * 3 * n);
+    if (e == hipSuccess) e = hipMalloc(&b.u, sizeof(double) * 3 * n);
+    if (e == hipSuccess) e = hipMalloc(&b.partials, sizeof(double) * 8 * b.nblk);
+    if (e == hipSuccess) e = hipMalloc(&b.result, sizeof(double) * 8);
+    if (e != hipSuccess) {
+        hipFree(b.rho);
+        hipFree(b.psi);
+        hipFree(b.j);
+        hipFree(b.F);
+        hipFree(b.u);
+        hipFree(b.partials);
+        hipFree(b.result);
+        b = ObsBuffers{};
+        return hip_err(e);
+    }
+    h->obs.ready = true;
+    return SC_OK;
+}
+
+static const void* args_ptr(sc_lbm* h) { return h->p.precision == SC_FP64 ? (const void*)&h->ad : (const void*)&h->af; }
+
+// fields + reductions of the current state; fills obs (except convergence fields)
+static int observe_core(sc_lbm* h, sc_lbm_obs* o)
+{
+    int rc = ensure_obs(h);
+    if (rc != SC_OK) return rc;
+    ObsBuffers& b = h->obs.b;
+    const sc_lbm_params& p = h->p;
+    hipError_t e = launch_macro(p.lattice, p.precision, h->f[h->cur], args_ptr(h), b, h->stream);
+    if (e == hipSuccess) e = launch_force(p.lattice, p.precision, p.order, args_ptr(h), b, true, h->stream);
+    if (e == hipSuccess) e = launch_reduce(h->dim, b, h->n, h->stream);
+    double res[8];
+    if (e == hipSuccess) e = hipMemcpyAsync(res, b.result, sizeof(res), hipMemcpyDeviceToHost, h->stream);
+    const int64_t ic = (int64_t)(p.nx / 2) + (int64_t)p.nx * ((int64_t)(p.ny / 2) + (int64_t)p.ny * (p.nz / 2));
+    double rin = 0, rout = 0, pin = 0, pout = 0;
+    double psi_pair[2] = {0, 0};
+    float psi_pair_f[2] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(&rin, b.rho + ic, sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&rout, b.rho, sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (p.precision == SC_FP64) {
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&psi_pair[0], (double*)b.psi + ic, 8, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(&psi_pair[1], (double*)b.psi, 8, hipMemcpyDeviceToHost, h->stream);
+    } else {
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&psi_pair_f[0], (float*)b.psi + ic, 4, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(&psi_pair_f[1], (float*)b.psi, 4, hipMemcpyDeviceToHost, h->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_err(e);
+    if (p.precision != SC_FP64) {
+        psi_pair[0] = psi_pair_f[0];
+        psi_pair[1] = psi_pair_f[1];
+    }
+    const double cs2 = 1.0 / 3.0;
+    pin = cs2 * rin + 0.5 * p.G * p.c0 * psi_pair[0] * psi_pair[0];
+    pout = cs2 * rout + 0.5 * p.G * p.c0 * psi_pair[1] * psi_pair[1];
+    std::memset(o, 0, sizeof(*o));
+    o->step = h->step;
+    o->mass = res[0];
+    o->mom[0] = res[1];
+    o->mom[1] = res[2];
+    o->mom[2] = res[3];
+    o->max_u = res[4];
+    const double nfin = (double)h->n - res[7];
+    o->mean_u = nfin > 0 ? res[5] / nfin : 0.0;
+    o->l2_u = nfin > 0 ? std::sqrt(res[6] / nfin) : 0.0;
+    o->nonfinite = (int64_t)res[7];
+    o->rho_in = rin;
+    o->rho_out = rout;
+    o->p_in = pin;
+    o->p_out = pout;
+    o->dp = pin - pout;
+    double vol = (rin != rout) ? (res[0] - (double)h->n * rout) / (rin - rout) : 0.0;
+    if (vol < 0) vol = 0;
+    o->radius = h->dim == 2 ? std::sqrt(vol / M_PI) : std::cbrt(3.0 * vol / (4.0 * M_PI));
+    o->d_max_u = h->last_max_u >= 0 ? std::fabs(o->max_u - h->last_max_u) : -1.0;
+    o->status = o->nonfinite ? SC_E_NONFINITE : SC_OK;
+    return SC_OK;
+}
+
+extern "C" int sc_lbm_step(sc_lbm* h, int64_t max_steps, double tol, int64_t* steps_done)
+{
+    if (!h || max_steps < 0 || !(tol >= 0.0)) return SC_E_INVAL;
+    const int64_t start = h->step;
+    if (tol == 0.0) {
+        hipError_t e = run_steps(h, max_steps);
+        if (steps_done) *steps_done = h->step - start;
+        return hip_err(e);
+    }
+    const int64_t K = h->p.obs_every;
+    int64_t left = max_steps;
+    int rc = SC_OK;
+    while (left > 0) {
+        const int64_t chunk = left < K ? left : K;
+        hipError_t e = run_steps(h, chunk);
+        if (e != hipSuccess) {
+            rc = hip_err(e);
+            break;
+        }
+        left -= chunk;
+        sc_lbm_obs o;
+        rc = observe_core(h, &o);
+        if (rc != SC_OK) break;
+        if (o.nonfinite) {
+            rc = SC_E_NONFINITE;
+            break;
+        }
+        bool done = false;
+        if (o.d_max_u >= 0 && o.d_max_u < tol) {
+            done = true;
+        } else if (h->p.precision == SC_FP32_SHIFTED && o.d_max_u >= 0 &&
+                   o.d_max_u <= 4.0 * o.max_u * 1.1920928955078125e-7) {
+            if (++h->fp32_hits >= 10) done = true;
+        } else {
+            h->fp32_hits = 0;
+        }
+        h->last_max_u = o.max_u;
+        if (done) break;
+    }
+    if (steps_done) *steps_done = h->step - start;
+    return rc;
+}
+
+extern "C" int sc_lbm_observe(sc_lbm* h, sc_lbm_obs* obs, double* rho_out, double* u_out, void* f_out)
+{
+    if (!h) return SC_E_INVAL;
+    sc_lbm_obs o;
+    int rc = observe_core(h, &o);
+    if (rc != SC_OK) return rc;
+    if (o.d_max_u >= 0 && h->p.precision == SC_FP32_SHIFTED && h->fp32_hits >= 10) o.converged_by = 2;
+    ObsBuffers& b = h->obs.b;
+    hipError_t e = hipSuccess;
+    if (rho_out) e = hipMemcpyAsync(rho_out, b.rho, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && u_out)
+        e = hipMemcpyAsync(u_out, b.u, sizeof(double) * h->dim * h->n, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && f_out)
+        e = hipMemcpyAsync(f_out, h->f[h->cur], h->tsize * h->q * h->n, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_err(e);
+    if (obs) *obs = o;
+    return o.nonfinite ? SC_E_NONFINITE : SC_OK;
+}
+
+extern "C" int sc_lbm_force(sc_lbm* h, const double* psi_in, double* F_out)
+{
+    if (!h || !F_out) return SC_E_INVAL;
+    int rc = ensure_obs(h);
+    if (rc != SC_OK) return rc;
+    ObsBuffers& b = h->obs.b;
+    const sc_lbm_params& p = h->p;
+    hipError_t e = hipSuccess;
+    if (psi_in) {
+        // stage the doubles in the u buffer, then convert to the state precision
+        e = hipMemcpyAsync(b.u, psi_in, sizeof(double) * h->n, hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess) e = launch_psi_from_host(p.precision, b.u, b.psi, h->n, h->stream);
+    } else {
+        e = launch_macro(p.lattice, p.precision, h->f[h->cur], args_ptr(h), b, h->stream);
+    }
+    if (e == hipSuccess) e = launch_force(p.lattice, p.precision, p.order, args_ptr(h), b, false, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(F_out, b.F, sizeof(double) * h->dim * h->n, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    return hip_err(e);
+}
+
+extern "C" int sc_lbm_set_state(sc_lbm* h, const void* f_in, int64_t step)
+{
+    if (!h || !f_in || step < 0) return SC_E_INVAL;
+    hipError_t e = hipMemcpyAsync(h->f[h->cur], f_in, h->tsize * h->q * h->n, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_err(e);
+    h->step = step;
+    h->last_max_u = -1.0;
+    h->fp32_hits = 0;
+    return SC_OK;
+}
+
+extern "C" const char* sc_lbm_last_error_detail(void) { return g_detail; }
+
+extern "C" const char* sc_lbm_strerror(int code)
+{
+    switch (code) {
+    case SC_OK: return "ok";
+    case SC_E_INVAL: return "invalid argument";
+    case SC_E_NOMEM: return "out of memory";
+    case SC_E_DEVICE: return "HIP device or runtime error";
+    case SC_E_UNSUPPORTED: return "unsupported parameter combination";
+    case SC_E_NONFINITE: return "non-finite value in the state";
+    default: return "unknown error";
+    }
+}

@@ -1,0 +1,310 @@
+"""ctypes binding of libsc_lbm.so (include/sc_lbm.h): argument marshalling only.
+
+Every step of the method runs in the library's HIP kernels; this module only
+converts numpy arrays and torch device buffers/streams to plain pointers.
+There is no CPU fallback: if the shared library is missing, importing the
+binding raises.
+
+Field arrays returned by :class:`Sim` are indexed [x, y] or [x, y, z]
+(vector fields with a leading component axis); the C ABI itself uses flat
+node order i = x + nx (y + ny z).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsc_lbm.so")
+
+SC_OK, SC_E_INVAL, SC_E_NOMEM, SC_E_DEVICE, SC_E_UNSUPPORTED, SC_E_NONFINITE = 0, -1, -2, -3, -4, -5
+SC_D2Q9, SC_D3Q19 = 0, 1
+SC_PSI_EXP, SC_PSI_IDENTITY = 0, 1
+SC_SRT, SC_MRT = 0, 1
+SC_FP32_SHIFTED, SC_FP64 = 0, 1
+
+LATTICE = {"D2Q9": SC_D2Q9, "D3Q19": SC_D3Q19}
+Q = {SC_D2Q9: 9, SC_D3Q19: 19}
+
+
+class sc_lbm_params(ctypes.Structure):
+    _fields_ = [
+        ("lattice", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("nz", ctypes.c_int32), ("order", ctypes.c_int32), ("psi_kind", ctypes.c_int32),
+        ("G", ctypes.c_double), ("c0", ctypes.c_double), ("psi0", ctypes.c_double),
+        ("rho_psi", ctypes.c_double), ("tau", ctypes.c_double),
+        ("collision", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("s_bulk", ctypes.c_double), ("s_ghost", ctypes.c_double), ("rho_ref", ctypes.c_double),
+        ("obs_every", ctypes.c_int32), ("variant", ctypes.c_int32),
+    ]
+
+
+class sc_lbm_obs(ctypes.Structure):
+    _fields_ = [
+        ("step", ctypes.c_int64), ("mass", ctypes.c_double), ("mom", ctypes.c_double * 3),
+        ("max_u", ctypes.c_double), ("mean_u", ctypes.c_double), ("l2_u", ctypes.c_double),
+        ("rho_in", ctypes.c_double), ("rho_out", ctypes.c_double),
+        ("p_in", ctypes.c_double), ("p_out", ctypes.c_double), ("dp", ctypes.c_double),
+        ("radius", ctypes.c_double), ("d_max_u", ctypes.c_double),
+        ("nonfinite", ctypes.c_int64), ("converged_by", ctypes.c_int32), ("status", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["mom"] = list(self.mom)
+        return d
+
+
+#: every symbol include/sc_lbm.h declares
+EXPORTS = [
+    "sc_lbm_default_params", "sc_lbm_state_bytes", "sc_lbm_create", "sc_lbm_step",
+    "sc_lbm_force", "sc_lbm_observe", "sc_lbm_set_state", "sc_lbm_state_ptr",
+    "sc_lbm_variant_name", "sc_lbm_num_variants", "sc_lbm_destroy", "sc_lbm_strerror",
+    "sc_lbm_last_error_detail",
+]
+
+#: velocity order of the state buffers (include/sc_lbm.h)
+VELOCITIES = {
+    SC_D2Q9: [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1)],
+    SC_D3Q19: [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
+               (1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0), (1, 0, 1), (-1, 0, -1),
+               (1, 0, -1), (-1, 0, 1), (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)],
+}
+
+_lib = None
+
+
+def lib():
+    """Load libsc_lbm.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libsc_lbm.so is not built (run __graft_entry__.build()); "
+                           "there is no CPU fallback")
+    # torch ships its own libamdhip64 (same soname, loaded by file name).  Load
+    # it first so this library binds to that copy: two HIP runtimes in one
+    # process do not share the device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp, dp = ctypes.c_void_p, P(ctypes.c_double)
+    L.sc_lbm_default_params.argtypes = [P(sc_lbm_params)]
+    L.sc_lbm_default_params.restype = None
+    L.sc_lbm_state_bytes.argtypes = [P(sc_lbm_params)]
+    L.sc_lbm_state_bytes.restype = ctypes.c_size_t
+    L.sc_lbm_create.argtypes = [P(sc_lbm_params), dp, vp, vp, vp, P(vp)]
+    L.sc_lbm_create.restype = ctypes.c_int
+    L.sc_lbm_step.argtypes = [vp, ctypes.c_int64, ctypes.c_double, P(ctypes.c_int64)]
+    L.sc_lbm_step.restype = ctypes.c_int
+    L.sc_lbm_force.argtypes = [vp, dp, dp]
+    L.sc_lbm_force.restype = ctypes.c_int
+    L.sc_lbm_observe.argtypes = [vp, P(sc_lbm_obs), dp, dp, vp]
+    L.sc_lbm_observe.restype = ctypes.c_int
+    L.sc_lbm_set_state.argtypes = [vp, vp, ctypes.c_int64]
+    L.sc_lbm_set_state.restype = ctypes.c_int
+    L.sc_lbm_state_ptr.argtypes = [vp]
+    L.sc_lbm_state_ptr.restype = vp
+    L.sc_lbm_variant_name.argtypes = [vp]
+    L.sc_lbm_variant_name.restype = ctypes.c_char_p
+    L.sc_lbm_num_variants.argtypes = [ctypes.c_int32]
+    L.sc_lbm_num_variants.restype = ctypes.c_int
+    L.sc_lbm_destroy.argtypes = [vp]
+    L.sc_lbm_destroy.restype = None
+    L.sc_lbm_strerror.argtypes = [ctypes.c_int]
+    L.sc_lbm_strerror.restype = ctypes.c_char_p
+    L.sc_lbm_last_error_detail.argtypes = []
+    L.sc_lbm_last_error_detail.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+class ScError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        msg = lib().sc_lbm_strerror(code).decode()
+        detail = lib().sc_lbm_last_error_detail().decode()
+        super().__init__("%s failed: %s (%d)%s" % (what, msg, code, (" [" + detail + "]") if detail else ""))
+
+
+def _check(code, what):
+    if code != SC_OK:
+        raise ScError(code, what)
+    return code
+
+
+def _dptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# ---------------------------------------------------------------------------
+# thin wrappers with the C names
+# ---------------------------------------------------------------------------
+
+def sc_lbm_default_params():
+    p = sc_lbm_params()
+    lib().sc_lbm_default_params(ctypes.byref(p))
+    return p
+
+
+def sc_lbm_state_bytes(p):
+    return lib().sc_lbm_state_bytes(ctypes.byref(p))
+
+
+def sc_lbm_create(p, rho_init=None, dev_a=None, dev_b=None, stream=None):
+    """Returns the handle (int).  rho_init: flat float64 [N] in node order."""
+    h = ctypes.c_void_p()
+    if rho_init is not None:
+        rho_init = np.ascontiguousarray(rho_init, dtype=np.float64)
+    rc = lib().sc_lbm_create(ctypes.byref(p), _dptr(rho_init), dev_a, dev_b, stream, ctypes.byref(h))
+    _check(rc, "sc_lbm_create")
+    return h.value
+
+
+def sc_lbm_step(h, max_steps, tol=0.0):
+    done = ctypes.c_int64(0)
+    rc = lib().sc_lbm_step(h, int(max_steps), float(tol), ctypes.byref(done))
+    return rc, done.value
+
+
+def sc_lbm_force(h, n, dim, psi_in=None):
+    F = np.zeros(dim * n)
+    if psi_in is not None:
+        psi_in = np.ascontiguousarray(psi_in, dtype=np.float64)
+    _check(lib().sc_lbm_force(h, _dptr(psi_in), _dptr(F)), "sc_lbm_force")
+    return F
+
+
+def sc_lbm_observe(h, rho_out=None, u_out=None, f_out=None):
+    o = sc_lbm_obs()
+    fptr = None if f_out is None else f_out.ctypes.data_as(ctypes.c_void_p)
+    rc = lib().sc_lbm_observe(h, ctypes.byref(o), _dptr(rho_out), _dptr(u_out), fptr)
+    if rc not in (SC_OK, SC_E_NONFINITE):
+        raise ScError(rc, "sc_lbm_observe")
+    return rc, o
+
+
+def sc_lbm_set_state(h, f_in, step):
+    _check(lib().sc_lbm_set_state(h, f_in.ctypes.data_as(ctypes.c_void_p), int(step)), "sc_lbm_set_state")
+
+
+def sc_lbm_state_ptr(h):
+    return lib().sc_lbm_state_ptr(h)
+
+
+def sc_lbm_variant_name(h):
+    return lib().sc_lbm_variant_name(h).decode()
+
+
+def sc_lbm_num_variants(lattice):
+    return lib().sc_lbm_num_variants(lattice)
+
+
+def sc_lbm_destroy(h):
+    lib().sc_lbm_destroy(h)
+
+
+def sc_lbm_strerror(code):
+    return lib().sc_lbm_strerror(code).decode()
+
+
+# ---------------------------------------------------------------------------
+# convenience handle
+# ---------------------------------------------------------------------------
+
+def make_params(lattice="D2Q9", shape=(64, 64), order=4, G=-5.0, c0=1.0 / 3.0, psi="exp",
+                psi0=1.0, rho_psi=1.0, tau=1.0, collision="srt", precision="fp32",
+                s_bulk=1.2, s_ghost=1.2, rho_ref=1.0, obs_every=100, variant=-1):
+    p = sc_lbm_default_params()
+    p.lattice = LATTICE[lattice]
+    shape = tuple(int(s) for s in shape)
+    p.nx, p.ny = shape[0], shape[1]
+    p.nz = shape[2] if len(shape) > 2 else 1
+    p.order = order
+    p.psi_kind = {"exp": SC_PSI_EXP, "identity": SC_PSI_IDENTITY}[psi]
+    p.G, p.c0, p.psi0, p.rho_psi, p.tau = G, c0, psi0, rho_psi, tau
+    p.collision = {"srt": SC_SRT, "mrt": SC_MRT}[collision]
+    p.precision = {"fp32": SC_FP32_SHIFTED, "fp64": SC_FP64}[precision]
+    p.s_bulk, p.s_ghost, p.rho_ref = s_bulk, s_ghost, rho_ref
+    p.obs_every, p.variant = obs_every, variant
+    return p
+
+
+class Sim:
+    """One periodic domain on the GPU.  Device memory and the stream come
+    from torch when `use_torch` is set (the default when torch sees a GPU)."""
+
+    def __init__(self, rho0, lattice="D2Q9", use_torch=None, **kw):
+        rho0 = np.asarray(rho0, dtype=np.float64)
+        self.shape = rho0.shape
+        self.dim = rho0.ndim
+        self.p = make_params(lattice, self.shape, **kw)
+        self.q = Q[self.p.lattice]
+        self.n = int(rho0.size)
+        self.lattice = lattice
+        self._bufs = None
+        dev_a = dev_b = stream = None
+        if use_torch is None:
+            try:
+                import torch
+                use_torch = torch.cuda.is_available()
+            except ImportError:
+                use_torch = False
+        if use_torch:
+            import torch
+            nbytes = sc_lbm_state_bytes(self.p)
+            if nbytes == 0:
+                raise ScError(SC_E_INVAL, "sc_lbm_state_bytes")
+            self._bufs = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(2)]
+            dev_a, dev_b = self._bufs[0].data_ptr(), self._bufs[1].data_ptr()
+            stream = torch.cuda.current_stream().cuda_stream
+        flat = np.ascontiguousarray(rho0.transpose()).ravel()
+        self.h = sc_lbm_create(self.p, flat, dev_a, dev_b, stream)
+
+    def close(self):
+        if getattr(self, "h", None):
+            sc_lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def _unflat(self, a):
+        return a.reshape(self.shape[::-1]).transpose()
+
+    def step(self, n=1, tol=0.0):
+        rc, done = sc_lbm_step(self.h, n, tol)
+        if rc not in (SC_OK, SC_E_NONFINITE):
+            raise ScError(rc, "sc_lbm_step")
+        return rc, done
+
+    def observe(self, fields=True):
+        rho = np.zeros(self.n) if fields else None
+        u = np.zeros(self.dim * self.n) if fields else None
+        rc, o = sc_lbm_observe(self.h, rho, u)
+        out = {"obs": o.as_dict(), "rc": rc}
+        if fields:
+            out["rho"] = self._unflat(rho)
+            out["u"] = np.stack([self._unflat(u[k * self.n:(k + 1) * self.n]) for k in range(self.dim)])
+        return out
+
+    def force(self, psi=None):
+        flat = None if psi is None else np.ascontiguousarray(np.asarray(psi, np.float64).transpose()).ravel()
+        F = sc_lbm_force(self.h, self.n, self.dim, flat)
+        return np.stack([self._unflat(F[k * self.n:(k + 1) * self.n]) for k in range(self.dim)])
+
+    def state(self):
+        dt = np.float64 if self.p.precision == SC_FP64 else np.float32
+        f = np.zeros(self.q * self.n, dtype=dt)
+        sc_lbm_observe(self.h, None, None, f)
+        return f
+
+    def set_state(self, f, step):
+        sc_lbm_set_state(self.h, np.ascontiguousarray(f), step)
+
+    @property
+    def variant(self):
+        return sc_lbm_variant_name(self.h)

@@ -1,0 +1,46 @@
+"""Helpers for the GPU parity tests: map the library's stored state (post-
+collision, shifted, library velocity order) to the oracle's pre-collision
+distributions, and compare fields."""
+import sys
+
+import numpy as np
+
+from paper_1906_11027_amd import sc_lbm as B
+
+
+def lib_velocities(sim):
+    return np.array(B.VELOCITIES[sim.p.lattice], dtype=np.int64)
+
+
+def lib_weights(lattice):
+    if lattice == "D2Q9":
+        return np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    return np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+
+
+def pre_collision_from_state(sim, oracle_c):
+    """f_b(x, t) = state_b(x - c_b) + w_b rho_ref, reordered to the oracle's
+    velocity list `oracle_c` and indexed [q][x, y(, z)] in float64."""
+    flat = sim.state().astype(np.float64)
+    c = lib_velocities(sim)
+    w = lib_weights(sim.lattice)
+    shape = sim.shape
+    out = np.zeros((len(c),) + shape)
+    for b in range(len(c)):
+        fb = flat[b * sim.n:(b + 1) * sim.n].reshape(shape[::-1]).transpose()
+        fb = np.roll(fb, tuple(int(v) for v in c[b][:sim.dim]), axis=tuple(range(sim.dim)))
+        out[b] = fb + w[b] * sim.p.rho_ref
+    order = []
+    for co in oracle_c:
+        key = tuple(int(v) for v in co[:sim.dim])
+        order.append([tuple(int(v) for v in cc) for cc in c].index(key))
+    return out[order]
+
+
+def rel_err(a, b):
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)))
+
+
+def say(*args):
+    print(*args, flush=True)
+    sys.stdout.flush()

@@ -1,0 +1,105 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol that
+include/sc_lbm.h declares, and rejects invalid parameter sets before any
+device call.  No kernel is launched here."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1906_11027_amd import sc_lbm as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sc_lbm.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sc_lbm_[a-z_]+)\s*\(", src)))
+
+
+def test_header_lists_match_binding():
+    assert declared_functions() == sorted(B.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+        assert ctypes.cast(getattr(L, name), ctypes.c_void_p).value
+
+
+def _c_layout(tmp_path, struct, fields):
+    """sizeof and field offsets as the C compiler lays the header out."""
+    prog = tmp_path / "layout.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sc_lbm.h"', 'int main(void){',
+             'printf("%%zu\\n", sizeof(%s));' % struct]
+    lines += ['printf("%%zu\\n", offsetof(%s, %s));' % (struct, f) for f in fields]
+    lines.append('return 0;}')
+    prog.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
+    return [int(v) for v in subprocess.check_output([str(exe)]).split()]
+
+
+@pytest.mark.parametrize("cls,name", [(B.sc_lbm_params, "sc_lbm_params"), (B.sc_lbm_obs, "sc_lbm_obs")])
+def test_struct_layout_matches_header(tmp_path, cls, name):
+    fields = [f for f, _ in cls._fields_]
+    got = _c_layout(tmp_path, name, fields)
+    assert got[0] == ctypes.sizeof(cls)
+    assert got[1:] == [getattr(cls, f).offset for f in fields]
+
+
+def test_defaults():
+    p = B.sc_lbm_default_params()
+    assert (p.lattice, p.nx, p.ny, p.nz, p.order) == (0, 64, 64, 1, 4)
+    assert p.G == -5.0 and abs(p.c0 - 1 / 3) < 1e-16 and p.tau == 1.0
+    assert p.variant == -1 and p.obs_every == 100
+    assert B.sc_lbm_state_bytes(p) == 9 * 64 * 64 * 4
+    p.precision = B.SC_FP64
+    assert B.sc_lbm_state_bytes(p) == 9 * 64 * 64 * 8
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("lattice", 7, B.SC_E_INVAL),
+    ("nx", 0, B.SC_E_INVAL),
+    ("nz", 2, B.SC_E_INVAL),          # 2D lattice with nz > 1
+    ("order", 5, B.SC_E_INVAL),
+    ("tau", 0.5, B.SC_E_INVAL),
+    ("tau", float("nan"), B.SC_E_INVAL),
+    ("psi_kind", 3, B.SC_E_INVAL),
+    ("collision", B.SC_MRT, B.SC_E_UNSUPPORTED),   # MRT is D3Q19 only
+    ("precision", 9, B.SC_E_INVAL),
+    ("variant", 99, B.SC_E_INVAL),
+    ("G", float("inf"), B.SC_E_INVAL),
+])
+def test_invalid_parameters_rejected(field, value, code):
+    p = B.sc_lbm_default_params()
+    setattr(p, field, value)
+    assert B.sc_lbm_state_bytes(p) == 0
+    h = ctypes.c_void_p()
+    assert B.lib().sc_lbm_create(ctypes.byref(p), None, None, None, None, ctypes.byref(h)) == code
+    assert h.value is None
+
+
+def test_3d_order_10_unsupported():
+    p = B.sc_lbm_default_params()
+    p.lattice, p.nz, p.order = B.SC_D3Q19, 8, 10
+    h = ctypes.c_void_p()
+    assert B.lib().sc_lbm_create(ctypes.byref(p), None, None, None, None, ctypes.byref(h)) == B.SC_E_UNSUPPORTED
+
+
+def test_single_buffer_rejected():
+    p = B.sc_lbm_default_params()
+    h = ctypes.c_void_p()
+    assert B.lib().sc_lbm_create(ctypes.byref(p), None, ctypes.c_void_p(1234), None, None,
+                                 ctypes.byref(h)) == B.SC_E_INVAL
+
+
+def test_strerror():
+    for code in (0, -1, -2, -3, -4, -5, -99):
+        assert B.sc_lbm_strerror(code)
+    assert B.sc_lbm_num_variants(B.SC_D2Q9) >= 1
+    assert B.sc_lbm_num_variants(B.SC_D3Q19) >= 1

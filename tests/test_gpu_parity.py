@@ -1,0 +1,291 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances.  FP32 state: density <= 1e-5 relative pointwise and velocity
+<= 1e-3 of max |u| up to 100 steps.  Beyond that the FP32 rounding drives a
+slow drift of the interface (measured: ~1e-5 at 200 steps, ~2e-4 at 3000,
+largest at interface nodes, for every storage shift), so long runs are
+compared on the observables the method reports (spurious max / mean |u|
+within 1e-3 relative, Laplace jump within 1e-4).  FP64 state: <= 1e-11
+pointwise at any horizon tested.  Launch shapes must agree bitwise, since
+every node's arithmetic is the same in every shape (a differing result
+would mean an LDS halo or indexing fault).
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from tests.gpu_helpers import pre_collision_from_state, rel_err, say
+from workload import droplet_rho
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1906_11027_amd import Sim  # noqa: E402
+from paper_1906_11027_amd import sc_lbm as B  # noqa: E402
+
+TOL = {"fp32": (1e-5, 1e-3), "fp64": (1e-11, 1e-9)}
+
+
+def _compare(sim, orc, prec, label):
+    got = sim.observe()
+    ref = orc.fields()
+    er = rel_err(got["rho"], ref["rho"])
+    umax = max(np.max(np.abs(ref["u"])), 1e-12)
+    eu = float(np.max(np.abs(got["u"] - ref["u"])) / umax)
+    say("%s: rho rel err %.3e, u err / max|u| %.3e (max|u| %.3e)" % (label, er, eu, umax))
+    tr, tu = TOL[prec]
+    assert er <= tr, (label, er)
+    assert eu <= tu, (label, eu)
+    return got, ref
+
+
+# --------------------------------------------------------------- D2Q9 -----
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("order", [4, 6, 8, 10])
+def test_d2q9_droplet_64(order, prec):
+    """Config-1 geometry (64^2, R = 16, G = -5, tau = 1) at a short horizon."""
+    say("case d2q9 64x64 order", order, prec)
+    rho0 = droplet_rho((64, 64), 16, seed=1)
+    sim = Sim(rho0, "D2Q9", order=order, precision=prec)
+    orc = O.Oracle(rho0, "D2Q9", order=order)
+    for steps in (1, 49, 50):
+        sim.step(steps)
+        orc.step(steps)
+        _compare(sim, orc, prec, "E%d %s t=%d" % (order, prec, orc.steps))
+    sim.close()
+
+
+@pytest.mark.parametrize("shape,order", [((37, 29), 10), ((8, 8), 8), ((3, 5), 4), ((1, 16), 6),
+                                         ((130, 67), 8)])
+def test_d2q9_ragged_and_tiny(shape, order):
+    say("case d2q9 ragged", shape, order)
+    rho0 = droplet_rho(shape, min(shape) / 3.0, seed=5)
+    for prec in ("fp32", "fp64"):
+        sim = Sim(rho0, "D2Q9", order=order, precision=prec, tau=0.8)
+        orc = O.Oracle(rho0, "D2Q9", order=order, tau=0.8)
+        sim.step(40)
+        orc.step(40)
+        _compare(sim, orc, prec, "%s E%d %s" % (shape, order, prec))
+        sim.close()
+
+
+@pytest.mark.parametrize("order", [4, 10])
+def test_d2q9_variants(order):
+    """Every launch shape matches the oracle (FP64 state, ragged 100 x 77
+    grid) and the FP32 shapes agree with each other to rounding."""
+    say("case d2q9 variants", order)
+    rho0 = droplet_rho((100, 77), 20, seed=9)
+    orc = O.Oracle(rho0, "D2Q9", order=order).step(25)
+    ref = None
+    for v in range(B.sc_lbm_num_variants(B.SC_D2Q9)):
+        sim = Sim(rho0, "D2Q9", order=order, variant=v, precision="fp64")
+        sim.step(25)
+        _compare(sim, orc, "fp64", "variant %s" % sim.variant)
+        sim.close()
+        sim = Sim(rho0, "D2Q9", order=order, variant=v)
+        sim.step(25)
+        st = sim.state()
+        sim.close()
+        if ref is None:
+            ref = st
+        else:
+            d = float(np.max(np.abs(st - ref)))
+            say("variant %d vs 0: max |diff| %.3e, bitwise %s" % (v, d, np.array_equal(st, ref)))
+            assert d <= 1e-6
+
+
+def test_d2q9_one_step_from_evolved_state():
+    """Oracle restarted from the GPU's state at t = 300 reproduces the GPU's
+    step t -> t + 1 (sampled one-step parity on developed fields)."""
+    rho0 = droplet_rho((64, 48), 14, seed=2)
+    sim = Sim(rho0, "D2Q9", order=8, precision="fp64")
+    sim.step(300)
+    orc = O.Oracle(rho0, "D2Q9", order=8)
+    orc.set_f(pre_collision_from_state(sim, orc.c))
+    sim.step(1)
+    orc.step(1)
+    _compare(sim, orc, "fp64", "restart E8")
+    sim.close()
+
+
+def test_force_on_analytic_psi():
+    """sc_lbm_force on a given psi field equals Eq. (1) in the oracle."""
+    x, y = np.meshgrid(np.arange(48.0), np.arange(40.0), indexing="ij")
+    psi = 0.6 + 0.3 * np.sin(2 * np.pi * x / 48) * np.cos(4 * np.pi * y / 40)
+    for order in (4, 6, 8, 10):
+        for prec, tol in (("fp32", 2e-6), ("fp64", 1e-14)):
+            sim = Sim(np.ones((48, 40)), "D2Q9", order=order, precision=prec)
+            F = sim.force(psi)
+            ref = O.force(psi, "D2Q9", order)
+            err = np.max(np.abs(F - ref)) / np.max(np.abs(ref))
+            say("force E%d %s err %.2e" % (order, prec, err))
+            assert err < tol
+            sim.close()
+
+
+def test_init_state_and_observables():
+    rho0 = droplet_rho((64, 64), 16, seed=1)
+    sim = Sim(rho0, "D2Q9", order=4, precision="fp64")
+    got = sim.observe()
+    orc = O.Oracle(rho0, "D2Q9", order=4)
+    ref = orc.fields()
+    assert np.max(np.abs(got["rho"] - rho0)) < 1e-14
+    assert np.max(np.abs(got["u"] - ref["u"])) < 1e-14
+    ob, ro = got["obs"], orc.observables()
+    for k in ("mass", "max_u", "mean_u", "l2_u", "rho_in", "rho_out", "p_in", "p_out", "dp", "radius"):
+        assert abs(ob[k] - ro[k]) <= 1e-12 * max(1.0, abs(ro[k])), k
+    sim.close()
+
+
+def test_observables_parity_fp32():
+    rho0 = droplet_rho((64, 64), 16, seed=1)
+    sim = Sim(rho0, "D2Q9", order=4)
+    orc = O.Oracle(rho0, "D2Q9", order=4)
+    sim.step(500)
+    orc.step(500)
+    ob, ro = sim.observe(fields=False)["obs"], orc.observables()
+    say("obs fp32:", {k: (ob[k], ro[k]) for k in ("max_u", "mean_u", "dp", "radius")})
+    assert abs(ob["mass"] - ro["mass"]) < 1e-6 * ro["mass"]
+    for k in ("max_u", "mean_u", "l2_u"):
+        assert abs(ob[k] - ro[k]) < 1e-3 * ro[k], k
+    assert abs(ob["dp"] - ro["dp"]) < 1e-4 * abs(ro["dp"]) + 1e-7
+    sim.close()
+
+
+# -------------------------------------------------------------- D3Q19 -----
+
+@pytest.mark.parametrize("collision", ["srt", "mrt"])
+@pytest.mark.parametrize("order", [4, 6, 8])
+def test_d3q19_droplet(order, collision):
+    say("case d3q19", order, collision)
+    rho0 = droplet_rho((20, 18, 13), 5, seed=3)
+    for prec in ("fp32", "fp64"):
+        sim = Sim(rho0, "D3Q19", order=order, collision=collision, precision=prec, tau=0.9)
+        orc = O.Oracle(rho0, "D3Q19", order=order, collision=collision, tau=0.9)
+        sim.step(30)
+        orc.step(30)
+        _compare(sim, orc, prec, "D3Q19 E%d %s %s" % (order, collision, prec))
+        sim.close()
+
+
+def test_d3q19_variants_bitwise():
+    rho0 = droplet_rho((40, 21, 35), 8, seed=4)
+    ref = None
+    for v in range(B.sc_lbm_num_variants(B.SC_D3Q19)):
+        sim = Sim(rho0, "D3Q19", order=8, collision="mrt", variant=v)
+        sim.step(6)
+        st = sim.state()
+        sim.close()
+        if ref is None:
+            ref = st
+        else:
+            assert np.array_equal(st, ref), v
+
+
+def test_d3q19_mrt_equals_srt_when_rates_equal():
+    rho0 = droplet_rho((16, 16, 16), 5, seed=3)
+    a = Sim(rho0, "D3Q19", order=8, collision="srt", precision="fp64", tau=0.8)
+    b = Sim(rho0, "D3Q19", order=8, collision="mrt", precision="fp64", tau=0.8,
+            s_bulk=1.25, s_ghost=1.25)
+    a.step(20)
+    b.step(20)
+    assert np.max(np.abs(a.state() - b.state())) < 1e-13
+    a.close()
+    b.close()
+
+
+# -------------------------------------------------- runtime behaviour -----
+
+def test_graph_and_direct_launch_agree():
+    rho0 = droplet_rho((64, 64), 16, seed=1)
+    a = Sim(rho0, "D2Q9", order=8)
+    b = Sim(rho0, "D2Q9", order=8)
+    a.step(96)          # graph-captured chunks of 32
+    for _ in range(96):
+        b.step(1)       # direct launches
+    assert np.array_equal(a.state(), b.state())
+    a.close()
+    b.close()
+
+
+def test_checkpoint_resume_bitwise():
+    rho0 = droplet_rho((64, 64), 16, seed=1)
+    a = Sim(rho0, "D2Q9", order=6)
+    a.step(70)
+    f = a.state()
+    a.step(45)
+    b = Sim(rho0, "D2Q9", order=6)
+    b.set_state(f, 70)
+    b.step(45)
+    assert np.array_equal(a.state(), b.state())
+    assert b.observe(fields=False)["obs"]["step"] == 115
+    a.close()
+    b.close()
+
+
+def test_convergence_loop_and_nonfinite():
+    rho0 = droplet_rho((32, 32), 8, seed=1)
+    sim = Sim(rho0, "D2Q9", order=4, obs_every=50)
+    rc, done = sim.step(20000, tol=1e-7)
+    assert rc == B.SC_OK
+    assert 0 < done < 20000
+    f = sim.state()
+    f[5] = np.nan
+    sim.set_state(f, 0)
+    rc, done = sim.step(200, tol=1e-9)
+    assert rc == B.SC_E_NONFINITE
+    sim.close()
+
+
+def test_mass_conservation_fp32():
+    rho0 = droplet_rho((64, 64), 16, seed=1)
+    sim = Sim(rho0, "D2Q9", order=8)
+    m0 = sim.observe(fields=False)["obs"]["mass"]
+    sim.step(10000)
+    ob = sim.observe(fields=False)["obs"]
+    say("fp32 mass drift over 1e4 steps: %.2e rel" % ((ob["mass"] - m0) / m0))
+    assert abs(ob["mass"] - m0) < 1e-5 * m0
+    sim.close()
+
+
+def test_mass_conservation_fp64():
+    rho0 = droplet_rho((64, 64), 16, seed=1)
+    sim = Sim(rho0, "D2Q9", order=8, precision="fp64")
+    m0 = sim.observe(fields=False)["obs"]["mass"]
+    sim.step(5000)
+    ob = sim.observe(fields=False)["obs"]
+    assert abs(ob["mass"] - m0) < 1e-12 * m0
+    sim.close()
+
+
+@pytest.mark.parametrize("order", [4, 8])
+def test_config1_long_horizon_observables(order):
+    """64^2 droplet (R = 16, G = -5, tau = 1) for 10,000 steps: FP32 GPU
+    spurious-velocity norms and Laplace jump against the FP64 oracle; the
+    FP64 GPU state pointwise."""
+    rho0 = droplet_rho((64, 64), 16, seed=1)
+    orc = O.Oracle(rho0, "D2Q9", order=order).step(10000)
+    ro = orc.observables()
+    ref = orc.fields()
+    s32 = Sim(rho0, "D2Q9", order=order)
+    s32.step(10000)
+    ob = s32.observe(fields=False)["obs"]
+    say("E%d 1e4 steps fp32 vs oracle: max_u %.6e/%.6e mean_u %.6e/%.6e dp %.6e/%.6e" % (
+        order, ob["max_u"], ro["max_u"], ob["mean_u"], ro["mean_u"], ob["dp"], ro["dp"]))
+    for k in ("max_u", "mean_u", "l2_u"):
+        assert abs(ob[k] - ro[k]) <= 1e-3 * ro[k], k
+    assert abs(ob["dp"] - ro["dp"]) <= 1e-4 * abs(ro["dp"])
+    assert abs(ob["radius"] - ro["radius"]) <= 1e-4 * ro["radius"]
+    s32.close()
+    s64 = Sim(rho0, "D2Q9", order=order, precision="fp64")
+    s64.step(10000)
+    got = s64.observe()
+    er = rel_err(got["rho"], ref["rho"])
+    say("E%d 1e4 steps fp64 pointwise rho err %.2e" % (order, er))
+    assert er <= 1e-11
+    s64.close()
