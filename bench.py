@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Throughput of the fused Shan-Chen step on one MI355X.
+
+Headline workload: D2Q9 SRT, 256 x 256 periodic, E8 force stencil (24
+neighbours), G = -5, tau = 1, psi = 1 - exp(-rho), droplet R = 40 (tanh
+profile rho_l = 2.0 / rho_v = 0.15, width 2, jitter 1e-3 seed 2), state in
+FP32 stored as f - w.  One "step" is one fused pass of psi(rho), the
+interaction force, Guo-forced collision and pull streaming over the grid;
+MLUPS = nodes x steps / time, with the state resident in HBM.
+
+Also reported (same JSON line, key "extra"): the 128^3 D3Q19 MRT E8 droplet,
+the HBM-bound grids 8192^2 (D2Q9 E8) and 320^3 (D3Q19 MRT E8), and the wall
+time of a 64^2 E4 droplet run to its steady state.
+
+Timing: HIP events on the library's stream around K graph-replayed steps,
+bracketed by device synchronisation.  The roofline uses the fused kernel's
+average duration from events around single launches.  The CPU baseline is
+the FP64 oracle on the host cores, on a bounded number of steps of the same
+workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extra] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS per GPU (D2Q9/D3Q19, E8 force) + wall-time to steady droplet"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "d2q9_e8_256": dict(lattice="D2Q9", shape=(256, 256), order=8, R=40, seed=2, collision="srt",
+                        desc="D2Q9 SRT 256x256 periodic, E8 force (24 nbrs), G=-5, tau=1, "
+                             "psi=1-exp(-rho), droplet R=40, FP32 shifted f-w"),
+    "d3q19_mrt_e8_128": dict(lattice="D3Q19", shape=(128, 128, 128), order=8, R=24, seed=3,
+                             collision="mrt",
+                             desc="D3Q19 MRT 128^3 periodic, E8 3D force (92 nbrs), G=-5, tau=1, "
+                                  "droplet R=24, FP32 shifted"),
+    "d2q9_e8_8192": dict(lattice="D2Q9", shape=(8192, 8192), order=8, R=1600, seed=7, collision="srt",
+                         desc="D2Q9 SRT 8192^2, E8, droplet R=1600, FP32 (HBM-bound size)"),
+    "d3q19_mrt_e8_320": dict(lattice="D3Q19", shape=(320, 320, 320), order=8, R=64, seed=8,
+                             collision="mrt",
+                             desc="D3Q19 MRT 320^3, E8, droplet R=64, FP32 (HBM-bound size)"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bytes_per_node(lattice):
+    q = 9 if lattice == "D2Q9" else 19
+    return 2 * q * 4   # read Q + write Q FP32 values (algorithmic traffic)
+
+
+def measure(name, steps, warmup, kernel_launches=50):
+    import torch
+
+    from paper_1906_11027_amd import Sim
+    from workload import droplet_rho
+
+    w = WORKLOADS[name]
+    rho0 = droplet_rho(w["shape"], w["R"], seed=w["seed"])
+    stream = torch.cuda.Stream()
+    sim = Sim(rho0, w["lattice"], order=w["order"], collision=w["collision"], precision="fp32",
+              stream=stream)
+    assert sim.stream == stream.cuda_stream, "library is not on the timed stream"
+    n = rho0.size
+    del rho0
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    # the device cannot finish before the host has enqueued the work it times
+    # only if the events bracket it: cross-check against the wall clock
+    if ms < 0.5 * wall * 1e3 and wall > 0.05:
+        raise RuntimeError("event time %.3f ms << wall %.3f ms: events do not bracket the steps"
+                           % (ms, wall * 1e3))
+    # per-launch kernel duration: events around single (non-graph) launches
+    ea = [torch.cuda.Event(enable_timing=True) for _ in range(kernel_launches)]
+    eb = [torch.cuda.Event(enable_timing=True) for _ in range(kernel_launches)]
+    for k in range(kernel_launches):
+        ea[k].record(stream)
+        sim.step(1)
+        eb[k].record(stream)
+    torch.cuda.synchronize()
+    kms = sorted(a.elapsed_time(b) for a, b in zip(ea, eb))
+    kmean = sum(kms) / len(kms)
+    ob = sim.observe(fields=False)["obs"]
+    variant = sim.variant
+    sim.close()
+    ok = ob["nonfinite"] == 0 and ob["mass"] > 0
+    mlups = n * steps / (ms * 1e-3) / 1e6
+    bpn = bytes_per_node(w["lattice"])
+    achieved = bpn * n / (kmean * 1e-3) / 1e9
+    return {
+        "workload": name, "desc": w["desc"], "nodes": n, "steps": steps, "ms_total": ms,
+        "ms_per_step": ms / steps, "wall_s": wall, "mlups": mlups, "kernel_ms_mean": kmean,
+        "kernel_ms_median": kms[len(kms) // 2], "bytes_per_node": bpn,
+        "achieved_gbs": achieved, "frac": achieved / HBM_PEAK_GBS, "variant": variant,
+        "finite": bool(ok), "max_u": ob["max_u"],
+    }
+
+
+def steady_droplet():
+    """Config-1 droplet (64^2, E4, R = 16) run to steady state on the GPU."""
+    import torch
+
+    from paper_1906_11027_amd import Sim
+    from workload import droplet_rho
+
+    rho0 = droplet_rho((64, 64), 16, seed=1)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim = Sim(rho0, "D2Q9", order=4, stream=stream, obs_every=100)
+    rc, done = sim.step(400000, tol=1e-10)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ob = sim.observe(fields=False)["obs"]
+    sim.close()
+    return {"workload": "D2Q9 SRT 64x64 E4 droplet R=16, FP32, to max|u| change < 1e-10 "
+                        "(or the FP32 round-off floor for 10 checks)",
+            "steps": done, "wall_s": wall, "max_u": ob["max_u"], "dp": ob["dp"], "rc": rc}
+
+
+def cpu_baseline(name, target_s=15.0):
+    from oracle import oracle as O
+    from workload import droplet_rho
+
+    w = WORKLOADS[name]
+    rho0 = droplet_rho(w["shape"], w["R"], seed=w["seed"])
+    o = O.Oracle(rho0, w["lattice"], order=w["order"], collision=w["collision"])
+    t0 = time.perf_counter()
+    o.step(2)
+    dt = (time.perf_counter() - t0) / 2
+    k = max(2, int(target_s / max(dt, 1e-6)))
+    t0 = time.perf_counter()
+    o.step(k)
+    el = time.perf_counter() - t0
+    return {"value": rho0.size * k / el / 1e6, "unit": "MLUPS", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": "%d steps of the %s workload (FP64 oracle, OpenMP over rows)" % (k, name)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="d2q9_e8_256", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the step would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    main_r = measure(args.workload, args.steps, args.warmup)
+    log("main:", json.dumps(main_r))
+    extra = {}
+    if not args.no_extra:
+        for name, st in (("d3q19_mrt_e8_128", 200), ("d2q9_e8_8192", 100), ("d3q19_mrt_e8_320", 40)):
+            if name == args.workload:
+                continue
+            r = measure(name, st, 10, kernel_launches=10)
+            log(name + ":", json.dumps(r))
+            extra[name] = {k: r[k] for k in ("mlups", "ms_per_step", "kernel_ms_mean", "achieved_gbs",
+                                             "frac", "variant", "finite")}
+        sd = steady_droplet()
+        log("steady:", json.dumps(sd))
+        extra["steady_droplet"] = sd
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(args.workload)
+        log("cpu:", json.dumps(cpu))
+
+    w = WORKLOADS[args.workload]
+    line = {
+        "metric": METRIC,
+        "value": round(main_r["mlups"], 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": w["desc"], "nodes": main_r["nodes"], "lattice": w["lattice"],
+                   "grid": list(w["shape"]), "stencil_order": w["order"], "variant": main_r["variant"]},
+        "roofline": {"bound": "hbm", "achieved": round(main_r["achieved_gbs"], 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(main_r["frac"], 4),
+                     "traffic": None,
+                     "kernel_ms_mean": main_r["kernel_ms_mean"],
+                     "bytes_per_launch": main_r["bytes_per_node"] * main_r["nodes"]},
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -159,6 +159,9 @@ int sc_lbm_set_state(sc_lbm* h, const void* f_in, int64_t step);
  * keep the data resident); NULL on a NULL handle. */
 void* sc_lbm_state_ptr(sc_lbm* h);
 
+/* The hipStream_t the handle enqueues on (the caller's, or its own). */
+void* sc_lbm_stream(sc_lbm* h);
+
 /* Name of the launch shape in use and the number of shapes available for
  * this lattice (for tuning sweeps through sc_lbm_params.variant). */
 const char* sc_lbm_variant_name(const sc_lbm* h);

@@ -70,12 +70,18 @@ def lib():
         L.orc_stencil.restype = ctypes.c_int
         L.orc_mrt_basis.argtypes = [ctypes.c_void_p, dp, dp, dp]
         L.orc_mrt_basis.restype = ctypes.c_int
+        L.orc_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
 
 def _dp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def num_threads():
+    """OpenMP threads the oracle's node loops use."""
+    return lib().orc_num_threads()
 
 
 def lattice_table(name):

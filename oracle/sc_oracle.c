@@ -27,6 +27,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_D2Q9 0
 #define ORC_D3Q19 1
@@ -461,4 +464,14 @@ int orc_mrt_basis(const orc_sim *s, double *M, double *norm, double *S)
         S[k] = s->S[k];
     }
     return 0;
+}
+
+/* Threads the node loops run on (for reporting CPU timings). */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -291,6 +291,8 @@ extern "C" void sc_lbm_destroy(sc_lbm* h)
 
 extern "C" void* sc_lbm_state_ptr(sc_lbm* h) { return h ? h->f[h->cur] : nullptr; }
 
+extern "C" void* sc_lbm_stream(sc_lbm* h) { return h ? (void*)h->stream : nullptr; }
+
 // one fused step from f[cur] into f[cur ^ 1] (no swap)
 static hipError_t enqueue_step(sc_lbm* h, int from)
 {

@@ -60,7 +60,7 @@ EXPORTS = [
     "sc_lbm_default_params", "sc_lbm_state_bytes", "sc_lbm_create", "sc_lbm_step",
     "sc_lbm_force", "sc_lbm_observe", "sc_lbm_set_state", "sc_lbm_state_ptr",
     "sc_lbm_variant_name", "sc_lbm_num_variants", "sc_lbm_destroy", "sc_lbm_strerror",
-    "sc_lbm_last_error_detail",
+    "sc_lbm_last_error_detail", "sc_lbm_stream",
 ]
 
 #: velocity order of the state buffers (include/sc_lbm.h)
@@ -116,6 +116,8 @@ def lib():
     L.sc_lbm_destroy.restype = None
     L.sc_lbm_strerror.argtypes = [ctypes.c_int]
     L.sc_lbm_strerror.restype = ctypes.c_char_p
+    L.sc_lbm_stream.argtypes = [vp]
+    L.sc_lbm_stream.restype = vp
     L.sc_lbm_last_error_detail.argtypes = []
     L.sc_lbm_last_error_detail.restype = ctypes.c_char_p
     _lib = L
@@ -237,7 +239,7 @@ class Sim:
     """One periodic domain on the GPU.  Device memory and the stream come
     from torch when `use_torch` is set (the default when torch sees a GPU)."""
 
-    def __init__(self, rho0, lattice="D2Q9", use_torch=None, **kw):
+    def __init__(self, rho0, lattice="D2Q9", use_torch=None, stream=None, **kw):
         rho0 = np.asarray(rho0, dtype=np.float64)
         self.shape = rho0.shape
         self.dim = rho0.ndim
@@ -246,7 +248,7 @@ class Sim:
         self.n = int(rho0.size)
         self.lattice = lattice
         self._bufs = None
-        dev_a = dev_b = stream = None
+        dev_a = dev_b = None
         if use_torch is None:
             try:
                 import torch
@@ -260,9 +262,12 @@ class Sim:
                 raise ScError(SC_E_INVAL, "sc_lbm_state_bytes")
             self._bufs = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(2)]
             dev_a, dev_b = self._bufs[0].data_ptr(), self._bufs[1].data_ptr()
-            stream = torch.cuda.current_stream().cuda_stream
+            if stream is None:
+                stream = torch.cuda.current_stream()
+        if stream is not None and hasattr(stream, "cuda_stream"):
+            stream = stream.cuda_stream
         flat = np.ascontiguousarray(rho0.transpose()).ravel()
-        self.h = sc_lbm_create(self.p, flat, dev_a, dev_b, stream)
+        self.h = sc_lbm_create(self.p, flat, dev_a, dev_b, stream or None)
 
     def close(self):
         if getattr(self, "h", None):
@@ -304,6 +309,11 @@ class Sim:
 
     def set_state(self, f, step):
         sc_lbm_set_state(self.h, np.ascontiguousarray(f), step)
+
+    @property
+    def stream(self):
+        """hipStream_t the library enqueues on (as an int)."""
+        return lib().sc_lbm_stream(self.h)
 
     @property
     def variant(self):
