@@ -170,6 +170,43 @@ int sc_lbm_num_variants(int32_t lattice);
 void sc_lbm_destroy(sc_lbm* h);
 const char* sc_lbm_strerror(int code);
 
+/* ---- batched sweeps ----------------------------------------------------- */
+/* Many independent D2Q9 SRT droplets (the droplet test of Sec. 3 repeated
+ * over a parameter sweep) advanced by ONE kernel launch per step over a
+ * (item, tile) work list.  Items may differ in nx, ny, stencil order, G, c0
+ * and tau; they must share precision, psi parameters and rho_ref.  Each
+ * item keeps its own state (two buffers carved from one allocation).
+ * Converged or diverged items leave the work list; the others continue. */
+typedef struct sc_lbm_batch sc_lbm_batch;
+
+/*   items      n parameter sets (lattice SC_D2Q9, collision SC_SRT);
+ *   rho_init   n host pointers to [nx*ny] initial densities (each nullable),
+ *              or NULL for rho = 1 everywhere;
+ *   hip_stream as for sc_lbm_create.
+ * Errors: SC_E_INVAL, SC_E_UNSUPPORTED (3D or MRT item), SC_E_NOMEM, SC_E_DEVICE. */
+int sc_lbm_batch_create(const sc_lbm_params* items, int32_t n, const double* const* rho_init, void* hip_stream,
+                        sc_lbm_batch** out);
+
+/* Advance every active item by up to max_steps.  tol = 0: exactly
+ * max_steps, asynchronously.  tol > 0: every K = items[0].obs_every steps
+ * each active item is reduced and leaves the work list when it meets the
+ * steady-state rule of sc_lbm_step, or is quarantined when non-finite.
+ * Returns when all items have left or max_steps are done. */
+int sc_lbm_batch_step(sc_lbm_batch* b, int64_t max_steps, double tol, int64_t* steps_done);
+
+/* Observables and optional fields of one item (as sc_lbm_observe);
+ * obs->converged_by reports the rule that retired the item. */
+int sc_lbm_batch_observe(sc_lbm_batch* b, int32_t item, sc_lbm_obs* obs, double* rho_out, double* u_out);
+
+/* Steps taken by an item and how it left (0 running, 1 tolerance rule,
+ * 2 FP32 round-off floor, -1 non-finite / quarantined). */
+int sc_lbm_batch_status(sc_lbm_batch* b, int32_t item, int64_t* steps, int32_t* converged_by);
+
+/* Number of items still in the work list. */
+int32_t sc_lbm_batch_active(sc_lbm_batch* b);
+
+void sc_lbm_batch_destroy(sc_lbm_batch* b);
+
 /* Detail of the last HIP failure seen by this host thread (which call, the
  * HIP error string and code); "" if none.  Valid until the next failure. */
 const char* sc_lbm_last_error_detail(void);

@@ -41,23 +41,53 @@ __device__ __forceinline__ int wrap_any(int v, int n)
     return r < 0 ? r + n : r;
 }
 
+// XCD-aware block order.  Work-groups are dealt round-robin to the 8 XCDs
+// (block b runs on XCD b % 8), each with its own L2.  Remap the linear block
+// id so that XCD k processes one contiguous range of logical tiles: tiles
+// that share halo lines then run on the same XCD at about the same time.
+// The map is a bijection on [0, nb) for any nb.
+__device__ __forceinline__ int xcd_swizzle(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7;
+    const int x = b & 7, i = b >> 3;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// Addressing of the hot kernels: one velocity plane holds N values, fewer
+// than 2^32 bytes (checked on the host), so a node is addressed as the plane's
+// uniform base pointer (scalar registers) plus a 32-bit per-lane byte offset,
+// the global-load form with a scalar base and a 32-bit vector offset.
+template <typename T>
+__device__ __forceinline__ T ld_off(const T* __restrict__ base, uint32_t off)
+{
+    return *(const T*)((const char*)base + off);
+}
+template <typename T>
+__device__ __forceinline__ void st_off(T* __restrict__ base, uint32_t off, T v)
+{
+    *(T*)((char*)base + off) = v;
+}
+
 // ---------------------------------------------------------------- D2Q9 ----
 // Pull the nine shifted distributions of node (x, y): value b comes from
-// (x - cx_b, y - cy_b).  xm/xp/ym/yp are the wrapped neighbours.
+// (x - cx_b, y - cy_b).  xo[0..2] are the byte offsets of columns x-1, x,
+// x+1 and yo[0..2] those of rows y-1, y, y+1 (wrapped).
 template <typename T>
-__device__ __forceinline__ void pull_d2q9(const T* __restrict__ f, int64_t n, int nx,
-                                          int x, int xm, int xp, int y, int ym, int yp, T (&g)[9])
+__device__ __forceinline__ void pull_d2q9(const T* __restrict__ f, int64_t n, const uint32_t (&xo)[3],
+                                          const uint32_t (&yo)[3], T (&g)[9])
 {
-    const int64_t r0 = (int64_t)y * nx, rm = (int64_t)ym * nx, rp = (int64_t)yp * nx;
-    g[0] = f[0 * n + r0 + x];
-    g[1] = f[1 * n + r0 + xm];
-    g[2] = f[2 * n + rm + x];
-    g[3] = f[3 * n + r0 + xp];
-    g[4] = f[4 * n + rp + x];
-    g[5] = f[5 * n + rm + xm];
-    g[6] = f[6 * n + rm + xp];
-    g[7] = f[7 * n + rp + xp];
-    g[8] = f[8 * n + rp + xm];
+#pragma unroll
+    for (int b = 0; b < 9; ++b)
+        g[b] = ld_off(f + b * n, yo[1 - D2Q9::cy[b]] + xo[1 - D2Q9::cx[b]]);
+}
+
+// byte offsets of the wrapped neighbours of coordinate v in [0, n): k-1, k, k+1
+template <typename T>
+__device__ __forceinline__ void nbr_offsets(int v, int n, uint32_t stride, uint32_t (&o)[3])
+{
+    o[0] = (uint32_t)(v == 0 ? n - 1 : v - 1) * stride;
+    o[1] = (uint32_t)v * stride;
+    o[2] = (uint32_t)(v == n - 1 ? 0 : v + 1) * stride;
 }
 
 template <typename T>
@@ -237,5 +267,14 @@ hipError_t launch_force(int lattice, int precision, int order, const void* args,
                         bool with_velocity, hipStream_t s);
 hipError_t launch_psi_from_host(int precision, const double* psi_dev_d, void* psi, int64_t n, hipStream_t s);
 hipError_t launch_reduce(int dim, ObsBuffers& ob, int64_t n, hipStream_t s);
+
+// Batched D2Q9 step over a (item, tile) work list (kernels_batch.hip).
+int batch_tile_w();
+int batch_tile_h();
+size_t batch_item_bytes(int precision);
+void batch_fill_item(void* dst, int precision, const void* a, void* b, int nx, int ny, int order, double gc0,
+                     double tau);
+hipError_t launch_batch_d2q9(const void* items, const int2* work, int nwork, int parity, int precision,
+                             const void* common, hipStream_t s);
 
 }  // namespace sclbm

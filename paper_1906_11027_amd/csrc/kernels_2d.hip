@@ -18,7 +18,7 @@ namespace sclbm {
 
 template <typename T, int ORDER, int TX, int TY, int RPT>
 __global__ void __launch_bounds__(TX*(TY / RPT))
-k_d2q9_tile(StepArgs<T> a)
+k_d2q9_tile(StepArgs<T> a, int nbx)
 {
     using ST = Stencil<2, ORDER>;
     constexpr int R = ST::R;
@@ -31,24 +31,28 @@ k_d2q9_tile(StepArgs<T> a)
     const int64_t n = a.n;
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = ty * TX + tx;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int L = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int x0 = (L % nbx) * TX, y0 = (L / nbx) * TY;
 
+    const uint32_t TS = sizeof(T), rowb = (uint32_t)nx * TS;
     const int xr = x0 + tx;
     const bool xin = xr < nx;
     const int x = xin ? xr : xr % nx;
-    const int xm = x == 0 ? nx - 1 : x - 1;
-    const int xp = x == nx - 1 ? 0 : x + 1;
+    uint32_t xo[3];
+    nbr_offsets<T>(x, nx, TS, xo);
 
     T g[RPT][9];
     T dr[RPT];
+    uint32_t own[RPT];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
         const int ly = ty * RPT + k;
         const int yr = y0 + ly;
         const int y = yr < ny ? yr : yr % ny;
-        const int ym = y == 0 ? ny - 1 : y - 1;
-        const int yp = y == ny - 1 ? 0 : y + 1;
-        pull_d2q9(a.fin, n, nx, x, xm, xp, y, ym, yp, g[k]);
+        uint32_t yo[3];
+        nbr_offsets<T>(y, ny, rowb, yo);
+        own[k] = yo[1] + xo[1];
+        pull_d2q9(a.fin, n, xo, yo, g[k]);
         dr[k] = sum9(g[k]);
         psi_s[(ly + R) * LW + tx + R] = psi_of(a.rho_ref + dr[k], a);
     }
@@ -70,12 +74,11 @@ k_d2q9_tile(StepArgs<T> a)
             const int c = j % (2 * R);
             lx = c < R ? c : TX + c;
         }
-        const int hx = wrap_any(x0 - R + lx, nx);
-        const int hy = wrap_any(y0 - R + ly, ny);
-        const int hxm = hx == 0 ? nx - 1 : hx - 1, hxp = hx == nx - 1 ? 0 : hx + 1;
-        const int hym = hy == 0 ? ny - 1 : hy - 1, hyp = hy == ny - 1 ? 0 : hy + 1;
+        uint32_t hxo[3], hyo[3];
+        nbr_offsets<T>(wrap_any(x0 - R + lx, nx), nx, TS, hxo);
+        nbr_offsets<T>(wrap_any(y0 - R + ly, ny), ny, rowb, hyo);
         T h[9];
-        pull_d2q9(a.fin, n, nx, hx, hxm, hxp, hy, hym, hyp, h);
+        pull_d2q9(a.fin, n, hxo, hyo, h);
         psi_s[ly * LW + lx] = psi_of(a.rho_ref + sum9(h), a);
     }
     __syncthreads();
@@ -98,23 +101,106 @@ k_d2q9_tile(StepArgs<T> a)
         const T pref = -a.gc0 * c[0];
         collide_d2q9_srt(g[k], dr[k], pref * sx, pref * sy, a);
         if (xin && yr < ny) {
-            T* o = a.fout + (int64_t)yr * nx + xr;
 #pragma unroll
-            for (int b = 0; b < 9; ++b) o[b * n] = g[k][b];
+            for (int b = 0; b < 9; ++b) st_off(a.fout + b * n, own[k], g[k][b]);
+        }
+    }
+}
+
+
+// y-marching kernel for large grids.  A block of NT threads owns the
+// NT - 2R output columns [x0, x0 + NT - 2R) and H rows [y0, y0 + H); thread t
+// handles column x0 - R + t, so the R outermost threads on each side only
+// supply halo psi.  The block walks rows y0 - R ... y0 + H + R - 1: row j's
+// psi goes into one of 2R + 2 LDS row slots, and once rows j - 2R ... j are
+// resident row j - R is collided and stored.  The 9 values of the next row
+// are loaded while the current row is processed (prefetch distance 1), and
+// the values of the R pending rows stay in registers: the row loop is
+// unrolled by R + 2 so the register window is statically indexed.  Each
+// interior value is read from HBM once; the halo costs 2R columns per block
+// (same XCD, L2 hits) and 2R + 2 rows per H (neighbouring segment).
+template <typename T, int ORDER, int NT>
+__global__ void __launch_bounds__(NT)
+k_d2q9_march(StepArgs<T> a, int H, int nbx)
+{
+    using ST = Stencil<2, ORDER>;
+    constexpr int R = ST::R;
+    constexpr int TXO = NT - 2 * R;
+    constexpr int NS = 2 * R + 2;
+    constexpr int W = R + 2;
+    __shared__ T psi_s[NS * NT];
+
+    const int nx = a.nx, ny = a.ny;
+    const int64_t n = a.n;
+    const int L = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int x0 = (L % nbx) * TXO, y0 = (L / nbx) * H;
+    const int t = threadIdx.x;
+    const uint32_t TS = sizeof(T), rowb = (uint32_t)nx * TS;
+    const int xr = x0 - R + t;
+    uint32_t xo[3];
+    nbr_offsets<T>(wrap_any(xr, nx), nx, TS, xo);
+    const bool interior = t >= R && t < NT - R && xr < nx;
+    const int nrows = H + 2 * R;
+
+    T g[W][9];
+    int yl = wrap_any(y0 - R, ny);   // row being loaded
+    {
+        uint32_t yo[3];
+        nbr_offsets<T>(yl, ny, rowb, yo);
+        pull_d2q9(a.fin, n, xo, yo, g[0]);
+    }
+    for (int j0 = 0; j0 < nrows; j0 += W) {
+#pragma unroll
+        for (int s = 0; s < W; ++s) {
+            const int j = j0 + s;
+            if (j < nrows) {   // uniform across the block
+                if (j + 1 < nrows) {
+                    yl = yl == ny - 1 ? 0 : yl + 1;
+                    uint32_t yo[3];
+                    nbr_offsets<T>(yl, ny, rowb, yo);
+                    pull_d2q9(a.fin, n, xo, yo, g[(s + 1) % W]);
+                }
+                const T dr = sum9(g[s]);
+                psi_s[(j % NS) * NT + t] = psi_of(a.rho_ref + dr, a);
+                __syncthreads();
+                if (j >= 2 * R && interior) {
+                    const int sc = (s + 2) % W;         // slot of row j - R
+                    const int yrel = j - 2 * R;
+                    const int yr = y0 + yrel;
+                    int sl[2 * R + 1];
+#pragma unroll
+                    for (int d = -R; d <= R; ++d) sl[d + R] = ((j - R + d) % NS) * NT + t;
+                    T sx = T(0), sy = T(0);
+#pragma unroll
+                    for (int p = 0; p < ST::NP; ++p) {
+                        constexpr PairList P = ST::P;
+                        const int ex = P.e[p][0], ey = P.e[p][1];
+                        const T d = psi_s[sl[R + ey] + ex] - psi_s[sl[R - ey] - ex];
+                        const T wd = T(P.w[p]) * d;
+                        if (ex) sx += T(ex) * wd;
+                        if (ey) sy += T(ey) * wd;
+                    }
+                    const T pref = -a.gc0 * psi_s[sl[R]];
+                    const T drc = sum9(g[sc]);
+                    collide_d2q9_srt(g[sc], drc, pref * sx, pref * sy, a);
+                    if (yrel < H && yr < ny) {
+                        const uint32_t off = (uint32_t)yr * rowb + (uint32_t)xr * TS;
+#pragma unroll
+                        for (int b = 0; b < 9; ++b) st_off(a.fout + b * n, off, g[sc][b]);
+                    }
+                }
+            }
         }
     }
 }
 
 // ------------------------------------------------------------ dispatch ----
 struct Shape2D {
-    int tx, ty, rpt;
     const char* name;
 };
 static const Shape2D kShapes2D[] = {
-    {64, 16, 4, "tile64x16r4"},
-    {64, 8, 2, "tile64x8r2"},
-    {32, 8, 1, "tile32x8r1"},
-    {64, 4, 1, "tile64x4r1"},
+    {"tile64x16r4"}, {"tile64x8r2"}, {"tile32x8r1"}, {"tile64x4r1"},
+    {"march256h128"}, {"march256h64"}, {"march512h128"}, {"march256h256"},
 };
 constexpr int kNumShapes2D = sizeof(kShapes2D) / sizeof(kShapes2D[0]);
 
@@ -124,9 +210,20 @@ const char* variant_name_d2q9(int v) { return (v >= 0 && v < kNumShapes2D) ? kSh
 template <typename T, int ORDER, int TX, int TY, int RPT>
 static hipError_t launch_tile(const StepArgs<T>& a, hipStream_t s)
 {
+    const int nbx = (a.nx + TX - 1) / TX, nby = (a.ny + TY - 1) / TY;
     dim3 block(TX, TY / RPT);
-    dim3 grid((a.nx + TX - 1) / TX, (a.ny + TY - 1) / TY);
-    hipLaunchKernelGGL((k_d2q9_tile<T, ORDER, TX, TY, RPT>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((k_d2q9_tile<T, ORDER, TX, TY, RPT>), dim3(nbx * nby), block, 0, s, a, nbx);
+    return hipGetLastError();
+}
+
+template <typename T, int ORDER, int NT>
+static hipError_t launch_march(const StepArgs<T>& a, int H, hipStream_t s)
+{
+    constexpr int R = Stencil<2, ORDER>::R;
+    constexpr int TXO = NT - 2 * R;
+    if (H > a.ny) H = a.ny;
+    const int nbx = (a.nx + TXO - 1) / TXO, nby = (a.ny + H - 1) / H;
+    hipLaunchKernelGGL((k_d2q9_march<T, ORDER, NT>), dim3(nbx * nby), dim3(NT), 0, s, a, H, nbx);
     return hipGetLastError();
 }
 
@@ -138,6 +235,10 @@ static hipError_t launch_order(const StepArgs<T>& a, int variant, hipStream_t s)
     case 1: return launch_tile<T, ORDER, 64, 8, 2>(a, s);
     case 2: return launch_tile<T, ORDER, 32, 8, 1>(a, s);
     case 3: return launch_tile<T, ORDER, 64, 4, 1>(a, s);
+    case 4: return launch_march<T, ORDER, 256>(a, 128, s);
+    case 5: return launch_march<T, ORDER, 256>(a, 64, s);
+    case 6: return launch_march<T, ORDER, 512>(a, 128, s);
+    case 7: return launch_march<T, ORDER, 256>(a, 256, s);
     default: return hipErrorInvalidValue;
     }
 }

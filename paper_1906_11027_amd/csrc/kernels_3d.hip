@@ -18,17 +18,18 @@
 namespace sclbm {
 
 template <typename T>
-__device__ __forceinline__ void pull_d3q19(const T* __restrict__ f, int64_t n, const int64_t (&zo)[3],
-                                           const int64_t (&yo)[3], const int (&xo)[3], T (&g)[19])
+__device__ __forceinline__ void pull_d3q19(const T* __restrict__ f, int64_t n, uint32_t zb, const uint32_t (&zo)[3],
+                                           const uint32_t (&yo)[3], const uint32_t (&xo)[3], T (&g)[19])
 {
+    (void)zb;
 #pragma unroll
     for (int b = 0; b < 19; ++b)
-        g[b] = f[b * n + zo[1 - D3Q19::cz[b]] + yo[1 - D3Q19::cy[b]] + xo[1 - D3Q19::cx[b]]];
+        g[b] = ld_off(f + b * n, zo[1 - D3Q19::cz[b]] + yo[1 - D3Q19::cy[b]] + xo[1 - D3Q19::cx[b]]);
 }
 
 template <typename T, int ORDER, bool MRT, int TX, int TYB, int RPT>
 __global__ void __launch_bounds__(TX* TYB)
-k_d3q19_march(StepArgs<T> a, int H)
+k_d3q19_march(StepArgs<T> a, int H, int nbx, int nby)
 {
     using ST = Stencil<3, ORDER>;
     constexpr int R = ST::R;
@@ -39,92 +40,89 @@ k_d3q19_march(StepArgs<T> a, int H)
     constexpr int NS = 2 * R + 2;        // psi ring slots
     constexpr int NT = TX * TYB;
     constexpr int W = R + 1;             // f register window
+    constexpr int RING = PL - TX * TY;   // halo nodes per plane
+    constexpr int RPERT = (RING + NT - 1) / NT;
     __shared__ T psi_s[NS * PL];
 
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int64_t n = a.n;
-    const int64_t nxy = (int64_t)nx * ny;
+    const uint32_t TS = sizeof(T), rowb = (uint32_t)nx * TS, planeb = (uint32_t)ny * rowb;
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = ty * TX + tx;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * H;
+    const int L = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int x0 = (L % nbx) * TX, y0 = ((L / nbx) % nby) * TY, z0 = (L / (nbx * nby)) * H;
 
     const int xr = x0 + tx;
     const bool xin = xr < nx;
-    const int x = xin ? xr : xr % nx;
-    int xo[3];
-    xo[0] = x == 0 ? nx - 1 : x - 1;
-    xo[1] = x;
-    xo[2] = x == nx - 1 ? 0 : x + 1;
-    int64_t yo[RPT][3];
+    uint32_t xo[3];
+    nbr_offsets<T>(xin ? xr : xr % nx, nx, TS, xo);
+    uint32_t yo[RPT][3];
     bool yin[RPT];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
         const int yr = y0 + ty * RPT + k;
         yin[k] = yr < ny;
-        const int y = yr < ny ? yr : yr % ny;
-        yo[k][0] = (int64_t)(y == 0 ? ny - 1 : y - 1) * nx;
-        yo[k][1] = (int64_t)y * nx;
-        yo[k][2] = (int64_t)(y == ny - 1 ? 0 : y + 1) * nx;
+        nbr_offsets<T>(yr < ny ? yr : yr % ny, ny, rowb, yo[k]);
+    }
+    // this thread's halo-ring nodes (same in every plane): LDS index and offsets
+    int rl[RPERT];
+    uint32_t rxo[RPERT][3], ryo[RPERT][3];
+#pragma unroll
+    for (int q = 0; q < RPERT; ++q) {
+        const int i = tid + q * NT;
+        int lx = 0, ly = 0;
+        if (i < R * LW) {
+            ly = i / LW;
+            lx = i - ly * LW;
+        } else if (i < 2 * R * LW) {
+            const int jj = i - R * LW;
+            ly = TY + R + jj / LW;
+            lx = jj % LW;
+        } else if (i < RING) {
+            const int jj = i - 2 * R * LW;
+            ly = R + jj / (2 * R);
+            const int c = jj % (2 * R);
+            lx = c < R ? c : TX + c;
+        }
+        rl[q] = i < RING ? ly * LW + lx : -1;
+        nbr_offsets<T>(wrap_any(x0 - R + lx, nx), nx, TS, rxo[q]);
+        nbr_offsets<T>(wrap_any(y0 - R + ly, ny), ny, rowb, ryo[q]);
     }
 
     T g[W][RPT][19];
     T dr[W][RPT];
     const int nplanes = H + 2 * R;
+    int zc = wrap_any(z0 - R, nz);
 
     for (int j0 = 0; j0 < nplanes; j0 += W) {
 #pragma unroll
         for (int s = 0; s < W; ++s) {
             const int j = j0 + s;
             if (j < nplanes) {   // uniform across the block
-                const int zc = wrap_any(z0 - R + j, nz);
-                int64_t zo[3];
-                zo[0] = (int64_t)(zc == 0 ? nz - 1 : zc - 1) * nxy;
-                zo[1] = (int64_t)zc * nxy;
-                zo[2] = (int64_t)(zc == nz - 1 ? 0 : zc + 1) * nxy;
+                uint32_t zo[3];
+                nbr_offsets<T>(zc, nz, planeb, zo);
                 T* slot = psi_s + (j % NS) * PL;
 #pragma unroll
                 for (int k = 0; k < RPT; ++k) {
-                    pull_d3q19(a.fin, n, zo, yo[k], xo, g[s][k]);
+                    pull_d3q19(a.fin, n, 0u, zo, yo[k], xo, g[s][k]);
                     dr[s][k] = sum19(g[s][k]);
                     slot[(ty * RPT + k + R) * LW + tx + R] = psi_of(a.rho_ref + dr[s][k], a);
                 }
-                constexpr int RING = PL - TX * TY;
-                for (int i = tid; i < RING; i += NT) {
-                    int lx, ly;
-                    if (i < R * LW) {
-                        ly = i / LW;
-                        lx = i - ly * LW;
-                    } else if (i < 2 * R * LW) {
-                        const int jj = i - R * LW;
-                        ly = TY + R + jj / LW;
-                        lx = jj % LW;
-                    } else {
-                        const int jj = i - 2 * R * LW;
-                        ly = R + jj / (2 * R);
-                        const int c = jj % (2 * R);
-                        lx = c < R ? c : TX + c;
+#pragma unroll
+                for (int q = 0; q < RPERT; ++q) {
+                    if (rl[q] >= 0) {
+                        T h[19];
+                        pull_d3q19(a.fin, n, 0u, zo, ryo[q], rxo[q], h);
+                        slot[rl[q]] = psi_of(a.rho_ref + sum19(h), a);
                     }
-                    const int hx = wrap_any(x0 - R + lx, nx);
-                    const int hy = wrap_any(y0 - R + ly, ny);
-                    int hxo[3];
-                    int64_t hyo[3];
-                    hxo[0] = hx == 0 ? nx - 1 : hx - 1;
-                    hxo[1] = hx;
-                    hxo[2] = hx == nx - 1 ? 0 : hx + 1;
-                    hyo[0] = (int64_t)(hy == 0 ? ny - 1 : hy - 1) * nx;
-                    hyo[1] = (int64_t)hy * nx;
-                    hyo[2] = (int64_t)(hy == ny - 1 ? 0 : hy + 1) * nx;
-                    T h[19];
-                    pull_d3q19(a.fin, n, zo, hyo, hxo, h);
-                    slot[ly * LW + lx] = psi_of(a.rho_ref + sum19(h), a);
                 }
+                zc = zc == nz - 1 ? 0 : zc + 1;
                 __syncthreads();
 
                 if (j >= 2 * R) {
                     const int sc = (s + 1) % W;          // register slot of plane j - R (static after unrolling)
                     const int zrel = j - 2 * R;          // 0 .. H-1
                     const int zr = z0 + zrel;
-                    const int cs = (j - R) % NS;         // psi slot of the centre plane
                     int sl[2 * R + 1];
 #pragma unroll
                     for (int d = -R; d <= R; ++d) sl[d + R] = ((j - R + d) % NS) * PL;
@@ -135,6 +133,9 @@ k_d3q19_march(StepArgs<T> a, int H)
 #pragma unroll
                         for (int p = 0; p < ST::NP; ++p) {
                             constexpr PairList P = ST::P;
+                            // keep the LDS reads in groups of 8 pairs so the
+                            // scheduler cannot hoist all of them (registers)
+                            if (p % 8 == 0 && p) __builtin_amdgcn_sched_barrier(0);
                             const int ex = P.e[p][0], ey = P.e[p][1], ez = P.e[p][2];
                             const T vp = psi_s[sl[R + ez] + cidx + ey * LW + ex];
                             const T vm = psi_s[sl[R - ez] + cidx - ey * LW - ex];
@@ -143,12 +144,12 @@ k_d3q19_march(StepArgs<T> a, int H)
                             if (ey) sy += T(ey) * wd;
                             if (ez) sz += T(ez) * wd;
                         }
-                        const T pref = -a.gc0 * psi_s[cs * PL + cidx];
+                        const T pref = -a.gc0 * psi_s[sl[R] + cidx];
                         collide_d3q19<T, MRT>(g[sc][k], dr[sc][k], pref * sx, pref * sy, pref * sz, a);
                         if (xin && yin[k] && zr < nz) {
-                            T* o = a.fout + (int64_t)zr * nxy + yo[k][1] + xr;
+                            const uint32_t off = (uint32_t)zr * planeb + yo[k][1] + xo[1];
 #pragma unroll
-                            for (int b = 0; b < 19; ++b) o[b * n] = g[sc][k][b];
+                            for (int b = 0; b < 19; ++b) st_off(a.fout + b * n, off, g[sc][k][b]);
                         }
                     }
                 }
@@ -167,6 +168,9 @@ static const Shape3D kShapes3D[] = {
     {64, 4, 2, 16, "march64x8h16"},
     {32, 8, 1, 16, "march32x8h16"},
     {32, 8, 2, 32, "march32x16h32"},
+    {32, 16, 1, 16, "march32x16r1h16"},
+    {64, 8, 1, 16, "march64x8r1h16"},
+    {32, 16, 1, 32, "march32x16r1h32"},
 };
 constexpr int kNumShapes3D = sizeof(kShapes3D) / sizeof(kShapes3D[0]);
 
@@ -178,8 +182,10 @@ static hipError_t launch_march(const StepArgs<T>& a, int H, hipStream_t s)
 {
     if (H > a.nz) H = a.nz;
     dim3 block(TX, TYB);
-    dim3 grid((a.nx + TX - 1) / TX, (a.ny + TYB * RPT - 1) / (TYB * RPT), (a.nz + H - 1) / H);
-    hipLaunchKernelGGL((k_d3q19_march<T, ORDER, MRT, TX, TYB, RPT>), grid, block, 0, s, a, H);
+    const int nbx = (a.nx + TX - 1) / TX, nby = (a.ny + TYB * RPT - 1) / (TYB * RPT);
+    const int nbz = (a.nz + H - 1) / H;
+    hipLaunchKernelGGL((k_d3q19_march<T, ORDER, MRT, TX, TYB, RPT>), dim3(nbx * nby * nbz), block, 0, s,
+                       a, H, nbx, nby);
     return hipGetLastError();
 }
 
@@ -191,6 +197,9 @@ static hipError_t launch_v(const StepArgs<T>& a, int variant, hipStream_t s)
     case 1: return launch_march<T, ORDER, MRT, 64, 4, 2>(a, 16, s);
     case 2: return launch_march<T, ORDER, MRT, 32, 8, 1>(a, 16, s);
     case 3: return launch_march<T, ORDER, MRT, 32, 8, 2>(a, 32, s);
+    case 4: return launch_march<T, ORDER, MRT, 32, 16, 1>(a, 16, s);
+    case 5: return launch_march<T, ORDER, MRT, 64, 8, 1>(a, 16, s);
+    case 6: return launch_march<T, ORDER, MRT, 32, 16, 1>(a, 32, s);
     default: return hipErrorInvalidValue;
     }
 }

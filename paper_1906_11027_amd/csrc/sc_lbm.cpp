@@ -98,7 +98,10 @@ static int validate(const sc_lbm_params* p)
     if (p->lattice == SC_D2Q9 && p->nz != 1) return SC_E_INVAL;
     const int64_t n = (int64_t)p->nx * p->ny * p->nz;
     const int q = p->lattice == SC_D2Q9 ? 9 : 19;
-    if (n * q >= ((int64_t)1 << 40)) return SC_E_INVAL;
+    // one velocity plane must stay below 4 GiB (32-bit byte offsets in the kernels)
+    const int64_t ts = p->precision == SC_FP64 ? 8 : 4;
+    if (n * ts >= ((int64_t)1 << 32)) return SC_E_UNSUPPORTED;
+    (void)q;
     if (p->lattice == SC_D2Q9) {
         if (p->order != 4 && p->order != 6 && p->order != 8 && p->order != 10) return SC_E_INVAL;
     } else {
@@ -554,4 +557,278 @@ extern "C" const char* sc_lbm_strerror(int code)
     case SC_E_NONFINITE: return "non-finite value in the state";
     default: return "unknown error";
     }
+}
+
+// =========================================================================
+// Batched sweeps: many D2Q9 items advanced by one launch per step.
+// =========================================================================
+
+struct sc_lbm_batch {
+    int n = 0;
+    int precision = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<sc_lbm*> items;
+    void* pool = nullptr;
+    void* desc = nullptr;
+    int2* work = nullptr;
+    int nwork = 0;
+    int work_cap = 0;
+    std::vector<int> tiles;       // tiles per item
+    std::vector<int> active;      // 1 while the item is stepped
+    std::vector<int> conv_by;     // 0 running, 1 tol rule, 2 FP32 floor, -1 non-finite
+    int parity = 0;
+    int64_t step = 0;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    bool graph_failed = false;
+    StepArgs<float> cf{};
+    StepArgs<double> cd{};
+};
+
+static void batch_release(sc_lbm_batch* b)
+{
+    if (!b) return;
+    for (int k = 0; k < 2; ++k)
+        if (b->gexec[k]) hipGraphExecDestroy(b->gexec[k]);
+    for (sc_lbm* h : b->items)
+        if (h) release(h);
+    hipFree(b->pool);
+    hipFree(b->desc);
+    hipFree(b->work);
+    if (b->own_stream && b->stream) hipStreamDestroy(b->stream);
+    delete b;
+}
+
+static int batch_rebuild_work(sc_lbm_batch* b)
+{
+    std::vector<int2> w;
+    for (int i = 0; i < b->n; ++i)
+        if (b->active[i])
+            for (int t = 0; t < b->tiles[i]; ++t) w.push_back(make_int2(i, t));
+    b->nwork = (int)w.size();
+    for (int k = 0; k < 2; ++k)
+        if (b->gexec[k]) {
+            hipGraphExecDestroy(b->gexec[k]);
+            b->gexec[k] = nullptr;
+        }
+    if (w.empty()) return SC_OK;
+    hipError_t e = hipMemcpyAsync(b->work, w.data(), sizeof(int2) * w.size(), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    return hip_err(e);
+}
+
+static hipError_t batch_enqueue(sc_lbm_batch* b, int parity)
+{
+    const void* common = b->precision == SC_FP64 ? (const void*)&b->cd : (const void*)&b->cf;
+    return launch_batch_d2q9(b->desc, b->work, b->nwork, parity, b->precision, common, b->stream);
+}
+
+// enqueue `count` steps for the active items (asynchronous)
+static hipError_t batch_run(sc_lbm_batch* b, int64_t count)
+{
+    hipError_t e = hipSuccess;
+    while (count >= 2 && !b->graph_failed && b->nwork > 0) {
+        if (!b->gexec[b->parity]) {
+            hipGraph_t g = nullptr;
+            e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+            hipError_t le = hipSuccess;
+            if (e == hipSuccess) {
+                le = batch_enqueue(b, b->parity);
+                if (le == hipSuccess) le = batch_enqueue(b, b->parity ^ 1);
+                e = hipStreamEndCapture(b->stream, &g);
+                if (le != hipSuccess) e = le;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec[b->parity], g, nullptr, nullptr, 0);
+            if (g) hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                b->graph_failed = true;
+                break;
+            }
+        }
+        e = hipGraphLaunch(b->gexec[b->parity], b->stream);
+        if (e != hipSuccess) return e;
+        count -= 2;
+        b->step += 2;
+    }
+    for (; count > 0; --count) {
+        e = batch_enqueue(b, b->parity);
+        if (e != hipSuccess) return e;
+        b->parity ^= 1;
+        b->step += 1;
+    }
+    for (int i = 0; i < b->n; ++i)
+        if (b->active[i]) {
+            b->items[i]->cur = b->parity;
+            b->items[i]->step = b->step;
+        }
+    return hipSuccess;
+}
+
+extern "C" int sc_lbm_batch_create(const sc_lbm_params* items, int32_t n, const double* const* rho_init,
+                                   void* hip_stream, sc_lbm_batch** out)
+{
+    if (!items || n < 1 || !out) return SC_E_INVAL;
+    for (int i = 0; i < n; ++i) {
+        int rc = validate(&items[i]);
+        if (rc != SC_OK) return rc;
+        if (items[i].lattice != SC_D2Q9 || items[i].collision != SC_SRT) return SC_E_UNSUPPORTED;
+        if (items[i].precision != items[0].precision || items[i].psi_kind != items[0].psi_kind ||
+            items[i].psi0 != items[0].psi0 || items[i].rho_psi != items[0].rho_psi ||
+            items[i].rho_ref != items[0].rho_ref)
+            return SC_E_INVAL;
+    }
+    sc_lbm_batch* b = new (std::nothrow) sc_lbm_batch();
+    if (!b) return SC_E_NOMEM;
+    b->n = n;
+    b->precision = items[0].precision;
+    hipError_t e;
+    if (hip_stream) {
+        b->stream = (hipStream_t)hip_stream;
+    } else {
+        e = hipStreamCreate(&b->stream);
+        if (e != hipSuccess) {
+            delete b;
+            return hip_err(e);
+        }
+        b->own_stream = true;
+    }
+    std::vector<size_t> off(n);
+    size_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        off[i] = total;
+        total += 2 * ((sc_lbm_state_bytes(&items[i]) + 255) / 256 * 256);
+    }
+    e = hipMalloc(&b->pool, total);
+    if (e == hipSuccess) e = hipMalloc(&b->desc, batch_item_bytes(b->precision) * n);
+    int64_t ntiles = 0;
+    const int tw = batch_tile_w(), th = batch_tile_h();
+    for (int i = 0; i < n; ++i) {
+        const int t = ((items[i].nx + tw - 1) / tw) * ((items[i].ny + th - 1) / th);
+        b->tiles.push_back(t);
+        ntiles += t;
+    }
+    if (ntiles > 0x7fffffff) e = hipErrorInvalidValue;
+    b->work_cap = (int)ntiles;
+    if (e == hipSuccess) e = hipMalloc(&b->work, sizeof(int2) * (size_t)ntiles);
+    if (e != hipSuccess) {
+        int rc = hip_err(e);
+        batch_release(b);
+        return rc;
+    }
+    std::vector<unsigned char> desc(batch_item_bytes(b->precision) * n);
+    for (int i = 0; i < n; ++i) {
+        char* base = (char*)b->pool + off[i];
+        const size_t half = (sc_lbm_state_bytes(&items[i]) + 255) / 256 * 256;
+        sc_lbm* h = nullptr;
+        int rc = sc_lbm_create(&items[i], rho_init ? rho_init[i] : nullptr, base, base + half, b->stream, &h);
+        if (rc != SC_OK) {
+            batch_release(b);
+            return rc;
+        }
+        b->items.push_back(h);
+        batch_fill_item(desc.data() + batch_item_bytes(b->precision) * i, b->precision, base, base + half,
+                        items[i].nx, items[i].ny, items[i].order, items[i].G * items[i].c0, items[i].tau);
+    }
+    b->active.assign(n, 1);
+    b->conv_by.assign(n, 0);
+    fill_args(b->items[0], b->cf);
+    fill_args(b->items[0], b->cd);
+    e = hipMemcpyAsync(b->desc, desc.data(), desc.size(), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    int rc = hip_err(e);
+    if (rc == SC_OK) rc = batch_rebuild_work(b);
+    if (rc != SC_OK) {
+        batch_release(b);
+        return rc;
+    }
+    *out = b;
+    return SC_OK;
+}
+
+extern "C" int sc_lbm_batch_step(sc_lbm_batch* b, int64_t max_steps, double tol, int64_t* steps_done)
+{
+    if (!b || max_steps < 0 || !(tol >= 0.0)) return SC_E_INVAL;
+    const int64_t start = b->step;
+    int rc = SC_OK;
+    if (tol == 0.0) {
+        rc = hip_err(batch_run(b, max_steps));
+        if (steps_done) *steps_done = b->step - start;
+        return rc;
+    }
+    const int64_t K = b->items[0]->p.obs_every;
+    int64_t left = max_steps;
+    while (left > 0 && b->nwork > 0) {
+        const int64_t chunk = left < K ? left : K;
+        rc = hip_err(batch_run(b, chunk));
+        if (rc != SC_OK) break;
+        left -= chunk;
+        bool changed = false;
+        for (int i = 0; i < b->n; ++i) {
+            if (!b->active[i]) continue;
+            sc_lbm* h = b->items[i];
+            sc_lbm_obs o;
+            rc = observe_core(h, &o);
+            if (rc != SC_OK) break;
+            int by = 0;
+            if (o.nonfinite) {
+                by = -1;
+            } else if (o.d_max_u >= 0 && o.d_max_u < tol) {
+                by = 1;
+            } else if (h->p.precision == SC_FP32_SHIFTED && o.d_max_u >= 0 &&
+                       o.d_max_u <= 4.0 * o.max_u * 1.1920928955078125e-7) {
+                if (++h->fp32_hits >= 10) by = 2;
+            } else {
+                h->fp32_hits = 0;
+            }
+            h->last_max_u = o.max_u;
+            if (by != 0) {
+                b->active[i] = 0;
+                b->conv_by[i] = by;
+                changed = true;
+            }
+        }
+        if (rc != SC_OK) break;
+        if (changed) {
+            rc = batch_rebuild_work(b);
+            if (rc != SC_OK) break;
+        }
+    }
+    if (steps_done) *steps_done = b->step - start;
+    return rc;
+}
+
+extern "C" int sc_lbm_batch_observe(sc_lbm_batch* b, int32_t item, sc_lbm_obs* obs, double* rho_out,
+                                    double* u_out)
+{
+    if (!b || item < 0 || item >= b->n) return SC_E_INVAL;
+    int rc = sc_lbm_observe(b->items[item], obs, rho_out, u_out, nullptr);
+    if (obs) {
+        obs->converged_by = b->conv_by[item] > 0 ? b->conv_by[item] : 0;
+        if (b->conv_by[item] < 0) obs->status = SC_E_NONFINITE;
+    }
+    return rc;
+}
+
+extern "C" int sc_lbm_batch_status(sc_lbm_batch* b, int32_t item, int64_t* steps, int32_t* converged_by)
+{
+    if (!b || item < 0 || item >= b->n) return SC_E_INVAL;
+    if (steps) *steps = b->items[item]->step;
+    if (converged_by) *converged_by = b->conv_by[item];
+    return SC_OK;
+}
+
+extern "C" int32_t sc_lbm_batch_active(sc_lbm_batch* b)
+{
+    if (!b) return 0;
+    int32_t k = 0;
+    for (int v : b->active) k += v;
+    return k;
+}
+
+extern "C" void sc_lbm_batch_destroy(sc_lbm_batch* b)
+{
+    if (!b) return;
+    hipStreamSynchronize(b->stream);
+    batch_release(b);
 }

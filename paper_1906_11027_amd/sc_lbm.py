@@ -61,6 +61,8 @@ EXPORTS = [
     "sc_lbm_force", "sc_lbm_observe", "sc_lbm_set_state", "sc_lbm_state_ptr",
     "sc_lbm_variant_name", "sc_lbm_num_variants", "sc_lbm_destroy", "sc_lbm_strerror",
     "sc_lbm_last_error_detail", "sc_lbm_stream",
+    "sc_lbm_batch_create", "sc_lbm_batch_step", "sc_lbm_batch_observe", "sc_lbm_batch_status",
+    "sc_lbm_batch_active", "sc_lbm_batch_destroy",
 ]
 
 #: velocity order of the state buffers (include/sc_lbm.h)
@@ -116,6 +118,18 @@ def lib():
     L.sc_lbm_destroy.restype = None
     L.sc_lbm_strerror.argtypes = [ctypes.c_int]
     L.sc_lbm_strerror.restype = ctypes.c_char_p
+    L.sc_lbm_batch_create.argtypes = [P(sc_lbm_params), ctypes.c_int32, P(dp), vp, P(vp)]
+    L.sc_lbm_batch_create.restype = ctypes.c_int
+    L.sc_lbm_batch_step.argtypes = [vp, ctypes.c_int64, ctypes.c_double, P(ctypes.c_int64)]
+    L.sc_lbm_batch_step.restype = ctypes.c_int
+    L.sc_lbm_batch_observe.argtypes = [vp, ctypes.c_int32, P(sc_lbm_obs), dp, dp]
+    L.sc_lbm_batch_observe.restype = ctypes.c_int
+    L.sc_lbm_batch_status.argtypes = [vp, ctypes.c_int32, P(ctypes.c_int64), P(ctypes.c_int32)]
+    L.sc_lbm_batch_status.restype = ctypes.c_int
+    L.sc_lbm_batch_active.argtypes = [vp]
+    L.sc_lbm_batch_active.restype = ctypes.c_int32
+    L.sc_lbm_batch_destroy.argtypes = [vp]
+    L.sc_lbm_batch_destroy.restype = None
     L.sc_lbm_stream.argtypes = [vp]
     L.sc_lbm_stream.restype = vp
     L.sc_lbm_last_error_detail.argtypes = []
@@ -318,3 +332,111 @@ class Sim:
     @property
     def variant(self):
         return sc_lbm_variant_name(self.h)
+
+
+# ---------------------------------------------------------------------------
+# batched sweeps
+# ---------------------------------------------------------------------------
+
+def sc_lbm_batch_create(params, rho_inits=None, stream=None):
+    n = len(params)
+    arr = (sc_lbm_params * n)(*params)
+    keep = None
+    ptrs = None
+    if rho_inits is not None:
+        keep = [np.ascontiguousarray(r, dtype=np.float64) for r in rho_inits]
+        ptrs = (ctypes.POINTER(ctypes.c_double) * n)(*[_dptr(r) for r in keep])
+    h = ctypes.c_void_p()
+    rc = lib().sc_lbm_batch_create(arr, n, ptrs, stream, ctypes.byref(h))
+    _check(rc, "sc_lbm_batch_create")
+    return h.value
+
+
+def sc_lbm_batch_step(h, max_steps, tol=0.0):
+    done = ctypes.c_int64(0)
+    rc = lib().sc_lbm_batch_step(h, int(max_steps), float(tol), ctypes.byref(done))
+    return rc, done.value
+
+
+def sc_lbm_batch_observe(h, item, rho_out=None, u_out=None):
+    o = sc_lbm_obs()
+    rc = lib().sc_lbm_batch_observe(h, item, ctypes.byref(o), _dptr(rho_out), _dptr(u_out))
+    if rc not in (SC_OK, SC_E_NONFINITE):
+        raise ScError(rc, "sc_lbm_batch_observe")
+    return rc, o
+
+
+def sc_lbm_batch_status(h, item):
+    st, by = ctypes.c_int64(), ctypes.c_int32()
+    _check(lib().sc_lbm_batch_status(h, item, ctypes.byref(st), ctypes.byref(by)), "sc_lbm_batch_status")
+    return st.value, by.value
+
+
+def sc_lbm_batch_active(h):
+    return lib().sc_lbm_batch_active(h)
+
+
+def sc_lbm_batch_destroy(h):
+    lib().sc_lbm_batch_destroy(h)
+
+
+class Batch:
+    """Many D2Q9 droplets advanced together (one launch per step).
+
+    items: list of dicts with keys rho0 (array [x, y]) and any make_params
+    keyword (order, G, tau, c0, ...).  Shared keywords go in **common."""
+
+    def __init__(self, items, stream=None, **common):
+        self.shapes = [np.asarray(it["rho0"]).shape for it in items]
+        params, rhos = [], []
+        for it in items:
+            kw = dict(common)
+            kw.update({k: v for k, v in it.items() if k != "rho0"})
+            rho0 = np.asarray(it["rho0"], dtype=np.float64)
+            params.append(make_params("D2Q9", rho0.shape, **kw))
+            rhos.append(np.ascontiguousarray(rho0.transpose()).ravel())
+        if stream is None:
+            try:
+                import torch
+                if torch.cuda.is_available():
+                    stream = torch.cuda.current_stream()
+            except ImportError:
+                pass
+        if stream is not None and hasattr(stream, "cuda_stream"):
+            stream = stream.cuda_stream
+        self.n = len(items)
+        self.h = sc_lbm_batch_create(params, rhos, stream or None)
+
+    def close(self):
+        if getattr(self, "h", None):
+            sc_lbm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def step(self, n, tol=0.0):
+        rc, done = sc_lbm_batch_step(self.h, n, tol)
+        if rc not in (SC_OK, SC_E_NONFINITE):
+            raise ScError(rc, "sc_lbm_batch_step")
+        return rc, done
+
+    def observe(self, item, fields=True):
+        shape = self.shapes[item]
+        nn = int(np.prod(shape))
+        rho = np.zeros(nn) if fields else None
+        u = np.zeros(2 * nn) if fields else None
+        rc, o = sc_lbm_batch_observe(self.h, item, rho, u)
+        out = {"obs": o.as_dict(), "rc": rc}
+        if fields:
+            un = lambda a: a.reshape(shape[::-1]).transpose()
+            out["rho"] = un(rho)
+            out["u"] = np.stack([un(u[:nn]), un(u[nn:])])
+        return out
+
+    def status(self, item):
+        return sc_lbm_batch_status(self.h, item)
+
+    @property
+    def active(self):
+        return sc_lbm_batch_active(self.h)

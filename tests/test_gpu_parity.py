@@ -289,3 +289,63 @@ def test_config1_long_horizon_observables(order):
     say("E%d 1e4 steps fp64 pointwise rho err %.2e" % (order, er))
     assert er <= 1e-11
     s64.close()
+
+
+# ------------------------------------------------------------ batches -----
+
+def _batch_items():
+    from workload import sweep_items
+    its = sweep_items(6, seed=11, side_range=(20, 70))
+    out = []
+    for k, it in enumerate(its):
+        side = it["side"]
+        shape = (side, side - 3 * k)          # ragged, non-square grids
+        out.append({"rho0": droplet_rho(shape, min(it["R"], min(shape) // 3), seed=it["seed"]),
+                    "order": it["order"], "G": it["G"], "tau": it["tau"]})
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_matches_oracle_and_single(prec):
+    from paper_1906_11027_amd import Batch
+    items = _batch_items()
+    say("batch items:", [(it["rho0"].shape, it["order"], round(it["G"], 3), it["tau"]) for it in items])
+    bt = Batch(items, precision=prec)
+    bt.step(60)
+    for k, it in enumerate(items):
+        orc = O.Oracle(it["rho0"], "D2Q9", order=it["order"], G=it["G"], tau=it["tau"]).step(60)
+        got, ref = bt.observe(k), orc.fields()
+        er = rel_err(got["rho"], ref["rho"])
+        eu = float(np.max(np.abs(got["u"] - ref["u"])) / max(np.max(np.abs(ref["u"])), 1e-12))
+        say("batch item %d %s: rho %.2e u %.2e" % (k, it["rho0"].shape, er, eu))
+        tr, tu = TOL[prec]
+        assert er <= tr and eu <= tu, (k, er, eu)
+        single = Sim(it["rho0"], "D2Q9", order=it["order"], G=it["G"], tau=it["tau"], precision=prec)
+        single.step(60)
+        sg = single.observe()
+        assert np.max(np.abs(sg["rho"] - got["rho"])) <= (1e-6 if prec == "fp32" else 1e-13)
+        single.close()
+    bt.close()
+
+
+def test_batch_convergence_and_quarantine():
+    from paper_1906_11027_amd import Batch
+    items = [{"rho0": droplet_rho((40, 40), 10, seed=1), "order": 4},
+             {"rho0": droplet_rho((48, 36), 9, seed=2), "order": 8, "tau": 0.8},
+             # far past the stable range: diverges and must be quarantined
+             {"rho0": droplet_rho((32, 32), 8, seed=3), "order": 4, "G": -30.0, "tau": 0.51}]
+    bt = Batch(items, obs_every=50)
+    rc, done = bt.step(200000, tol=1e-7)
+    st = [bt.status(k) for k in range(3)]
+    say("batch status:", st, "steps", done)
+    assert bt.active == 0
+    assert st[0][1] in (1, 2) and st[1][1] in (1, 2)
+    assert st[2][1] == -1
+    # retired items keep their state: a converged item matches a single run
+    single = Sim(items[0]["rho0"], "D2Q9", order=4)
+    single.step(st[0][0])
+    a = single.observe()["rho"]
+    b = bt.observe(0)["rho"]
+    assert np.max(np.abs(a - b)) < 1e-6
+    single.close()
+    bt.close()
