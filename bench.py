@@ -63,7 +63,13 @@ def measure(name, steps, warmup, kernel_launches=50):
     from paper_1906_11027_amd import Sim
     from workload import droplet_rho
 
+    from paper_1906_11027_amd import sc_lbm as B
+
     w = WORKLOADS[name]
+    # pick the launch shape by timing every candidate (cached for variant -1)
+    tuned = B.sc_lbm_autotune(B.make_params(w["lattice"], w["shape"], order=w["order"],
+                                            collision=w["collision"]), steps=20)
+    log("autotune %s: variant %d, %.4f ms/step" % (name, tuned[0], tuned[1]))
     rho0 = droplet_rho(w["shape"], w["R"], seed=w["seed"])
     stream = torch.cuda.Stream()
     sim = Sim(rho0, w["lattice"], order=w["order"], collision=w["collision"], precision="fp32",

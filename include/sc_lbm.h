@@ -162,6 +162,13 @@ void* sc_lbm_state_ptr(sc_lbm* h);
 /* The hipStream_t the handle enqueues on (the caller's, or its own). */
 void* sc_lbm_stream(sc_lbm* h);
 
+/* Time every launch shape of the fused step on *p's lattice, order,
+ * precision, collision and grid for `steps` steps (state rho = 1), and
+ * remember the fastest: later sc_lbm_create calls with variant = -1 and the
+ * same problem shape use it.  With SC_LBM_TUNE_CACHE set to a file path the
+ * choices persist across processes.  Outputs are nullable. */
+int sc_lbm_autotune(const sc_lbm_params* p, int32_t steps, int32_t* best_variant, double* best_ms_per_step);
+
 /* Name of the launch shape in use and the number of shapes available for
  * this lattice (for tuning sweeps through sc_lbm_params.variant). */
 const char* sc_lbm_variant_name(const sc_lbm* h);
@@ -206,6 +213,61 @@ int sc_lbm_batch_status(sc_lbm_batch* b, int32_t item, int64_t* steps, int32_t* 
 int32_t sc_lbm_batch_active(sc_lbm_batch* b);
 
 void sc_lbm_batch_destroy(sc_lbm_batch* b);
+
+/* ---- learned warm start: network kernels -------------------------------- */
+/* Not part of the paper's method: a small convolutional net predicts the
+ * steady density of a droplet from its parameters so the iteration above
+ * starts closer to its fixed point (the iteration stays the judge of the
+ * steady state).  Every pointer below is DEVICE memory owned by the caller;
+ * every call is asynchronous on `stream` (a hipStream_t or NULL) and returns
+ * SC_OK, SC_E_INVAL (bad size or NULL pointer) or SC_E_DEVICE.
+ *
+ * Layout: activations NCHW float32 [batch][C][h][w]; weights [cout][cin][3][3]
+ * bfloat16 (stored as uint16) used in the products, FP32 accumulation;
+ * biases float32 [cout].  3x3 convolutions use circular padding:
+ *     out[b][co][y][x] = bias[co] + sum_ci sum_{dy,dx in -1..1}
+ *                        w[co][ci][dy+1][dx+1] in[b][ci][(y+dy) mod h][(x+dx) mod w].
+ * Supported channel counts: cin <= 32, cout in {1, 32}; batch <= 65535. */
+int sc_nn_conv3x3_fwd(const float* in, const uint16_t* w, const float* bias, float* out, int32_t batch,
+                      int32_t cin, int32_t cout, int32_t h, int32_t wd, void* stream);
+
+/* Gradient w.r.t. the input (cin must be 32): gin = conv(gout, w flipped and
+ * transposed); wt_scratch holds cin*cout*9 bfloat16. */
+int sc_nn_conv3x3_bwd_data(const float* gout, const uint16_t* w, uint16_t* wt_scratch, float* gin, int32_t batch,
+                           int32_t cin, int32_t cout, int32_t h, int32_t wd, void* stream);
+
+/* Gradients w.r.t. the weights (gw [cout][cin][9] float32) and biases
+ * (gbias [cout]) summed over the batch, through nblk per-block partial rows
+ * in partial_scratch (sc_nn_bwd_weight_scratch_floats(cin, cout, nblk)
+ * floats); the partials are summed in a fixed order (deterministic). */
+int32_t sc_nn_bwd_weight_scratch_floats(int32_t cin, int32_t cout, int32_t nblk);
+int sc_nn_conv3x3_bwd_weight(const float* in, const float* gout, float* partial_scratch, int32_t nblk, float* gw,
+                             float* gbias, int32_t batch, int32_t cin, int32_t cout, int32_t h, int32_t wd,
+                             void* stream);
+
+/* x <- tanh(x);  g <- g (1 - y^2) with y = tanh output. */
+int sc_nn_tanh_fwd(float* x, int64_t n, void* stream);
+int sc_nn_tanh_bwd(const float* y, float* g, int64_t n, void* stream);
+
+/* Mean squared error over n values: grad (nullable) <- 2 (out - tgt) / n and
+ * partial_scratch[k] <- sum over block k's share of (out - tgt)^2 (nblk
+ * doubles; the loss is their sum / n). */
+int sc_nn_mse(const float* out, const float* tgt, float* grad, double* partial_scratch, int32_t nblk, int64_t n,
+              void* stream);
+
+/* Adam step t >= 1 on n FP32 parameters p with gradient g and moments m, v;
+ * writes the bfloat16 copy p_bf16 when non-NULL. */
+int sc_nn_adam(float* p, const float* g, float* m, float* v, uint16_t* p_bf16, int64_t n, float lr, float beta1,
+               float beta2, float eps, int32_t t, void* stream);
+
+/* y <- bfloat16(x), round to nearest even. */
+int sc_nn_to_bf16(const float* x, uint16_t* y, int64_t n, void* stream);
+
+/* Network input: out [batch][5][h][w] with channel 0 = distance of the node to
+ * the domain centre (w/2, h/2) divided by scale_r and channels 1..4 the four
+ * per-image values params[batch][4] broadcast over the grid. */
+int sc_nn_features(const float* params, float* out, int32_t batch, int32_t h, int32_t wd, float scale_r,
+                   void* stream);
 
 /* Detail of the last HIP failure seen by this host thread (which call, the
  * HIP error string and code); "" if none.  Valid until the next failure. */

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -165,10 +166,86 @@ static void fill_args(sc_lbm* h, StepArgs<T>& a)
     a.s_ghost = (T)p.s_ghost;
 }
 
+// ---- launch-shape autotuning --------------------------------------------
+// Tuned choices are kept per (lattice, order, precision, collision, grid) in
+// process memory and, when SC_LBM_TUNE_CACHE names a file, in that file (one
+// "lattice order precision collision nx ny nz variant ms" line per entry).
+struct TuneKey {
+    int lattice, order, precision, collision, nx, ny, nz;
+    bool operator==(const TuneKey& o) const
+    {
+        return lattice == o.lattice && order == o.order && precision == o.precision && collision == o.collision &&
+               nx == o.nx && ny == o.ny && nz == o.nz;
+    }
+};
+struct TuneEntry {
+    TuneKey k;
+    int variant;
+    double ms;
+};
+static std::mutex g_tune_mu;
+static std::vector<TuneEntry> g_tune;
+static bool g_tune_loaded = false;
+
+static TuneKey tune_key(const sc_lbm_params& p)
+{
+    return TuneKey{p.lattice, p.order, p.precision, p.collision, p.nx, p.ny, p.nz};
+}
+
+static void tune_load_locked()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = std::getenv("SC_LBM_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    TuneEntry e;
+    while (std::fscanf(f, "%d %d %d %d %d %d %d %d %lf", &e.k.lattice, &e.k.order, &e.k.precision, &e.k.collision,
+                       &e.k.nx, &e.k.ny, &e.k.nz, &e.variant, &e.ms) == 9)
+        g_tune.push_back(e);
+    std::fclose(f);
+}
+
+static int tune_lookup(const sc_lbm_params& p)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    const TuneKey k = tune_key(p);
+    for (const TuneEntry& e : g_tune)
+        if (e.k == k) return e.variant;
+    return -1;
+}
+
+static void tune_store(const sc_lbm_params& p, int variant, double ms)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    const TuneKey k = tune_key(p);
+    bool found = false;
+    for (TuneEntry& e : g_tune)
+        if (e.k == k) {
+            e.variant = variant;
+            e.ms = ms;
+            found = true;
+        }
+    if (!found) g_tune.push_back(TuneEntry{k, variant, ms});
+    const char* path = std::getenv("SC_LBM_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "w");
+    if (!f) return;
+    for (const TuneEntry& e : g_tune)
+        std::fprintf(f, "%d %d %d %d %d %d %d %d %.6g\n", e.k.lattice, e.k.order, e.k.precision, e.k.collision,
+                     e.k.nx, e.k.ny, e.k.nz, e.variant, e.ms);
+    std::fclose(f);
+}
+
 static int auto_variant(const sc_lbm_params& p, int64_t n)
 {
+    const int tuned = tune_lookup(p);
+    if (tuned >= 0) return tuned;
     if (p.lattice == SC_D2Q9) return n < (int64_t)1 << 20 ? 2 : 0;
-    return 0;
+    return n < (int64_t)1 << 22 ? 5 : 5;
 }
 
 static void release(sc_lbm* h)
@@ -831,4 +908,63 @@ extern "C" void sc_lbm_batch_destroy(sc_lbm_batch* b)
     if (!b) return;
     hipStreamSynchronize(b->stream);
     batch_release(b);
+}
+
+// =========================================================================
+// Autotuner: time every launch shape on the caller's problem statement.
+// =========================================================================
+extern "C" int sc_lbm_autotune(const sc_lbm_params* p, int32_t steps, int32_t* best_variant, double* best_ms)
+{
+    int rc = validate(p);
+    if (rc != SC_OK) return rc;
+    if (steps < 1) return SC_E_INVAL;
+    const int nv = p->lattice == SC_D2Q9 ? num_variants_d2q9() : num_variants_d3q19();
+    int best = -1;
+    double bms = 1e300;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        if (e0) hipEventDestroy(e0);
+        return hip_err(e);
+    }
+    // one state pair for all candidates
+    sc_lbm_params q = *p;
+    q.variant = 0;
+    sc_lbm* h = nullptr;
+    rc = sc_lbm_create(&q, nullptr, nullptr, nullptr, nullptr, &h);
+    if (rc == SC_OK) {
+        for (int v = 0; v < nv && rc == SC_OK; ++v) {
+            h->variant = v;
+            for (int k = 0; k < 2; ++k)
+                if (h->gexec[k]) {
+                    hipGraphExecDestroy(h->gexec[k]);
+                    h->gexec[k] = nullptr;
+                }
+            e = run_steps(h, 2);
+            if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+            if (e == hipSuccess) e = run_steps(h, steps);
+            if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                rc = hip_err(e);
+                break;
+            }
+            const double per = (double)ms / steps;
+            if (per < bms) {
+                bms = per;
+                best = v;
+            }
+        }
+        sc_lbm_destroy(h);
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc != SC_OK) return rc;
+    tune_store(*p, best, bms);
+    if (best_variant) *best_variant = best;
+    if (best_ms) *best_ms = bms;
+    return SC_OK;
 }

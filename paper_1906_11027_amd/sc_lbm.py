@@ -62,7 +62,10 @@ EXPORTS = [
     "sc_lbm_variant_name", "sc_lbm_num_variants", "sc_lbm_destroy", "sc_lbm_strerror",
     "sc_lbm_last_error_detail", "sc_lbm_stream",
     "sc_lbm_batch_create", "sc_lbm_batch_step", "sc_lbm_batch_observe", "sc_lbm_batch_status",
-    "sc_lbm_batch_active", "sc_lbm_batch_destroy",
+    "sc_lbm_batch_active", "sc_lbm_batch_destroy", "sc_lbm_autotune",
+    "sc_nn_conv3x3_fwd", "sc_nn_conv3x3_bwd_data", "sc_nn_bwd_weight_scratch_floats",
+    "sc_nn_conv3x3_bwd_weight", "sc_nn_tanh_fwd", "sc_nn_tanh_bwd", "sc_nn_mse", "sc_nn_adam",
+    "sc_nn_to_bf16", "sc_nn_features",
 ]
 
 #: velocity order of the state buffers (include/sc_lbm.h)
@@ -130,6 +133,23 @@ def lib():
     L.sc_lbm_batch_active.restype = ctypes.c_int32
     L.sc_lbm_batch_destroy.argtypes = [vp]
     L.sc_lbm_batch_destroy.restype = None
+    L.sc_lbm_autotune.argtypes = [P(sc_lbm_params), ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_double)]
+    L.sc_lbm_autotune.restype = ctypes.c_int
+    i32, i64, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+    L.sc_nn_conv3x3_fwd.argtypes = [vp, vp, vp, vp, i32, i32, i32, i32, i32, vp]
+    L.sc_nn_conv3x3_bwd_data.argtypes = [vp, vp, vp, vp, i32, i32, i32, i32, i32, vp]
+    L.sc_nn_bwd_weight_scratch_floats.argtypes = [i32, i32, i32]
+    L.sc_nn_bwd_weight_scratch_floats.restype = i32
+    L.sc_nn_conv3x3_bwd_weight.argtypes = [vp, vp, vp, i32, vp, vp, i32, i32, i32, i32, i32, vp]
+    L.sc_nn_tanh_fwd.argtypes = [vp, i64, vp]
+    L.sc_nn_tanh_bwd.argtypes = [vp, vp, i64, vp]
+    L.sc_nn_mse.argtypes = [vp, vp, vp, vp, i32, i64, vp]
+    L.sc_nn_adam.argtypes = [vp, vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp]
+    L.sc_nn_to_bf16.argtypes = [vp, vp, i64, vp]
+    L.sc_nn_features.argtypes = [vp, vp, i32, i32, i32, f32, vp]
+    for name in ("sc_nn_conv3x3_fwd", "sc_nn_conv3x3_bwd_data", "sc_nn_conv3x3_bwd_weight", "sc_nn_tanh_fwd",
+                 "sc_nn_tanh_bwd", "sc_nn_mse", "sc_nn_adam", "sc_nn_to_bf16", "sc_nn_features"):
+        getattr(L, name).restype = ctypes.c_int
     L.sc_lbm_stream.argtypes = [vp]
     L.sc_lbm_stream.restype = vp
     L.sc_lbm_last_error_detail.argtypes = []
@@ -209,6 +229,13 @@ def sc_lbm_set_state(h, f_in, step):
 
 def sc_lbm_state_ptr(h):
     return lib().sc_lbm_state_ptr(h)
+
+
+def sc_lbm_autotune(p, steps=20):
+    """Returns (best variant, ms per step) and records the choice."""
+    v, ms = ctypes.c_int32(), ctypes.c_double()
+    _check(lib().sc_lbm_autotune(ctypes.byref(p), int(steps), ctypes.byref(v), ctypes.byref(ms)), "sc_lbm_autotune")
+    return v.value, ms.value
 
 
 def sc_lbm_variant_name(h):

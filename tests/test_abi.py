@@ -17,7 +17,7 @@ HEADER = os.path.join(ROOT, "include", "sc_lbm.h")
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(sc_lbm_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(sc_(?:lbm|nn)_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_lists_match_binding():

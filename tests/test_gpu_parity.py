@@ -349,3 +349,17 @@ def test_batch_convergence_and_quarantine():
     assert np.max(np.abs(a - b)) < 1e-6
     single.close()
     bt.close()
+
+
+def test_autotune_picks_a_variant_and_is_used():
+    p = B.make_params("D2Q9", (96, 80), order=6)
+    v, ms = B.sc_lbm_autotune(p, steps=10)
+    assert 0 <= v < B.sc_lbm_num_variants(B.SC_D2Q9) and ms > 0
+    sim = Sim(droplet_rho((96, 80), 20, seed=1), "D2Q9", order=6)
+    names = []
+    for k in range(B.sc_lbm_num_variants(B.SC_D2Q9)):
+        s2 = Sim(np.ones((96, 80)), "D2Q9", order=6, variant=k)
+        names.append(s2.variant)
+        s2.close()
+    assert sim.variant == names[v]
+    sim.close()
