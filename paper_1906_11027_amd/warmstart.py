@@ -4,10 +4,13 @@ A five-layer 3x3 convolutional net (5 -> 32 -> 32 -> 32 -> 32 -> 1 channels,
 tanh between layers, circular padding, bfloat16 weights with FP32
 accumulation) maps the droplet parameters (R, G, tau, stencil order,
 broadcast as channels) plus the radial coordinate grid to the steady density
-field.  Its prediction, shifted to the mass of the usual tanh start (mass is
-conserved by the step, so the steady state is fixed by it), replaces the
-tanh profile as the initial condition; the lattice Boltzmann iteration still
-runs to its own steady state and remains the judge of it.
+field.  It is trained on the residual between the steady field and the usual
+tanh start (scaled by TARGET_SCALE), so an untrained net reproduces the tanh
+start and training moves it towards the steady state.  The prediction
+(tanh start + residual), clamped to a physical range and shifted to the mass
+of the tanh start (mass is conserved by the step, so the steady state is
+fixed by it), becomes the initial condition; the lattice Boltzmann iteration
+still runs to its own steady state and remains the judge of it.
 
 Every arithmetic step runs in the library's kernels (sc_nn_* for the net,
 sc_lbm_batch_* for the data); torch only allocates device memory and
@@ -21,12 +24,16 @@ import numpy as np
 from . import sc_lbm as B
 
 CHANNELS = [5, 32, 32, 32, 32, 1]
-SCALE_R = 100.0
+# radius and radial coordinate in units of ten nodes (a few interface widths),
+# so r - R is of order one across the interface
+SCALE_R = 10.0
+RHO_CLAMP = (0.05, 2.5)
+TARGET_SCALE = 10.0
 
 
 def normalise(R, G, tau, order):
-    """Parameters as the net sees them (roughly unit range)."""
-    return [R / 100.0, (G + 5.0) / 0.5, (tau - 1.0) / 0.2, (order - 7.0) / 3.0]
+    """Parameters as the net sees them (roughly unit range near the interface)."""
+    return [R / SCALE_R, (G + 5.0) / 0.5, (tau - 1.0) / 0.2, (order - 7.0) / 3.0]
 
 
 def _bf16_round(a):
@@ -203,5 +210,100 @@ def predict(net, inputs):
 
 
 def mass_project(rho_pred, rho_ref):
-    """Shift the prediction uniformly to the mass of rho_ref."""
-    return rho_pred + (rho_ref.sum() - rho_pred.sum()) / rho_pred.size
+    """Clamp the prediction to a physical density range, then shift it
+    uniformly to the mass of rho_ref."""
+    r = np.clip(rho_pred, RHO_CLAMP[0], RHO_CLAMP[1])
+    return r + (rho_ref.sum() - r.sum()) / r.size
+
+
+def make_dataset(n_train, n_test, side, tol, max_steps, obs_every, chunk, seed, log=print):
+    """Steady states of the sweep's items (side fixed) from the tanh start."""
+    from workload import droplet_rho, sweep_items
+    items = sweep_items(n_train + n_test, seed=seed, sides=side)
+    fields, steps, conv = [], [], []
+    t_gen = 0.0
+    for s in range(0, len(items), chunk):
+        part = [{"rho0": droplet_rho((side, side), it["R"], seed=it["seed"]), "order": it["order"], "G": it["G"],
+                 "tau": it["tau"]} for it in items[s:s + chunk]]
+        f, st, by, wall = steady_states(part, tol=tol, max_steps=max_steps, obs_every=obs_every)
+        fields += f
+        steps += st
+        conv += by
+        t_gen += wall
+        log("steady states %d/%d (%.1f s)" % (min(s + chunk, len(items)), len(items), t_gen))
+    return {"items": items, "fields": fields, "steps": steps, "conv": conv, "gen_wall_s": t_gen,
+            "n_train": n_train, "side": side, "tol": tol, "max_steps": max_steps, "obs_every": obs_every}
+
+
+def evaluate(ds, epochs=20, batch=16, lr=2e-3, fp64_baseline=8, seed=2026, log=print):
+    """Train on the dataset's training items, then compare steps and wall time
+    to steady state on its held-out items: tanh start (batched FP32), learned
+    start (batched FP32, inference included), plain per-droplet FP64 runs."""
+    from workload import droplet_rho
+    torch = __import__("torch")
+    items, fields, conv = ds["items"], ds["fields"], ds["conv"]
+    side, tol, max_steps, obs_every = ds["side"], ds["tol"], ds["max_steps"], ds["obs_every"]
+    n_train = ds["n_train"]
+    rho0 = lambda it: droplet_rho((side, side), it["R"], seed=it["seed"])  # noqa: E731
+    base = lambda it: droplet_rho((side, side), it["R"])  # noqa: E731  tanh start without jitter
+    ok = [k for k in range(len(items)) if conv[k] > 0]
+    train_idx = [k for k in ok if k < n_train]
+    test_idx = [k for k in ok if k >= n_train]
+    inputs = [normalise(it["R"], it["G"], it["tau"], it["order"]) for it in items]
+    resid = {k: TARGET_SCALE * (fields[k] - base(items[k])) for k in ok}
+    net = WarmStartNet(side, side, batch, seed=seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = train(net, [inputs[k] for k in train_idx], [resid[k] for k in train_idx], epochs=epochs, lr=lr,
+                 log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    pred = [base(items[k]) + r / TARGET_SCALE
+            for k, r in zip(test_idx, predict(net, [inputs[k] for k in test_idx]))]
+    warm_items = [{"rho0": mass_project(p, rho0(items[k])), "order": items[k]["order"], "G": items[k]["G"],
+                   "tau": items[k]["tau"]} for k, p in zip(test_idx, pred)]
+    torch.cuda.synchronize()
+    t_inf = time.perf_counter() - t0
+    wf, wst, wby, t_warm = steady_states(warm_items, tol=tol, max_steps=max_steps, obs_every=obs_every)
+    cold_items = [{"rho0": rho0(items[k]), "order": items[k]["order"], "G": items[k]["G"],
+                   "tau": items[k]["tau"]} for k in test_idx]
+    cf, cst, cby, t_cold = steady_states(cold_items, tol=tol, max_steps=max_steps, obs_every=obs_every)
+    t0 = time.perf_counter()
+    fp64_steps = []
+    for k in test_idx[:fp64_baseline]:
+        it = items[k]
+        sim = B.Sim(rho0(it), "D2Q9", order=it["order"], G=it["G"], tau=it["tau"], precision="fp64",
+                    obs_every=obs_every)
+        rc, done = sim.step(max_steps, tol=tol)
+        fp64_steps.append(done)
+        sim.close()
+    torch.cuda.synchronize()
+    t_fp64 = time.perf_counter() - t0
+    nb = max(1, min(fp64_baseline, len(test_idx)))
+    nt = max(1, len(test_idx))
+    pred_err = [float(np.max(np.abs(p - fields[k])) / np.max(fields[k])) for k, p in zip(test_idx, pred)]
+    tanh_err = [float(np.max(np.abs(base(items[k]) - fields[k])) / np.max(fields[k])) for k in test_idx]
+    agree = [float(np.max(np.abs(a - b))) for a, b, x, y in zip(wf, cf, wby, cby) if x > 0 and y > 0]
+    return {
+        "n_train": len(train_idx), "n_test": len(test_idx), "diverged": int(sum(1 for c in conv if c < 0)),
+        "side": side, "tol": tol, "epochs": epochs, "lr": lr, "loss_first": hist[0], "loss_last": hist[-1],
+        "gen_wall_s": ds["gen_wall_s"], "train_wall_s": t_train, "inference_wall_s": t_inf,
+        "pred_max_rel_err_median": float(np.median(pred_err)),
+        "tanh_max_rel_err_median": float(np.median(tanh_err)),
+        "steps_tanh_mean": float(np.mean(cst)), "steps_warm_mean": float(np.mean(wst)),
+        "steps_ratio_median": float(np.median(np.array(wst) / np.maximum(np.array(cst), 1))),
+        "wall_tanh_batched_s_per_item": t_cold / nt,
+        "wall_warm_batched_s_per_item": (t_warm + t_inf) / nt,
+        "wall_fp64_per_droplet_s_per_item": t_fp64 / nb,
+        "fp64_steps_mean": float(np.mean(fp64_steps)) if fp64_steps else None,
+        "steady_fields_max_abs_diff_median": float(np.median(agree)) if agree else None,
+        "warm_converged": int(sum(1 for v in wby if v > 0)),
+    }
+
+
+def run_experiment(n_train=2000, n_test=64, side=256, tol=1e-8, epochs=20, batch=16, lr=2e-3,
+                   max_steps=150000, obs_every=200, chunk=64, fp64_baseline=8, seed=2026, log=print):
+    """Config-5 experiment: dataset from batched sweeps, then evaluate()."""
+    ds = make_dataset(n_train, n_test, side, tol, max_steps, obs_every, chunk, seed, log=log)
+    return evaluate(ds, epochs=epochs, batch=batch, lr=lr, fp64_baseline=fp64_baseline, seed=seed, log=log)
