@@ -41,26 +41,17 @@ k_d2q9_tile(StepArgs<T> a, int nbx)
     uint32_t xo[3];
     nbr_offsets<T>(x, nx, TS, xo);
 
-    T g[RPT][9];
-    T dr[RPT];
-    uint32_t own[RPT];
-#pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-        const int ly = ty * RPT + k;
-        const int yr = y0 + ly;
-        const int y = yr < ny ? yr : yr % ny;
-        uint32_t yo[3];
-        nbr_offsets<T>(y, ny, rowb, yo);
-        own[k] = yo[1] + xo[1];
-        pull_d2q9(a.fin, n, xo, yo, g[k]);
-        dr[k] = sum9(g[k]);
-        psi_s[(ly + R) * LW + tx + R] = psi_of(a.rho_ref + dr[k], a);
-    }
-
-    // halo ring: R rows on top and bottom (full width), R columns each side
+    // this thread's halo-ring nodes (R rows above and below at full width,
+    // R columns each side): coordinates first, so the ring pulls are issued
+    // together with the tile's own pulls
     constexpr int RING = LH * LW - TX * TY;
-    for (int i = tid; i < RING; i += NT) {
-        int lx, ly;
+    constexpr int RPERT = (RING + NT - 1) / NT;
+    int rl[RPERT];
+    uint32_t rxo[RPERT][3], ryo[RPERT][3];
+#pragma unroll
+    for (int q = 0; q < RPERT; ++q) {
+        const int i = tid + q * NT;
+        int lx = 0, ly = 0;
         if (i < R * LW) {
             ly = i / LW;
             lx = i - ly * LW;
@@ -68,19 +59,40 @@ k_d2q9_tile(StepArgs<T> a, int nbx)
             const int j = i - R * LW;
             ly = TY + R + j / LW;
             lx = j % LW;
-        } else {
+        } else if (i < RING) {
             const int j = i - 2 * R * LW;
             ly = R + j / (2 * R);
             const int c = j % (2 * R);
             lx = c < R ? c : TX + c;
         }
-        uint32_t hxo[3], hyo[3];
-        nbr_offsets<T>(wrap_any(x0 - R + lx, nx), nx, TS, hxo);
-        nbr_offsets<T>(wrap_any(y0 - R + ly, ny), ny, rowb, hyo);
-        T h[9];
-        pull_d2q9(a.fin, n, hxo, hyo, h);
-        psi_s[ly * LW + lx] = psi_of(a.rho_ref + sum9(h), a);
+        rl[q] = i < RING ? ly * LW + lx : -1;
+        nbr_offsets<T>(wrap_any(x0 - R + lx, nx), nx, TS, rxo[q]);
+        nbr_offsets<T>(wrap_any(y0 - R + ly, ny), ny, rowb, ryo[q]);
     }
+
+    T g[RPT][9];
+    T dr[RPT];
+    uint32_t own[RPT];
+    T h[RPERT][9];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int yr = y0 + ty * RPT + k;
+        uint32_t yo[3];
+        nbr_offsets<T>(yr < ny ? yr : yr % ny, ny, rowb, yo);
+        own[k] = yo[1] + xo[1];
+        pull_d2q9(a.fin, n, xo, yo, g[k]);
+    }
+#pragma unroll
+    for (int q = 0; q < RPERT; ++q)
+        if (rl[q] >= 0) pull_d2q9(a.fin, n, rxo[q], ryo[q], h[q]);
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        dr[k] = sum9(g[k]);
+        psi_s[(ty * RPT + k + R) * LW + tx + R] = psi_of(a.rho_ref + dr[k], a);
+    }
+#pragma unroll
+    for (int q = 0; q < RPERT; ++q)
+        if (rl[q] >= 0) psi_s[rl[q]] = psi_of(a.rho_ref + sum9(h[q]), a);
     __syncthreads();
 
 #pragma unroll

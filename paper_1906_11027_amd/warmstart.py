@@ -307,3 +307,27 @@ def run_experiment(n_train=2000, n_test=64, side=256, tol=1e-8, epochs=20, batch
     """Config-5 experiment: dataset from batched sweeps, then evaluate()."""
     ds = make_dataset(n_train, n_test, side, tol, max_steps, obs_every, chunk, seed, log=log)
     return evaluate(ds, epochs=epochs, batch=batch, lr=lr, fp64_baseline=fp64_baseline, seed=seed, log=log)
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+    import os
+    import sys
+
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    ap = argparse.ArgumentParser(description="learned warm start experiment (droplet sweep on side^2 grids)")
+    ap.add_argument("--n-train", type=int, default=2000)
+    ap.add_argument("--n-test", type=int, default=64)
+    ap.add_argument("--side", type=int, default=256)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    res = run_experiment(n_train=a.n_train, n_test=a.n_test, side=a.side, tol=a.tol, epochs=a.epochs, lr=a.lr,
+                         log=lambda m: print(m, flush=True))
+    print(json.dumps(res), flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(res, f, indent=1)
