@@ -144,6 +144,35 @@ def steady_droplet():
             "steps": done, "wall_s": wall, "max_u": ob["max_u"], "dp": ob["dp"], "rc": rc}
 
 
+def batched_sweep(steps=200):
+    """64 droplets drawn like the sweep configuration (sides 64..512, R, G,
+    tau, stencil order per item) advanced by one launch per step."""
+    import torch
+
+    from paper_1906_11027_amd import Batch
+    from workload import droplet_rho, sweep_items
+
+    its = sweep_items(64, seed=1906)
+    items = [{"rho0": droplet_rho((it["side"],) * 2, it["R"], seed=it["seed"]), "order": it["order"],
+              "G": it["G"], "tau": it["tau"]} for it in its]
+    nodes = sum(it["rho0"].size for it in items)
+    st = torch.cuda.Stream()
+    bt = Batch(items, stream=st)
+    bt.step(20)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    bt.step(steps)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    bt.close()
+    return {"workload": "64 D2Q9 droplets, sides U{64..512}, R, G, tau, order per item (PCG64 seed 1906), "
+                        "FP32, one launch per step", "nodes": nodes, "ms_per_step": ms,
+            "mlups": nodes / ms / 1e3, "achieved_gbs": nodes * 72 / ms / 1e6}
+
+
 def cpu_baseline(name, target_s=15.0):
     from oracle import oracle as O
     from workload import droplet_rho
@@ -204,6 +233,9 @@ def main():
         sd = steady_droplet()
         log("steady:", json.dumps(sd))
         extra["steady_droplet"] = sd
+        bs = batched_sweep()
+        log("batch:", json.dumps(bs))
+        extra["batched_sweep_64"] = bs
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(args.workload)

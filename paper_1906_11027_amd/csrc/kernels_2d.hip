@@ -131,7 +131,7 @@ k_d2q9_tile(StepArgs<T> a, int nbx)
 // unrolled by R + 2 so the register window is statically indexed.  Each
 // interior value is read from HBM once; the halo costs 2R columns per block
 // (same XCD, L2 hits) and 2R + 2 rows per H (neighbouring segment).
-template <typename T, int ORDER, int NT>
+template <typename T, int ORDER, int NT, int PF>
 __global__ void __launch_bounds__(NT)
 k_d2q9_march(StepArgs<T> a, int H, int nbx)
 {
@@ -139,7 +139,7 @@ k_d2q9_march(StepArgs<T> a, int H, int nbx)
     constexpr int R = ST::R;
     constexpr int TXO = NT - 2 * R;
     constexpr int NS = 2 * R + 2;
-    constexpr int W = R + 2;
+    constexpr int W = R + 1 + PF;   // R pending rows, the current row, PF rows in flight
     __shared__ T psi_s[NS * NT];
 
     const int nx = a.nx, ny = a.ny;
@@ -155,28 +155,30 @@ k_d2q9_march(StepArgs<T> a, int H, int nbx)
     const int nrows = H + 2 * R;
 
     T g[W][9];
-    int yl = wrap_any(y0 - R, ny);   // row being loaded
-    {
+    int yl = wrap_any(y0 - R, ny);   // last row whose load was issued
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {   // rows 0 .. PF-1
+        if (q) yl = yl == ny - 1 ? 0 : yl + 1;
         uint32_t yo[3];
         nbr_offsets<T>(yl, ny, rowb, yo);
-        pull_d2q9(a.fin, n, xo, yo, g[0]);
+        pull_d2q9(a.fin, n, xo, yo, g[q]);
     }
     for (int j0 = 0; j0 < nrows; j0 += W) {
 #pragma unroll
         for (int s = 0; s < W; ++s) {
             const int j = j0 + s;
             if (j < nrows) {   // uniform across the block
-                if (j + 1 < nrows) {
+                if (j + PF < nrows) {
                     yl = yl == ny - 1 ? 0 : yl + 1;
                     uint32_t yo[3];
                     nbr_offsets<T>(yl, ny, rowb, yo);
-                    pull_d2q9(a.fin, n, xo, yo, g[(s + 1) % W]);
+                    pull_d2q9(a.fin, n, xo, yo, g[(s + PF) % W]);
                 }
                 const T dr = sum9(g[s]);
                 psi_s[(j % NS) * NT + t] = psi_of(a.rho_ref + dr, a);
                 __syncthreads();
                 if (j >= 2 * R && interior) {
-                    const int sc = (s + 2) % W;         // slot of row j - R
+                    const int sc = (s + W - R) % W;     // slot of row j - R
                     const int yrel = j - 2 * R;
                     const int yr = y0 + yrel;
                     int sl[2 * R + 1];
@@ -212,7 +214,7 @@ struct Shape2D {
 };
 static const Shape2D kShapes2D[] = {
     {"tile64x16r4"}, {"tile64x8r2"}, {"tile32x8r1"}, {"tile64x4r1"},
-    {"march256h128"}, {"march256h64"}, {"march512h128"}, {"march256h256"},
+    {"march256h128"}, {"march256h128pf2"}, {"march512h128"}, {"march256h128pf3"}, {"march512h128pf2"},
 };
 constexpr int kNumShapes2D = sizeof(kShapes2D) / sizeof(kShapes2D[0]);
 
@@ -228,14 +230,14 @@ static hipError_t launch_tile(const StepArgs<T>& a, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename T, int ORDER, int NT>
+template <typename T, int ORDER, int NT, int PF>
 static hipError_t launch_march(const StepArgs<T>& a, int H, hipStream_t s)
 {
     constexpr int R = Stencil<2, ORDER>::R;
     constexpr int TXO = NT - 2 * R;
     if (H > a.ny) H = a.ny;
     const int nbx = (a.nx + TXO - 1) / TXO, nby = (a.ny + H - 1) / H;
-    hipLaunchKernelGGL((k_d2q9_march<T, ORDER, NT>), dim3(nbx * nby), dim3(NT), 0, s, a, H, nbx);
+    hipLaunchKernelGGL((k_d2q9_march<T, ORDER, NT, PF>), dim3(nbx * nby), dim3(NT), 0, s, a, H, nbx);
     return hipGetLastError();
 }
 
@@ -247,10 +249,11 @@ static hipError_t launch_order(const StepArgs<T>& a, int variant, hipStream_t s)
     case 1: return launch_tile<T, ORDER, 64, 8, 2>(a, s);
     case 2: return launch_tile<T, ORDER, 32, 8, 1>(a, s);
     case 3: return launch_tile<T, ORDER, 64, 4, 1>(a, s);
-    case 4: return launch_march<T, ORDER, 256>(a, 128, s);
-    case 5: return launch_march<T, ORDER, 256>(a, 64, s);
-    case 6: return launch_march<T, ORDER, 512>(a, 128, s);
-    case 7: return launch_march<T, ORDER, 256>(a, 256, s);
+    case 4: return launch_march<T, ORDER, 256, 1>(a, 128, s);
+    case 5: return launch_march<T, ORDER, 256, 2>(a, 128, s);
+    case 6: return launch_march<T, ORDER, 512, 1>(a, 128, s);
+    case 7: return launch_march<T, ORDER, 256, 3>(a, 128, s);
+    case 8: return launch_march<T, ORDER, 512, 2>(a, 128, s);
     default: return hipErrorInvalidValue;
     }
 }

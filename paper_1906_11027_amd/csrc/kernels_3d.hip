@@ -27,7 +27,7 @@ __device__ __forceinline__ void pull_d3q19(const T* __restrict__ f, int64_t n, u
         g[b] = ld_off(f + b * n, zo[1 - D3Q19::cz[b]] + yo[1 - D3Q19::cy[b]] + xo[1 - D3Q19::cx[b]]);
 }
 
-template <typename T, int ORDER, bool MRT, int TX, int TYB, int RPT>
+template <typename T, int ORDER, bool MRT, int TX, int TYB, int RPT, int PF>
 __global__ void __launch_bounds__(TX* TYB)
 k_d3q19_march(StepArgs<T> a, int H, int nbx, int nby)
 {
@@ -39,7 +39,7 @@ k_d3q19_march(StepArgs<T> a, int H, int nbx, int nby)
     constexpr int PL = LW * LH;          // one psi plane
     constexpr int NS = 2 * R + 2;        // psi ring slots
     constexpr int NT = TX * TYB;
-    constexpr int W = R + 1;             // f register window
+    constexpr int W = R + 1 + PF;        // f register window (PF = 1: next plane in flight)
     constexpr int RING = PL - TX * TY;   // halo nodes per plane
     constexpr int RPERT = (RING + NT - 1) / NT;
     __shared__ T psi_s[NS * PL];
@@ -91,36 +91,43 @@ k_d3q19_march(StepArgs<T> a, int H, int nbx, int nby)
 
     T g[W][RPT][19];
     T dr[W][RPT];
+    T h[RPERT][19];
     const int nplanes = H + 2 * R;
-    int zc = wrap_any(z0 - R, nz);
+    int zc = wrap_any(z0 - R, nz);   // plane whose pulls are issued next
+
+    // pulls of one plane (tile nodes into register slot `gs`, ring nodes into h)
+    auto issue = [&](T (&gs)[RPT][19]) {
+        uint32_t zo[3];
+        nbr_offsets<T>(zc, nz, planeb, zo);
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) pull_d3q19(a.fin, n, 0u, zo, yo[k], xo, gs[k]);
+#pragma unroll
+        for (int q = 0; q < RPERT; ++q)
+            if (rl[q] >= 0) pull_d3q19(a.fin, n, 0u, zo, ryo[q], rxo[q], h[q]);
+        zc = zc == nz - 1 ? 0 : zc + 1;
+    };
+    if (PF) issue(g[0]);
 
     for (int j0 = 0; j0 < nplanes; j0 += W) {
 #pragma unroll
         for (int s = 0; s < W; ++s) {
             const int j = j0 + s;
             if (j < nplanes) {   // uniform across the block
-                uint32_t zo[3];
-                nbr_offsets<T>(zc, nz, planeb, zo);
+                if (!PF) issue(g[s]);
                 T* slot = psi_s + (j % NS) * PL;
 #pragma unroll
                 for (int k = 0; k < RPT; ++k) {
-                    pull_d3q19(a.fin, n, 0u, zo, yo[k], xo, g[s][k]);
                     dr[s][k] = sum19(g[s][k]);
                     slot[(ty * RPT + k + R) * LW + tx + R] = psi_of(a.rho_ref + dr[s][k], a);
                 }
 #pragma unroll
-                for (int q = 0; q < RPERT; ++q) {
-                    if (rl[q] >= 0) {
-                        T h[19];
-                        pull_d3q19(a.fin, n, 0u, zo, ryo[q], rxo[q], h);
-                        slot[rl[q]] = psi_of(a.rho_ref + sum19(h), a);
-                    }
-                }
-                zc = zc == nz - 1 ? 0 : zc + 1;
+                for (int q = 0; q < RPERT; ++q)
+                    if (rl[q] >= 0) slot[rl[q]] = psi_of(a.rho_ref + sum19(h[q]), a);
+                if (PF && j + 1 < nplanes) issue(g[(s + 1) % W]);
                 __syncthreads();
 
                 if (j >= 2 * R) {
-                    const int sc = (s + 1) % W;          // register slot of plane j - R (static after unrolling)
+                    const int sc = (s + W - R) % W;      // register slot of plane j - R (static after unrolling)
                     const int zrel = j - 2 * R;          // 0 .. H-1
                     const int zr = z0 + zrel;
                     int sl[2 * R + 1];
@@ -171,20 +178,23 @@ static const Shape3D kShapes3D[] = {
     {32, 16, 1, 16, "march32x16r1h16"},
     {64, 8, 1, 16, "march64x8r1h16"},
     {32, 16, 1, 32, "march32x16r1h32"},
+    {64, 8, 1, 16, "march64x8r1h16pf1"},
+    {64, 8, 1, 32, "march64x8r1h32pf1"},
+    {64, 8, 2, 32, "march64x16h32"},
 };
 constexpr int kNumShapes3D = sizeof(kShapes3D) / sizeof(kShapes3D[0]);
 
 int num_variants_d3q19() { return kNumShapes3D; }
 const char* variant_name_d3q19(int v) { return (v >= 0 && v < kNumShapes3D) ? kShapes3D[v].name : "?"; }
 
-template <typename T, int ORDER, bool MRT, int TX, int TYB, int RPT>
+template <typename T, int ORDER, bool MRT, int TX, int TYB, int RPT, int PF = 0>
 static hipError_t launch_march(const StepArgs<T>& a, int H, hipStream_t s)
 {
     if (H > a.nz) H = a.nz;
     dim3 block(TX, TYB);
     const int nbx = (a.nx + TX - 1) / TX, nby = (a.ny + TYB * RPT - 1) / (TYB * RPT);
     const int nbz = (a.nz + H - 1) / H;
-    hipLaunchKernelGGL((k_d3q19_march<T, ORDER, MRT, TX, TYB, RPT>), dim3(nbx * nby * nbz), block, 0, s,
+    hipLaunchKernelGGL((k_d3q19_march<T, ORDER, MRT, TX, TYB, RPT, PF>), dim3(nbx * nby * nbz), block, 0, s,
                        a, H, nbx, nby);
     return hipGetLastError();
 }
@@ -200,6 +210,9 @@ static hipError_t launch_v(const StepArgs<T>& a, int variant, hipStream_t s)
     case 4: return launch_march<T, ORDER, MRT, 32, 16, 1>(a, 16, s);
     case 5: return launch_march<T, ORDER, MRT, 64, 8, 1>(a, 16, s);
     case 6: return launch_march<T, ORDER, MRT, 32, 16, 1>(a, 32, s);
+    case 7: return launch_march<T, ORDER, MRT, 64, 8, 1, 1>(a, 16, s);
+    case 8: return launch_march<T, ORDER, MRT, 64, 8, 1, 1>(a, 32, s);
+    case 9: return launch_march<T, ORDER, MRT, 64, 8, 2, 0>(a, 32, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -245,7 +245,7 @@ static int auto_variant(const sc_lbm_params& p, int64_t n)
     const int tuned = tune_lookup(p);
     if (tuned >= 0) return tuned;
     if (p.lattice == SC_D2Q9) return n < (int64_t)1 << 20 ? 2 : 0;
-    return n < (int64_t)1 << 22 ? 5 : 5;
+    return 7;   // march64x8r1h16pf1
 }
 
 static void release(sc_lbm* h)
