@@ -40,7 +40,9 @@ class Params(ctypes.Structure):
         ("psi_kind", ctypes.c_int), ("psi0", ctypes.c_double),
         ("rho_psi", ctypes.c_double), ("tau", ctypes.c_double),
         ("collision", ctypes.c_int), ("s_bulk", ctypes.c_double),
-        ("s_ghost", ctypes.c_double),
+        ("s_ghost", ctypes.c_double), ("forcing", ctypes.c_int),
+        ("pr_a", ctypes.c_double), ("pr_b", ctypes.c_double), ("pr_R", ctypes.c_double),
+        ("pr_T", ctypes.c_double), ("pr_alpha", ctypes.c_double),
     ]
 
 
@@ -108,13 +110,17 @@ def stencil_table(dim, order):
 
 def make_params(lattice="D2Q9", shape=(64, 64), order=4, G=-5.0, c0=1.0 / 3.0,
                 psi="exp", psi0=1.0, rho_psi=1.0, tau=1.0, collision="srt",
-                s_bulk=1.2, s_ghost=1.2):
+                s_bulk=1.2, s_ghost=1.2, forcing="guo", eos=None):
+    """eos: for psi == "pr", a dict with a, b, R, T (absolute) and alpha."""
     shape = tuple(shape)
     nx, ny = shape[0], shape[1]
     nz = shape[2] if len(shape) > 2 else 1
+    eos = eos or {}
     return Params(LATTICES[lattice], nx, ny, nz, order, G, c0,
-                  {"exp": 0, "identity": 1}[psi], psi0, rho_psi, tau,
-                  {"srt": 0, "mrt": 1}[collision], s_bulk, s_ghost)
+                  {"exp": 0, "identity": 1, "pr": 2}[psi], psi0, rho_psi, tau,
+                  {"srt": 0, "mrt": 1}[collision], s_bulk, s_ghost,
+                  {"guo": 0, "edm": 1}[forcing], eos.get("a", 0.0), eos.get("b", 0.0),
+                  eos.get("R", 0.0), eos.get("T", 0.0), eos.get("alpha", 0.0))
 
 
 def force(psi_field, lattice="D2Q9", order=4, G=-5.0, c0=1.0 / 3.0):
@@ -136,7 +142,7 @@ class Oracle:
 
     def __init__(self, rho0, lattice="D2Q9", order=4, G=-5.0, c0=1.0 / 3.0,
                  psi="exp", psi0=1.0, rho_psi=1.0, tau=1.0, collision="srt",
-                 s_bulk=1.2, s_ghost=1.2):
+                 s_bulk=1.2, s_ghost=1.2, forcing="guo", eos=None):
         rho0 = np.asarray(rho0, dtype=np.float64)
         self.shape = rho0.shape
         self.dim = DIMS[lattice]
@@ -145,7 +151,8 @@ class Oracle:
         self.psi_kind, self.psi0, self.rho_psi = psi, psi0, rho_psi
         self.tau = tau
         self.p = make_params(lattice, self.shape, order, G, c0, psi, psi0, rho_psi,
-                             tau, collision, s_bulk, s_ghost)
+                             tau, collision, s_bulk, s_ghost, forcing, eos)
+        self.eos = eos
         self.n = rho0.size
         self._dim, self.c, self.w, self.cs2 = lattice_table(lattice)
         self.q = len(self.w)
@@ -202,6 +209,12 @@ class Oracle:
 
 
 def observables(fl, cs2, G, c0):
+    """(The pressure uses the psi definition of Sec. 3 for every psi kind:
+    p = cs2 rho + G c0 psi^2 / 2, which equals the EOS pressure for "pr".)"""
+    return _observables(fl, cs2, G, c0)
+
+
+def _observables(fl, cs2, G, c0):
     """Reductions every K steps: mass, momentum, spurious-velocity norms
     (maximum and field average, Sec. 3 Fig. 3), Laplace pressure jump
     between the centre node and the corner node, equivalent radius."""

@@ -41,11 +41,14 @@ typedef struct {
     int nx, ny, nz;         /* nz = 1 for 2D */
     int order;              /* force-stencil isotropy order 4, 6, 8, 10 */
     double G, c0;           /* F = -G c0 psi sum_a what_a psi(x+e_a) e_a */
-    int psi_kind;           /* 0: psi0 (1 - exp(-rho/rho_psi)); 1: psi = rho */
+    int psi_kind;           /* 0: psi0 (1 - exp(-rho/rho_psi)); 1: psi = rho;
+                               2: from the Peng-Robinson EOS (Sec. 3) */
     double psi0, rho_psi;
     double tau;
     int collision;          /* 0 SRT, 1 MRT (3D lattices) */
     double s_bulk, s_ghost; /* MRT rates of the c^2 moment and the ghosts */
+    int forcing;            /* 0 Guo (Sec. 2, Eq. (4)); 1 exact difference method */
+    double pr_a, pr_b, pr_R, pr_T, pr_alpha;  /* P-R EOS: a, b, R, T, alpha(T) */
 } orc_params;
 
 typedef struct {
@@ -253,9 +256,22 @@ static void build_mrt(orc_sim *s)
 
 /* ------------------------------------------------------------------------ */
 
-static double psi_of(const orc_params *p, double rho)
+/* Peng-Robinson pressure (Sec. 3):
+ *   p = rho R T / (1 - b rho) - a alpha rho^2 / (1 + 2 b rho - b^2 rho^2) */
+static double p_pr(const orc_params *p, double rho)
+{
+    return rho * p->pr_R * p->pr_T / (1.0 - p->pr_b * rho)
+           - p->pr_a * p->pr_alpha * rho * rho / (1.0 + 2.0 * p->pr_b * rho - p->pr_b * p->pr_b * rho * rho);
+}
+
+static double psi_of_cs(const orc_params *p, double rho, double cs2)
 {
     if (p->psi_kind == 1) return rho;
+    if (p->psi_kind == 2) {
+        /* Sec. 3: psi = sqrt(2 (p - cs2 rho) / (G cs'^2)), cs'^2 = c0 here */
+        double arg = 2.0 * (p_pr(p, rho) - cs2 * rho) / (p->G * p->c0);
+        return arg > 0.0 ? sqrt(arg) : 0.0;
+    }
     return p->psi0 * (1.0 - exp(-rho / p->rho_psi));
 }
 
@@ -298,7 +314,7 @@ static void macro(orc_sim *s)
         double r = 0.0;
         for (int b = 0; b < s->q; ++b) r += s->f[b * n + i];
         s->rho[i] = r;
-        s->psi[i] = psi_of(&s->p, r);
+        s->psi[i] = psi_of_cs(&s->p, r, s->cs2);
     }
     force_from_psi(s, s->psi, s->F);
 }
@@ -312,10 +328,48 @@ static void velocity(const orc_sim *s, long i, double *u)
     for (int d = 0; d < s->dim; ++d) u[d] = (u[d] + 0.5 * s->F[d * n + i]) / s->rho[i];
 }
 
+static void feq_of(const orc_sim *s, double rho, const double *u, double *feq)
+{
+    const double cs2 = s->cs2;
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int b = 0; b < s->q; ++b) {
+        double cu = s->c[b][0] * u[0] + s->c[b][1] * u[1] + s->c[b][2] * u[2];
+        feq[b] = rho * s->w[b] * (1.0 + cu / cs2 + cu * cu / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
+    }
+}
+
+/* Exact difference method (the forcing used in the paper's experiments,
+ * Sec. 3): relax towards feq(rho, v) with v = sum f c / rho, then add the
+ * change of the equilibrium under the velocity increment F / rho:
+ *   f* = f - (f - feq(rho, v)) / tau + feq(rho, v + F/rho) - feq(rho, v). */
+static void collide_edm(const orc_sim *s, long i, double *fstar)
+{
+    const long n = s->n;
+    double rho = s->rho[i];
+    double v[3] = {0.0, 0.0, 0.0}, v2[3] = {0.0, 0.0, 0.0};
+    for (int b = 0; b < s->q; ++b)
+        for (int d = 0; d < s->dim; ++d) v[d] += s->f[b * n + i] * s->c[b][d];
+    for (int d = 0; d < s->dim; ++d) {
+        v[d] /= rho;
+        v2[d] = v[d] + s->F[d * n + i] / rho;
+    }
+    double fe[25], fe2[25];
+    feq_of(s, rho, v, fe);
+    feq_of(s, rho, v2, fe2);
+    for (int b = 0; b < s->q; ++b) {
+        double f = s->f[b * n + i];
+        fstar[b] = f - (f - fe[b]) / s->p.tau + (fe2[b] - fe[b]);
+    }
+}
+
 static void collide_node(const orc_sim *s, long i, double *fstar)
 {
     const long n = s->n;
     const double cs2 = s->cs2, tau = s->p.tau;
+    if (s->p.forcing == 1) {
+        collide_edm(s, i, fstar);
+        return;
+    }
     double u[3], Fv[3] = {0.0, 0.0, 0.0};
     velocity(s, i, u);
     for (int d = 0; d < s->dim; ++d) Fv[d] = s->F[d * n + i];
@@ -368,7 +422,7 @@ orc_sim *orc_create(const orc_params *p, const double *rho0)
     s->ns = orc_stencil(s->dim, p->order, s->e, s->ew);
     if (s->ns <= 0) goto fail;
     if (p->collision == 1) {
-        if (s->q != 19) goto fail;
+        if (s->q != 19 || p->forcing != 0) goto fail;
         build_mrt(s);
     }
     s->n = (long)s->p.nx * s->p.ny * s->p.nz;

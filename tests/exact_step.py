@@ -19,7 +19,7 @@ def _add(a, b, shape):
 
 
 def exact_steps(rho0, shape, lattice, order, G, c0, tau, nsteps=1,
-                collision="srt", s_bulk=None, s_ghost=None):
+                collision="srt", s_bulk=None, s_ghost=None, forcing="guo"):
     """rho0: dict node -> Fraction.  Returns dict node -> list of f (Fractions)
     after nsteps, with f = feq(rho0, 0) at t = 0."""
     dim, cs2, vel = T.lattice(lattice)
@@ -64,7 +64,21 @@ def exact_steps(rho0, shape, lattice, order, G, c0, tau, nsteps=1,
                 feq.append(rho[x] * w * (1 + cu / cs2 + cu * cu / (2 * cs2 * cs2) - uu / (2 * cs2)))
                 ph.append(w * sum(((c[d] - u[d]) / cs2 + cu * c[d] / (cs2 * cs2)) * F[x][d]
                                   for d in range(dim)))
-            if collision == "srt":
+            if forcing == "edm":
+                # exact difference method: equilibria at v = mom/rho and v + F/rho
+                v = [m / rho[x] for m in mom]
+                v2 = [v[d] + F[x][d] / rho[x] for d in range(dim)]
+
+                def eq(vel):
+                    vv = sum(t * t for t in vel)
+                    out = []
+                    for c, w in T.lattice(lattice)[2]:
+                        cv = sum(c[d] * vel[d] for d in range(dim))
+                        out.append(rho[x] * w * (1 + cv / cs2 + cv * cv / (2 * cs2 * cs2) - vv / (2 * cs2)))
+                    return out
+                e1, e2 = eq(v), eq(v2)
+                fs = [fb - (fb - a) / tau + (b - a) for fb, a, b in zip(fx, e1, e2)]
+            elif collision == "srt":
                 fs = [fb - (fb - fe) / tau + (1 - 1 / (2 * tau)) * p
                       for fb, fe, p in zip(fx, feq, ph)]
             else:
