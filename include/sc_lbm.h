@@ -9,10 +9,17 @@
  *     w_a = c0 * w_hat_a with w_hat normalised to sum w_hat e_x^2 = 1;
  *   - Guo-forced lattice Boltzmann step with pull streaming               (Sec. 2, Eq. (3)-(4)),
  *     u = (sum_b f_b c_b + F/2) / rho                                     (Sec. 4, Eq. (7));
- *   - psi = psi0 (1 - exp(-rho / rho_psi)), or psi = rho for exact tests;
+ *   - psi = psi0 (1 - exp(-rho / rho_psi)), psi = rho for exact tests, or
+ *     the Peng-Robinson pseudo-potential of Sec. 3,
+ *       psi = sqrt(2 (p_PR(rho) - cs2 rho) / (G c0)),
+ *       p_PR = rho R T / (1 - b rho) - a alpha rho^2 / (1 + 2 b rho - b^2 rho^2);
  *   - pressure p = cs2 rho + G c0 psi^2 / 2 (the psi definition of Sec. 3);
- *   - lattices D2Q9 (Table 1) and D3Q19 (Sec. 3); D3Q19 also with MRT
- *     collision (rates grouped conserved / bulk / shear = 1/tau / ghost).
+ *   - lattices D2Q9, D2Q13, D2Q25 (Sec. 3, Table 1) and D3Q19 (Sec. 3);
+ *     D3Q19 also with MRT collision (rates grouped conserved / bulk /
+ *     shear = 1/tau / ghost);
+ *   - forcing: Guo (Eq. (4)) or, on the 2D lattices with SRT, the exact
+ *     difference method the experiments of Sec. 3 use:
+ *       f* = f - (f - feq(v))/tau + feq(v + F/rho) - feq(v),  v = sum f c / rho.
  *
  * Conventions
  *   - Lattice units, dt = dx = 1, periodic in every axis.
@@ -24,6 +31,11 @@
  *       D3Q19: (0,0,0) (1,0,0) (-1,0,0) (0,1,0) (0,-1,0) (0,0,1) (0,0,-1)
  *              (1,1,0) (-1,-1,0) (1,-1,0) (-1,1,0) (1,0,1) (-1,0,-1)
  *              (1,0,-1) (-1,0,1) (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1)
+ *       D2Q13: (0,0), then by |c|^2 and within a shell lexicographically:
+ *              (-1,0) (0,-1) (0,1) (1,0) (-1,-1) (-1,1) (1,-1) (1,1)
+ *              (-2,0) (0,-2) (0,2) (2,0)
+ *       D2Q25: the D2Q13 list, then (-2,-1) (-2,1) (-1,-2) (-1,2) (1,-2)
+ *              (1,2) (2,-1) (2,1) (-2,-2) (-2,2) (2,-2) (2,2)
  *     so the next step pulls f_b(x) = state_b(x - c_b) + w_b rho_ref.
  *   - Every entry point returns SC_OK (0) or a negative SC_E_* code and
  *     never aborts or throws.  sc_lbm_strerror() names the code.
@@ -55,9 +67,15 @@ extern "C" {
 /* ---- enumerations ------------------------------------------------------ */
 #define SC_D2Q9 0
 #define SC_D3Q19 1
+#define SC_D2Q13 2             /* cs^2 = 2/5, 6th-order isotropic (Table 1)  */
+#define SC_D2Q25 3             /* cs^2 = 4/7, 8th-order isotropic (Table 1)  */
 
 #define SC_PSI_EXP 0           /* psi = psi0 (1 - exp(-rho / rho_psi))      */
 #define SC_PSI_IDENTITY 1      /* psi = rho                                 */
+#define SC_PSI_PR 2            /* Peng-Robinson pseudo-potential (Sec. 3)   */
+
+#define SC_GUO 0               /* Guo forcing, Eq. (4)                      */
+#define SC_EDM 1               /* exact difference method (2D, SRT)          */
 
 #define SC_SRT 0
 #define SC_MRT 1               /* D3Q19 only                               */
@@ -67,11 +85,11 @@ extern "C" {
 
 /* ---- problem statement -------------------------------------------------- */
 typedef struct sc_lbm_params {
-    int32_t lattice;      /* SC_D2Q9 or SC_D3Q19                                 */
-    int32_t nx, ny, nz;   /* grid; nz must be 1 for SC_D2Q9                       */
+    int32_t lattice;      /* SC_D2Q9, SC_D3Q19, SC_D2Q13 or SC_D2Q25             */
+    int32_t nx, ny, nz;   /* grid; nz must be 1 on the 2D lattices                */
     int32_t order;        /* force-stencil isotropy order: 4, 6, 8, 10 (2D);
                              4, 6, 8 (3D)                                         */
-    int32_t psi_kind;     /* SC_PSI_EXP or SC_PSI_IDENTITY                        */
+    int32_t psi_kind;     /* SC_PSI_EXP, SC_PSI_IDENTITY or SC_PSI_PR             */
     double G;             /* interaction strength (Eq. (1)); G < 0 attracts       */
     double c0;            /* force-weight scale: w_a = c0 w_hat_a (1/3 for the
                              classic nearest-neighbour weights 1/9, 1/36)         */
@@ -84,11 +102,16 @@ typedef struct sc_lbm_params {
     double rho_ref;       /* storage shift (normally 1)                           */
     int32_t obs_every;    /* K: steps between convergence checks (default 100)    */
     int32_t variant;      /* launch shape of the fused kernel; -1 = automatic     */
+    int32_t forcing;      /* SC_GUO or SC_EDM                                     */
+    /* (4 bytes of padding) */
+    double eos_a, eos_b;  /* Peng-Robinson a, b (SC_PSI_PR; Sec. 3: 2/49, 2/21)   */
+    double eos_R, eos_T;  /* gas constant and absolute temperature                */
+    double eos_alpha;     /* alpha(T) of the Peng-Robinson attraction term        */
 } sc_lbm_params;
 
 /* Fills *p with the defaults: D2Q9 64x64, E4, G = -5, c0 = 1/3, exp psi with
- * psi0 = rho_psi = 1, tau = 1, SRT, FP32 shifted, MRT rates 1.2, rho_ref = 1,
- * K = 100, automatic variant. */
+ * psi0 = rho_psi = 1, tau = 1, SRT, Guo forcing, FP32 shifted, MRT rates 1.2,
+ * rho_ref = 1, K = 100, automatic variant, EOS fields zero. */
 void sc_lbm_default_params(sc_lbm_params* p);
 
 /* ---- observables (FP64 reductions) -------------------------------------- */
@@ -169,10 +192,13 @@ void* sc_lbm_stream(sc_lbm* h);
  * choices persist across processes.  Outputs are nullable. */
 int sc_lbm_autotune(const sc_lbm_params* p, int32_t steps, int32_t* best_variant, double* best_ms_per_step);
 
-/* Name of the launch shape in use and the number of shapes available for
- * this lattice (for tuning sweeps through sc_lbm_params.variant). */
+/* Name of the launch shape in use, and the number of launch shapes of the
+ * kernel family that serves *p (for sweeps through sc_lbm_params.variant;
+ * *p's own variant field is ignored): D2Q9 with Guo forcing, D3Q19, and the
+ * any-lattice 2D family (D2Q13, D2Q25, D2Q9 with EDM) each have their own
+ * list.  0 if *p is invalid. */
 const char* sc_lbm_variant_name(const sc_lbm* h);
-int sc_lbm_num_variants(int32_t lattice);
+int sc_lbm_num_variants(const sc_lbm_params* p);
 
 void sc_lbm_destroy(sc_lbm* h);
 const char* sc_lbm_strerror(int code);
@@ -186,11 +212,13 @@ const char* sc_lbm_strerror(int code);
  * Converged or diverged items leave the work list; the others continue. */
 typedef struct sc_lbm_batch sc_lbm_batch;
 
-/*   items      n parameter sets (lattice SC_D2Q9, collision SC_SRT);
+/*   items      n parameter sets (lattice SC_D2Q9, collision SC_SRT, Guo
+ *              forcing, psi SC_PSI_EXP or SC_PSI_IDENTITY);
  *   rho_init   n host pointers to [nx*ny] initial densities (each nullable),
  *              or NULL for rho = 1 everywhere;
  *   hip_stream as for sc_lbm_create.
- * Errors: SC_E_INVAL, SC_E_UNSUPPORTED (3D or MRT item), SC_E_NOMEM, SC_E_DEVICE. */
+ * Errors: SC_E_INVAL, SC_E_UNSUPPORTED (other lattice, MRT, EDM or
+ * Peng-Robinson item), SC_E_NOMEM, SC_E_DEVICE. */
 int sc_lbm_batch_create(const sc_lbm_params* items, int32_t n, const double* const* rho_init, void* hip_stream,
                         sc_lbm_batch** out);
 

@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsc_lbm.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["kernels_2d.hip", "kernels_3d.hip", "kernels_batch.hip", "observe.hip", "nn.hip", "sc_lbm.cpp"]
+SOURCES = ["kernels_2d.hip", "kernels_3d.hip", "kernels_batch.hip", "kernels_wide_q9.hip", "kernels_wide_q13.hip",
+           "kernels_wide_q25.hip", "observe.hip", "nn.hip", "sc_lbm.cpp"]
 ARCH = os.environ.get("SC_LBM_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -24,14 +24,26 @@ struct StepArgs {
     T guo;                       // 1 - 1 / (2 tau)   (Guo forcing, Eq. (4))
     T rho_ref;                   // storage shift
     T psi0, inv_rho_psi;         // psi = psi0 (1 - exp(-rho / rho_psi))
-    int psi_kind;                // 0 exp form, 1 psi = rho
+    int psi_kind;                // 0 exp form, 1 psi = rho, 2 Peng-Robinson
     T s_bulk, s_ghost;           // MRT rates (D3Q19)
+    T cs2;                       // lattice sound speed squared
+    T eos_RT, eos_b, eos_aa;     // Peng-Robinson R T, b and a alpha(T)
+    T eos_k;                     // 2 / (G c0)
 };
 
+// Pseudo-potential.  The Peng-Robinson form inverts the bulk pressure of the
+// model, p = cs2 rho + G c0 psi^2 / 2 (Sec. 3):
+//   psi = sqrt(2 (p_PR(rho) - cs2 rho) / (G c0)),  0 where the root is not real.
 template <typename T>
 __device__ __forceinline__ T psi_of(T rho, const StepArgs<T>& a)
 {
     if (a.psi_kind == 1) return rho;
+    if (a.psi_kind == 2) {
+        const T br = a.eos_b * rho;
+        const T p = rho * a.eos_RT / (T(1) - br) - a.eos_aa * rho * rho / (T(1) + T(2) * br - br * br);
+        const T arg = (p - a.cs2 * rho) * a.eos_k;
+        return arg > T(0) ? sqrt(arg) : T(0);
+    }
     return a.psi0 * (T(1) - exp(-rho * a.inv_rho_psi));
 }
 
@@ -235,7 +247,8 @@ __device__ __forceinline__ void collide_d3q19(T (&g)[19], T drho, T Fx, T Fy, T 
 
 // ------------------------------------------------------------ launchers ----
 // Fused force + collide + pull-stream step.  `variant` picks a launch shape
-// (see kernels_2d.hip / kernels_3d.hip); returns hipSuccess or an error.
+// (see kernels_2d.hip / kernels_3d.hip / wide2d.h); returns hipSuccess or an
+// error.
 hipError_t launch_step_d2q9(const StepArgs<float>& a, int order, int variant, hipStream_t s);
 hipError_t launch_step_d2q9(const StepArgs<double>& a, int order, int variant, hipStream_t s);
 hipError_t launch_step_d3q19(const StepArgs<float>& a, int order, bool mrt, int variant, hipStream_t s);
@@ -245,8 +258,24 @@ int num_variants_d3q19();
 const char* variant_name_d2q9(int v);
 const char* variant_name_d3q19(int v);
 
+// Any-lattice 2D step (D2Q13, D2Q25, and D2Q9 with the exact difference
+// method): lattice is the SC_* id, edm selects the forcing.
+hipError_t launch_step_wide(int lattice, const StepArgs<float>& a, int order, bool edm, int variant,
+                            hipStream_t s);
+hipError_t launch_step_wide(int lattice, const StepArgs<double>& a, int order, bool edm, int variant,
+                            hipStream_t s);
+int num_variants_wide();
+const char* variant_name_wide(int v);
+// per-lattice instantiations (kernels_wide_q*.hip)
+hipError_t launch_wide_q9(const StepArgs<float>& a, int order, bool edm, int variant, hipStream_t s);
+hipError_t launch_wide_q9(const StepArgs<double>& a, int order, bool edm, int variant, hipStream_t s);
+hipError_t launch_wide_q13(const StepArgs<float>& a, int order, bool edm, int variant, hipStream_t s);
+hipError_t launch_wide_q13(const StepArgs<double>& a, int order, bool edm, int variant, hipStream_t s);
+hipError_t launch_wide_q25(const StepArgs<float>& a, int order, bool edm, int variant, hipStream_t s);
+hipError_t launch_wide_q25(const StepArgs<double>& a, int order, bool edm, int variant, hipStream_t s);
+
 // Initial state: g_b(x) = w_b (rho0(x + c_b) - rho_ref), i.e. the pull of
-// the next step sees f = feq(rho0, u = 0) everywhere.
+// the next step sees f = feq(rho0, u = 0) everywhere.  lattice: SC_* id.
 hipError_t launch_init(int lattice, void* f, int precision, const double* rho0, int nx, int ny, int nz,
                        double rho_ref, hipStream_t s);
 
@@ -263,7 +292,7 @@ struct ObsBuffers {
 };
 hipError_t launch_macro(int lattice, int precision, const void* f, const void* args, ObsBuffers& ob,
                         hipStream_t s);
-hipError_t launch_force(int lattice, int precision, int order, const void* args, ObsBuffers& ob,
+hipError_t launch_force(int dim, int precision, int order, const void* args, ObsBuffers& ob,
                         bool with_velocity, hipStream_t s);
 hipError_t launch_psi_from_host(int precision, const double* psi_dev_d, void* psi, int64_t n, hipStream_t s);
 hipError_t launch_reduce(int dim, ObsBuffers& ob, int64_t n, hipStream_t s);

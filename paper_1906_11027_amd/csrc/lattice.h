@@ -24,6 +24,7 @@ struct D2Q9 {
     static constexpr int cz[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     static constexpr double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
                                     1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    static constexpr double cs2 = 1.0 / 3;
 };
 
 // --------------------------------------------------------------- D3Q19 ----
@@ -38,6 +39,42 @@ struct D3Q19 {
                                      1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
                                      1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
                                      1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    static constexpr double cs2 = 1.0 / 3;
+};
+
+// --------------------------------------------------- D2Q13, D2Q25 ----
+// The larger 2D sets of Sec. 3, Table 1 (weights by |c|^2): D2Q13 with
+// cs^2 = 2/5 (6th-order isotropic), D2Q25 with cs^2 = 4/7 (8th-order).
+// Order: rest, then shells by |c|^2, each shell in (cx, cy) lexicographic order.
+struct D2Q13 {
+    static constexpr int Q = 13;
+    static constexpr int D = 2;
+    static constexpr int cx[13] = {0, -1, 0, 0, 1, -1, -1, 1, 1, -2, 0, 0, 2};
+    static constexpr int cy[13] = {0, 0, -1, 1, 0, -1, 1, -1, 1, 0, -2, 2, 0};
+    static constexpr int cz[13] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    static constexpr double w[13] = {2.0 / 5,
+                                     8.0 / 75, 8.0 / 75, 8.0 / 75, 8.0 / 75,
+                                     1.0 / 25, 1.0 / 25, 1.0 / 25, 1.0 / 25,
+                                     1.0 / 300, 1.0 / 300, 1.0 / 300, 1.0 / 300};
+    static constexpr double cs2 = 2.0 / 5;
+};
+struct D2Q25 {
+    static constexpr int Q = 25;
+    static constexpr int D = 2;
+    static constexpr int cx[25] = {0, -1, 0, 0, 1, -1, -1, 1, 1, -2, 0, 0, 2,
+                                   -2, -2, -1, -1, 1, 1, 2, 2, -2, -2, 2, 2};
+    static constexpr int cy[25] = {0, 0, -1, 1, 0, -1, 1, -1, 1, 0, -2, 2, 0,
+                                   -1, 1, -2, 2, -2, 2, -1, 1, -2, 2, -2, 2};
+    static constexpr int cz[25] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0,
+                                   0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    static constexpr double w[25] = {72.0 / 245,
+                                     16.0 / 147, 16.0 / 147, 16.0 / 147, 16.0 / 147,
+                                     16.0 / 315, 16.0 / 315, 16.0 / 315, 16.0 / 315,
+                                     1.0 / 105, 1.0 / 105, 1.0 / 105, 1.0 / 105,
+                                     8.0 / 2205, 8.0 / 2205, 8.0 / 2205, 8.0 / 2205,
+                                     8.0 / 2205, 8.0 / 2205, 8.0 / 2205, 8.0 / 2205,
+                                     1.0 / 8820, 1.0 / 8820, 1.0 / 8820, 1.0 / 8820};
+    static constexpr double cs2 = 4.0 / 7;
 };
 
 // ------------------------------------------------------- force stencils ----

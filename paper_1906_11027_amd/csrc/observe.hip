@@ -30,46 +30,85 @@ __device__ __forceinline__ void neighbours(int64_t i, int nx, int ny, int nz, in
     zo[2] = (int64_t)(z == nz - 1 ? 0 : z + 1) * nxy;
 }
 
+// Flat index of node (x, y, z) + (dx, dy, dz) on the periodic grid (any
+// offset; used by the lattices that stream over distance 2).
+__device__ __forceinline__ int64_t shifted_node(int x, int y, int z, int dx, int dy, int dz, int nx, int ny, int nz)
+{
+    return ((int64_t)wrap_any(z + dz, nz) * ny + wrap_any(y + dy, ny)) * nx + wrap_any(x + dx, nx);
+}
+
+__device__ __forceinline__ void coords(int64_t i, int nx, int ny, int& x, int& y, int& z)
+{
+    const int64_t nxy = (int64_t)nx * ny;
+    z = (int)(i / nxy);
+    const int64_t rem = i - (int64_t)z * nxy;
+    y = (int)(rem / nx);
+    x = (int)(rem - (int64_t)y * nx);
+}
+
 // ---------------------------------------------------------------- init ----
-template <typename T, typename L>
+template <typename T, typename L, int M>
 __global__ void k_init(T* __restrict__ f, const double* __restrict__ rho0, int nx, int ny, int nz,
                        double rho_ref)
 {
     const int64_t n = (int64_t)nx * ny * nz;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        int64_t zo[3], yo[3];
-        int xo[3];
-        neighbours<L>(i, nx, ny, nz, zo, yo, xo);
+        if (M == 1) {
+            int64_t zo[3], yo[3];
+            int xo[3];
+            neighbours<L>(i, nx, ny, nz, zo, yo, xo);
 #pragma unroll
-        for (int b = 0; b < L::Q; ++b) {
-            // node x + c_b: the pull of the next step brings this value to it
-            const int64_t src = zo[1 + L::cz[b]] + yo[1 + L::cy[b]] + xo[1 + L::cx[b]];
-            f[b * n + i] = (T)(L::w[b] * (rho0[src] - rho_ref));
+            for (int b = 0; b < L::Q; ++b) {
+                // node x + c_b: the pull of the next step brings this value to it
+                const int64_t src = zo[1 + L::cz[b]] + yo[1 + L::cy[b]] + xo[1 + L::cx[b]];
+                f[b * n + i] = (T)(L::w[b] * (rho0[src] - rho_ref));
+            }
+        } else {
+            int x, y, z;
+            coords(i, nx, ny, x, y, z);
+#pragma unroll
+            for (int b = 0; b < L::Q; ++b) {
+                const int64_t src = shifted_node(x, y, z, L::cx[b], L::cy[b], L::cz[b], nx, ny, nz);
+                f[b * n + i] = (T)(L::w[b] * (rho0[src] - rho_ref));
+            }
         }
     }
 }
 
 // --------------------------------------------------------------- macro ----
 // rho, psi and j = sum_b f_b c_b of the pulled (pre-collision) state.
-template <typename T, typename L>
+template <typename T, typename L, int M>
 __global__ void k_macro(const T* __restrict__ f, StepArgs<T> a, double* __restrict__ rho,
                         T* __restrict__ psi, double* __restrict__ j)
 {
     const int64_t n = a.n;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        int64_t zo[3], yo[3];
-        int xo[3];
-        neighbours<L>(i, a.nx, a.ny, a.nz, zo, yo, xo);
         T dr = T(0), jx = T(0), jy = T(0), jz = T(0);
+        if (M == 1) {
+            int64_t zo[3], yo[3];
+            int xo[3];
+            neighbours<L>(i, a.nx, a.ny, a.nz, zo, yo, xo);
 #pragma unroll
-        for (int b = 0; b < L::Q; ++b) {
-            const T v = f[b * n + zo[1 - L::cz[b]] + yo[1 - L::cy[b]] + xo[1 - L::cx[b]]];
-            dr += v;
-            jx += T(L::cx[b]) * v;
-            jy += T(L::cy[b]) * v;
-            jz += T(L::cz[b]) * v;
+            for (int b = 0; b < L::Q; ++b) {
+                const T v = f[b * n + zo[1 - L::cz[b]] + yo[1 - L::cy[b]] + xo[1 - L::cx[b]]];
+                dr += v;
+                jx += T(L::cx[b]) * v;
+                jy += T(L::cy[b]) * v;
+                jz += T(L::cz[b]) * v;
+            }
+        } else {
+            int x, y, z;
+            coords(i, a.nx, a.ny, x, y, z);
+#pragma unroll
+            for (int b = 0; b < L::Q; ++b) {
+                const T v = f[b * n + shifted_node(x, y, z, -L::cx[b], -L::cy[b], -L::cz[b], a.nx, a.ny, a.nz)];
+                dr += v;
+                jx += T(L::cx[b]) * v;
+                jy += T(L::cy[b]) * v;
+                jz += T(L::cz[b]) * v;
+            }
         }
         const T r = a.rho_ref + dr;
         rho[i] = (double)r;
@@ -217,21 +256,39 @@ static int grid_for(int64_t n, int threads)
     return (int)b;
 }
 
+template <typename T>
+static hipError_t init_t(int lattice, T* f, const double* rho0, int nx, int ny, int nz, double rho_ref,
+                         hipStream_t s)
+{
+    const int g = grid_for((int64_t)nx * ny * nz, 256);
+    switch (lattice) {
+    case 0: hipLaunchKernelGGL((k_init<T, D2Q9, 1>), g, 256, 0, s, f, rho0, nx, ny, nz, rho_ref); break;
+    case 1: hipLaunchKernelGGL((k_init<T, D3Q19, 1>), g, 256, 0, s, f, rho0, nx, ny, nz, rho_ref); break;
+    case 2: hipLaunchKernelGGL((k_init<T, D2Q13, 2>), g, 256, 0, s, f, rho0, nx, ny, nz, rho_ref); break;
+    case 3: hipLaunchKernelGGL((k_init<T, D2Q25, 2>), g, 256, 0, s, f, rho0, nx, ny, nz, rho_ref); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_init(int lattice, void* f, int precision, const double* rho0, int nx, int ny, int nz,
                        double rho_ref, hipStream_t s)
 {
-    const int64_t n = (int64_t)nx * ny * nz;
-    const int g = grid_for(n, 256);
-    if (lattice == 0) {
-        if (precision == 0)
-            hipLaunchKernelGGL((k_init<float, D2Q9>), g, 256, 0, s, (float*)f, rho0, nx, ny, nz, rho_ref);
-        else
-            hipLaunchKernelGGL((k_init<double, D2Q9>), g, 256, 0, s, (double*)f, rho0, nx, ny, nz, rho_ref);
-    } else {
-        if (precision == 0)
-            hipLaunchKernelGGL((k_init<float, D3Q19>), g, 256, 0, s, (float*)f, rho0, nx, ny, nz, rho_ref);
-        else
-            hipLaunchKernelGGL((k_init<double, D3Q19>), g, 256, 0, s, (double*)f, rho0, nx, ny, nz, rho_ref);
+    return precision == 0 ? init_t<float>(lattice, (float*)f, rho0, nx, ny, nz, rho_ref, s)
+                          : init_t<double>(lattice, (double*)f, rho0, nx, ny, nz, rho_ref, s);
+}
+
+template <typename T>
+static hipError_t macro_t(int lattice, const T* f, const StepArgs<T>& a, ObsBuffers& ob, hipStream_t s)
+{
+    const int g = grid_for(a.n, 256);
+    T* psi = (T*)ob.psi;
+    switch (lattice) {
+    case 0: hipLaunchKernelGGL((k_macro<T, D2Q9, 1>), g, 256, 0, s, f, a, ob.rho, psi, ob.j); break;
+    case 1: hipLaunchKernelGGL((k_macro<T, D3Q19, 1>), g, 256, 0, s, f, a, ob.rho, psi, ob.j); break;
+    case 2: hipLaunchKernelGGL((k_macro<T, D2Q13, 2>), g, 256, 0, s, f, a, ob.rho, psi, ob.j); break;
+    case 3: hipLaunchKernelGGL((k_macro<T, D2Q25, 2>), g, 256, 0, s, f, a, ob.rho, psi, ob.j); break;
+    default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
@@ -239,22 +296,8 @@ hipError_t launch_init(int lattice, void* f, int precision, const double* rho0, 
 hipError_t launch_macro(int lattice, int precision, const void* f, const void* args, ObsBuffers& ob,
                         hipStream_t s)
 {
-    if (precision == 0) {
-        const StepArgs<float>& a = *(const StepArgs<float>*)args;
-        const int g = grid_for(a.n, 256);
-        if (lattice == 0)
-            hipLaunchKernelGGL((k_macro<float, D2Q9>), g, 256, 0, s, (const float*)f, a, ob.rho, (float*)ob.psi, ob.j);
-        else
-            hipLaunchKernelGGL((k_macro<float, D3Q19>), g, 256, 0, s, (const float*)f, a, ob.rho, (float*)ob.psi, ob.j);
-    } else {
-        const StepArgs<double>& a = *(const StepArgs<double>*)args;
-        const int g = grid_for(a.n, 256);
-        if (lattice == 0)
-            hipLaunchKernelGGL((k_macro<double, D2Q9>), g, 256, 0, s, (const double*)f, a, ob.rho, (double*)ob.psi, ob.j);
-        else
-            hipLaunchKernelGGL((k_macro<double, D3Q19>), g, 256, 0, s, (const double*)f, a, ob.rho, (double*)ob.psi, ob.j);
-    }
-    return hipGetLastError();
+    if (precision == 0) return macro_t<float>(lattice, (const float*)f, *(const StepArgs<float>*)args, ob, s);
+    return macro_t<double>(lattice, (const double*)f, *(const StepArgs<double>*)args, ob, s);
 }
 
 template <typename T, int D>
@@ -276,17 +319,17 @@ static hipError_t force_d(int order, const StepArgs<T>& a, ObsBuffers& ob, bool 
     return hipGetLastError();
 }
 
-hipError_t launch_force(int lattice, int precision, int order, const void* args, ObsBuffers& ob,
+hipError_t launch_force(int dim, int precision, int order, const void* args, ObsBuffers& ob,
                         bool with_velocity, hipStream_t s)
 {
     if (precision == 0) {
         const StepArgs<float>& a = *(const StepArgs<float>*)args;
-        return lattice == 0 ? force_d<float, 2>(order, a, ob, with_velocity, s)
-                            : force_d<float, 3>(order, a, ob, with_velocity, s);
+        return dim == 2 ? force_d<float, 2>(order, a, ob, with_velocity, s)
+                        : force_d<float, 3>(order, a, ob, with_velocity, s);
     }
     const StepArgs<double>& a = *(const StepArgs<double>*)args;
-    return lattice == 0 ? force_d<double, 2>(order, a, ob, with_velocity, s)
-                        : force_d<double, 3>(order, a, ob, with_velocity, s);
+    return dim == 2 ? force_d<double, 2>(order, a, ob, with_velocity, s)
+                    : force_d<double, 3>(order, a, ob, with_velocity, s);
 }
 
 hipError_t launch_psi_from_host(int precision, const double* psi_dev_d, void* psi, int64_t n, hipStream_t s)

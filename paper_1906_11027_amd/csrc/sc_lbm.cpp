@@ -67,6 +67,62 @@ static int hip_err_at(hipError_t e, const char* where)
 }
 #define hip_err(e) hip_err_at((e), __func__)
 
+// ---- lattice facts used on the host ---------------------------------------
+static int lattice_q(int lattice)
+{
+    switch (lattice) {
+    case SC_D2Q9: return 9;
+    case SC_D3Q19: return 19;
+    case SC_D2Q13: return 13;
+    case SC_D2Q25: return 25;
+    default: return 0;
+    }
+}
+static int lattice_dim(int lattice) { return lattice == SC_D3Q19 ? 3 : 2; }
+static double lattice_cs2(int lattice)
+{
+    return lattice == SC_D2Q13 ? D2Q13::cs2 : (lattice == SC_D2Q25 ? D2Q25::cs2 : 1.0 / 3.0);
+}
+
+// Kernel families: the D2Q9 Guo kernels, the D3Q19 kernels, and the
+// any-lattice 2D kernels (D2Q13, D2Q25, D2Q9 with the exact difference method).
+enum Family { kFamD2Q9 = 0, kFamD3Q19 = 1, kFamWide = 2 };
+static Family family_of(const sc_lbm_params& p)
+{
+    if (p.lattice == SC_D3Q19) return kFamD3Q19;
+    if (p.lattice == SC_D2Q9 && p.forcing == SC_GUO) return kFamD2Q9;
+    return kFamWide;
+}
+static int family_variants(Family f)
+{
+    return f == kFamD2Q9 ? num_variants_d2q9() : (f == kFamD3Q19 ? num_variants_d3q19() : num_variants_wide());
+}
+
+namespace sclbm {
+static const char* const kShapesWide[] = {"wide64x8r2", "wide32x8r1", "wide64x16r4", "wide64x16r2"};
+int num_variants_wide() { return (int)(sizeof(kShapesWide) / sizeof(kShapesWide[0])); }
+const char* variant_name_wide(int v) { return (v >= 0 && v < num_variants_wide()) ? kShapesWide[v] : "?"; }
+
+template <typename T>
+static hipError_t wide_dispatch(int lattice, const StepArgs<T>& a, int order, bool edm, int variant, hipStream_t s)
+{
+    switch (lattice) {
+    case SC_D2Q9: return launch_wide_q9(a, order, edm, variant, s);
+    case SC_D2Q13: return launch_wide_q13(a, order, edm, variant, s);
+    case SC_D2Q25: return launch_wide_q25(a, order, edm, variant, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+hipError_t launch_step_wide(int lattice, const StepArgs<float>& a, int order, bool edm, int variant, hipStream_t s)
+{
+    return wide_dispatch<float>(lattice, a, order, edm, variant, s);
+}
+hipError_t launch_step_wide(int lattice, const StepArgs<double>& a, int order, bool edm, int variant, hipStream_t s)
+{
+    return wide_dispatch<double>(lattice, a, order, edm, variant, s);
+}
+}  // namespace sclbm
+
 extern "C" void sc_lbm_default_params(sc_lbm_params* p)
 {
     if (!p) return;
@@ -91,26 +147,36 @@ extern "C" void sc_lbm_default_params(sc_lbm_params* p)
     p->variant = -1;
 }
 
-static int validate(const sc_lbm_params* p)
+// Checks everything but the variant index.
+static int validate_problem(const sc_lbm_params* p)
 {
     if (!p) return SC_E_INVAL;
-    if (p->lattice != SC_D2Q9 && p->lattice != SC_D3Q19) return SC_E_INVAL;
+    if (lattice_q(p->lattice) == 0) return SC_E_INVAL;
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return SC_E_INVAL;
-    if (p->lattice == SC_D2Q9 && p->nz != 1) return SC_E_INVAL;
+    const int dim = lattice_dim(p->lattice);
+    if (dim == 2 && p->nz != 1) return SC_E_INVAL;
     const int64_t n = (int64_t)p->nx * p->ny * p->nz;
-    const int q = p->lattice == SC_D2Q9 ? 9 : 19;
     // one velocity plane must stay below 4 GiB (32-bit byte offsets in the kernels)
     const int64_t ts = p->precision == SC_FP64 ? 8 : 4;
     if (n * ts >= ((int64_t)1 << 32)) return SC_E_UNSUPPORTED;
-    (void)q;
-    if (p->lattice == SC_D2Q9) {
+    if (dim == 2) {
         if (p->order != 4 && p->order != 6 && p->order != 8 && p->order != 10) return SC_E_INVAL;
     } else {
         if (p->order != 4 && p->order != 6 && p->order != 8) return SC_E_UNSUPPORTED;
     }
-    if (p->psi_kind != SC_PSI_EXP && p->psi_kind != SC_PSI_IDENTITY) return SC_E_INVAL;
+    if (p->psi_kind != SC_PSI_EXP && p->psi_kind != SC_PSI_IDENTITY && p->psi_kind != SC_PSI_PR) return SC_E_INVAL;
     if (p->collision != SC_SRT && p->collision != SC_MRT) return SC_E_INVAL;
     if (p->collision == SC_MRT && p->lattice != SC_D3Q19) return SC_E_UNSUPPORTED;
+    if (p->forcing != SC_GUO && p->forcing != SC_EDM) return SC_E_INVAL;
+    if (p->forcing == SC_EDM && (dim != 2 || p->collision != SC_SRT)) return SC_E_UNSUPPORTED;
+    if (p->psi_kind == SC_PSI_PR) {
+        const double v[5] = {p->eos_a, p->eos_b, p->eos_R, p->eos_T, p->eos_alpha};
+        for (double x : v)
+            if (!std::isfinite(x)) return SC_E_INVAL;
+        if (!(p->eos_b > 0.0) || !(p->eos_R > 0.0) || !(p->eos_T > 0.0) || p->eos_a < 0.0 || p->eos_alpha < 0.0)
+            return SC_E_INVAL;
+        if (!(p->G * p->c0 != 0.0)) return SC_E_INVAL;
+    }
     if (p->precision != SC_FP32_SHIFTED && p->precision != SC_FP64) return SC_E_INVAL;
     if (!std::isfinite(p->G) || !std::isfinite(p->c0) || !std::isfinite(p->rho_ref)) return SC_E_INVAL;
     if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return SC_E_INVAL;
@@ -119,30 +185,39 @@ static int validate(const sc_lbm_params* p)
         if (!(p->s_bulk > 0.0 && p->s_bulk < 2.0) || !(p->s_ghost > 0.0 && p->s_ghost < 2.0)) return SC_E_INVAL;
     }
     if (p->obs_every < 0) return SC_E_INVAL;
-    const int nv = p->lattice == SC_D2Q9 ? num_variants_d2q9() : num_variants_d3q19();
-    if (p->variant < -1 || p->variant >= nv) return SC_E_INVAL;
+    return SC_OK;
+}
+
+static int validate(const sc_lbm_params* p)
+{
+    const int rc = validate_problem(p);
+    if (rc != SC_OK) return rc;
+    if (p->variant < -1 || p->variant >= family_variants(family_of(*p))) return SC_E_INVAL;
     return SC_OK;
 }
 
 extern "C" size_t sc_lbm_state_bytes(const sc_lbm_params* p)
 {
     if (validate(p) != SC_OK) return 0;
-    const size_t q = p->lattice == SC_D2Q9 ? 9 : 19;
+    const size_t q = (size_t)lattice_q(p->lattice);
     const size_t ts = p->precision == SC_FP64 ? 8 : 4;
     return q * (size_t)p->nx * p->ny * p->nz * ts;
 }
 
-extern "C" int sc_lbm_num_variants(int32_t lattice)
+extern "C" int sc_lbm_num_variants(const sc_lbm_params* p)
 {
-    if (lattice == SC_D2Q9) return num_variants_d2q9();
-    if (lattice == SC_D3Q19) return num_variants_d3q19();
-    return 0;
+    if (validate_problem(p) != SC_OK) return 0;
+    return family_variants(family_of(*p));
 }
 
 extern "C" const char* sc_lbm_variant_name(const sc_lbm* h)
 {
     if (!h) return "";
-    return h->p.lattice == SC_D2Q9 ? variant_name_d2q9(h->variant) : variant_name_d3q19(h->variant);
+    switch (family_of(h->p)) {
+    case kFamD2Q9: return variant_name_d2q9(h->variant);
+    case kFamD3Q19: return variant_name_d3q19(h->variant);
+    default: return variant_name_wide(h->variant);
+    }
 }
 
 template <typename T>
@@ -164,18 +239,25 @@ static void fill_args(sc_lbm* h, StepArgs<T>& a)
     a.psi_kind = p.psi_kind;
     a.s_bulk = (T)p.s_bulk;
     a.s_ghost = (T)p.s_ghost;
+    a.cs2 = (T)lattice_cs2(p.lattice);
+    const bool pr = p.psi_kind == SC_PSI_PR;
+    a.eos_RT = (T)(pr ? p.eos_R * p.eos_T : 0.0);
+    a.eos_b = (T)(pr ? p.eos_b : 0.0);
+    a.eos_aa = (T)(pr ? p.eos_a * p.eos_alpha : 0.0);
+    a.eos_k = (T)(pr ? 2.0 / (p.G * p.c0) : 0.0);
 }
 
 // ---- launch-shape autotuning --------------------------------------------
 // Tuned choices are kept per (lattice, order, precision, collision, grid) in
 // process memory and, when SC_LBM_TUNE_CACHE names a file, in that file (one
-// "lattice order precision collision nx ny nz variant ms" line per entry).
+// "lattice order precision collision forcing nx ny nz variant ms" line per
+// entry; entries whose variant is out of range for their family are dropped).
 struct TuneKey {
-    int lattice, order, precision, collision, nx, ny, nz;
+    int lattice, order, precision, collision, forcing, nx, ny, nz;
     bool operator==(const TuneKey& o) const
     {
         return lattice == o.lattice && order == o.order && precision == o.precision && collision == o.collision &&
-               nx == o.nx && ny == o.ny && nz == o.nz;
+               forcing == o.forcing && nx == o.nx && ny == o.ny && nz == o.nz;
     }
 };
 struct TuneEntry {
@@ -189,7 +271,15 @@ static bool g_tune_loaded = false;
 
 static TuneKey tune_key(const sc_lbm_params& p)
 {
-    return TuneKey{p.lattice, p.order, p.precision, p.collision, p.nx, p.ny, p.nz};
+    return TuneKey{p.lattice, p.order, p.precision, p.collision, p.forcing, p.nx, p.ny, p.nz};
+}
+
+static Family family_of_key(const TuneKey& k)
+{
+    sc_lbm_params p{};
+    p.lattice = k.lattice;
+    p.forcing = k.forcing;
+    return family_of(p);
 }
 
 static void tune_load_locked()
@@ -201,9 +291,9 @@ static void tune_load_locked()
     FILE* f = std::fopen(path, "r");
     if (!f) return;
     TuneEntry e;
-    while (std::fscanf(f, "%d %d %d %d %d %d %d %d %lf", &e.k.lattice, &e.k.order, &e.k.precision, &e.k.collision,
-                       &e.k.nx, &e.k.ny, &e.k.nz, &e.variant, &e.ms) == 9)
-        g_tune.push_back(e);
+    while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %lf", &e.k.lattice, &e.k.order, &e.k.precision,
+                       &e.k.collision, &e.k.forcing, &e.k.nx, &e.k.ny, &e.k.nz, &e.variant, &e.ms) == 10)
+        if (e.variant >= 0 && e.variant < family_variants(family_of_key(e.k))) g_tune.push_back(e);
     std::fclose(f);
 }
 
@@ -235,8 +325,8 @@ static void tune_store(const sc_lbm_params& p, int variant, double ms)
     FILE* f = std::fopen(path, "w");
     if (!f) return;
     for (const TuneEntry& e : g_tune)
-        std::fprintf(f, "%d %d %d %d %d %d %d %d %.6g\n", e.k.lattice, e.k.order, e.k.precision, e.k.collision,
-                     e.k.nx, e.k.ny, e.k.nz, e.variant, e.ms);
+        std::fprintf(f, "%d %d %d %d %d %d %d %d %d %.6g\n", e.k.lattice, e.k.order, e.k.precision, e.k.collision,
+                     e.k.forcing, e.k.nx, e.k.ny, e.k.nz, e.variant, e.ms);
     std::fclose(f);
 }
 
@@ -244,8 +334,11 @@ static int auto_variant(const sc_lbm_params& p, int64_t n)
 {
     const int tuned = tune_lookup(p);
     if (tuned >= 0) return tuned;
-    if (p.lattice == SC_D2Q9) return n < (int64_t)1 << 20 ? 2 : 0;
-    return 7;   // march64x8r1h16pf1
+    switch (family_of(p)) {
+    case kFamD2Q9: return n < (int64_t)1 << 20 ? 2 : 0;   // tile32x8r1 / tile64x16r4
+    case kFamD3Q19: return 7;                              // march64x8r1h16pf1
+    default: return n < (int64_t)1 << 20 ? 1 : 0;          // wide32x8r1 / wide64x8r2
+    }
 }
 
 static void release(sc_lbm* h)
@@ -282,8 +375,8 @@ extern "C" int sc_lbm_create(const sc_lbm_params* p, const double* rho_init, voi
     if (!h) return SC_E_NOMEM;
     h->p = *p;
     if (h->p.obs_every == 0) h->p.obs_every = 100;
-    h->dim = p->lattice == SC_D2Q9 ? 2 : 3;
-    h->q = p->lattice == SC_D2Q9 ? 9 : 19;
+    h->dim = lattice_dim(p->lattice);
+    h->q = lattice_q(p->lattice);
     h->n = (int64_t)p->nx * p->ny * p->nz;
     h->tsize = p->precision == SC_FP64 ? 8 : 4;
     h->variant = p->variant >= 0 ? p->variant : auto_variant(*p, h->n);
@@ -373,6 +466,17 @@ extern "C" void* sc_lbm_state_ptr(sc_lbm* h) { return h ? h->f[h->cur] : nullptr
 
 extern "C" void* sc_lbm_stream(sc_lbm* h) { return h ? (void*)h->stream : nullptr; }
 
+template <typename T>
+static hipError_t launch_family(sc_lbm* h, const StepArgs<T>& a)
+{
+    const sc_lbm_params& p = h->p;
+    switch (family_of(p)) {
+    case kFamD2Q9: return launch_step_d2q9(a, p.order, h->variant, h->stream);
+    case kFamD3Q19: return launch_step_d3q19(a, p.order, p.collision == SC_MRT, h->variant, h->stream);
+    default: return launch_step_wide(p.lattice, a, p.order, p.forcing == SC_EDM, h->variant, h->stream);
+    }
+}
+
 // one fused step from f[cur] into f[cur ^ 1] (no swap)
 static hipError_t enqueue_step(sc_lbm* h, int from)
 {
@@ -381,14 +485,12 @@ static hipError_t enqueue_step(sc_lbm* h, int from)
         StepArgs<float> a = h->af;
         a.fin = (const float*)h->f[from];
         a.fout = (float*)h->f[from ^ 1];
-        return p.lattice == SC_D2Q9 ? launch_step_d2q9(a, p.order, h->variant, h->stream)
-                                    : launch_step_d3q19(a, p.order, p.collision == SC_MRT, h->variant, h->stream);
+        return launch_family(h, a);
     }
     StepArgs<double> a = h->ad;
     a.fin = (const double*)h->f[from];
     a.fout = (double*)h->f[from ^ 1];
-    return p.lattice == SC_D2Q9 ? launch_step_d2q9(a, p.order, h->variant, h->stream)
-                                : launch_step_d3q19(a, p.order, p.collision == SC_MRT, h->variant, h->stream);
+    return launch_family(h, a);
 }
 
 static hipError_t build_graph(sc_lbm* h, int from)
@@ -472,7 +574,7 @@ static int observe_core(sc_lbm* h, sc_lbm_obs* o)
     ObsBuffers& b = h->obs.b;
     const sc_lbm_params& p = h->p;
     hipError_t e = launch_macro(p.lattice, p.precision, h->f[h->cur], args_ptr(h), b, h->stream);
-    if (e == hipSuccess) e = launch_force(p.lattice, p.precision, p.order, args_ptr(h), b, true, h->stream);
+    if (e == hipSuccess) e = launch_force(h->dim, p.precision, p.order, args_ptr(h), b, true, h->stream);
     if (e == hipSuccess) e = launch_reduce(h->dim, b, h->n, h->stream);
     double res[8];
     if (e == hipSuccess) e = hipMemcpyAsync(res, b.result, sizeof(res), hipMemcpyDeviceToHost, h->stream);
@@ -497,7 +599,7 @@ static int observe_core(sc_lbm* h, sc_lbm_obs* o)
         psi_pair[0] = psi_pair_f[0];
         psi_pair[1] = psi_pair_f[1];
     }
-    const double cs2 = 1.0 / 3.0;
+    const double cs2 = lattice_cs2(p.lattice);
     pin = cs2 * rin + 0.5 * p.G * p.c0 * psi_pair[0] * psi_pair[0];
     pout = cs2 * rout + 0.5 * p.G * p.c0 * psi_pair[1] * psi_pair[1];
     std::memset(o, 0, sizeof(*o));
@@ -602,7 +704,7 @@ extern "C" int sc_lbm_force(sc_lbm* h, const double* psi_in, double* F_out)
     } else {
         e = launch_macro(p.lattice, p.precision, h->f[h->cur], args_ptr(h), b, h->stream);
     }
-    if (e == hipSuccess) e = launch_force(p.lattice, p.precision, p.order, args_ptr(h), b, false, h->stream);
+    if (e == hipSuccess) e = launch_force(h->dim, p.precision, p.order, args_ptr(h), b, false, h->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(F_out, b.F, sizeof(double) * h->dim * h->n, hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
@@ -749,7 +851,9 @@ extern "C" int sc_lbm_batch_create(const sc_lbm_params* items, int32_t n, const 
     for (int i = 0; i < n; ++i) {
         int rc = validate(&items[i]);
         if (rc != SC_OK) return rc;
-        if (items[i].lattice != SC_D2Q9 || items[i].collision != SC_SRT) return SC_E_UNSUPPORTED;
+        if (items[i].lattice != SC_D2Q9 || items[i].collision != SC_SRT || items[i].forcing != SC_GUO ||
+            items[i].psi_kind == SC_PSI_PR)
+            return SC_E_UNSUPPORTED;
         if (items[i].precision != items[0].precision || items[i].psi_kind != items[0].psi_kind ||
             items[i].psi0 != items[0].psi0 || items[i].rho_psi != items[0].rho_psi ||
             items[i].rho_ref != items[0].rho_ref)
@@ -918,7 +1022,7 @@ extern "C" int sc_lbm_autotune(const sc_lbm_params* p, int32_t steps, int32_t* b
     int rc = validate(p);
     if (rc != SC_OK) return rc;
     if (steps < 1) return SC_E_INVAL;
-    const int nv = p->lattice == SC_D2Q9 ? num_variants_d2q9() : num_variants_d3q19();
+    const int nv = family_variants(family_of(*p));
     int best = -1;
     double bms = 1e300;
     hipEvent_t e0 = nullptr, e1 = nullptr;

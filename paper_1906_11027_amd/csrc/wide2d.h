@@ -1,0 +1,270 @@
+// wide2d.h -- fused step for any 2D lattice of lattice.h (D2Q9, D2Q13,
+// D2Q25), Guo forcing or the exact difference method, for gfx950.
+//
+// The larger velocity sets of Sec. 3 (Table 1) keep the equilibrium and
+// forcing of the nearest-neighbour model with their own weights and cs^2,
+// and stream over distance 2.  The kernel is the tile scheme of the D2Q9
+// path written for a lattice template: a block owns a TX x TY tile, each
+// thread RPT rows of one column;
+//   phase 1  pull the Q values of the owned nodes into registers (reach M =
+//            max |c_i| = 1 or 2, so 2M + 1 wrapped row and column offsets),
+//            form rho and psi, write psi to LDS; then fill the psi halo ring
+//            of the force stencil (radius R) by pulling and summing the ring
+//            nodes' values one node at a time (L2 hits: the neighbouring
+//            tiles' lines);
+//   phase 2  interaction force from LDS (Sec. 2, Eq. (1), summed over +-e
+//            pairs), collision with Guo forcing (Eq. (3)-(4)) or the exact
+//            difference method (Sec. 3), coalesced store at the own address.
+// Ragged tiles: out-of-grid threads still supply wrapped psi and skip the
+// store, so any nx, ny >= 1 works.
+#pragma once
+#include "kernels.h"
+
+namespace sclbm {
+
+template <typename L>
+constexpr int lattice_reach()
+{
+    int m = 0;
+    for (int b = 0; b < L::Q; ++b) {
+        const int ax = L::cx[b] < 0 ? -L::cx[b] : L::cx[b];
+        const int ay = L::cy[b] < 0 ? -L::cy[b] : L::cy[b];
+        if (ax > m) m = ax;
+        if (ay > m) m = ay;
+    }
+    return m;
+}
+
+// byte offsets of the wrapped coordinates v - M ... v + M of an axis of n nodes
+template <int M>
+__device__ __forceinline__ void offsets_m(int v, int n, uint32_t stride, uint32_t (&o)[2 * M + 1])
+{
+#pragma unroll
+    for (int k = 0; k <= 2 * M; ++k) {
+        int c = v - M + k;
+        if (M == 1) {
+            c = c < 0 ? c + n : (c >= n ? c - n : c);
+        } else {
+            c = wrap_any(c, n);
+        }
+        o[k] = (uint32_t)c * stride;
+    }
+}
+
+// value b of node (x, y) comes from (x - cx_b, y - cy_b)
+template <typename T, typename L, int M>
+__device__ __forceinline__ void pull_lat(const T* __restrict__ f, int64_t n, const uint32_t (&xo)[2 * M + 1],
+                                         const uint32_t (&yo)[2 * M + 1], T (&g)[L::Q])
+{
+#pragma unroll
+    for (int b = 0; b < L::Q; ++b) g[b] = ld_off(f + b * n, yo[M - L::cy[b]] + xo[M - L::cx[b]]);
+}
+
+// pairwise sum of g[LO .. LO + N) in a fixed tree order
+template <int LO, int N>
+struct TreeSum {
+    template <typename T, int Q>
+    __device__ __forceinline__ static T of(const T (&g)[Q])
+    {
+        return TreeSum<LO, N / 2>::of(g) + TreeSum<LO + N / 2, N - N / 2>::of(g);
+    }
+};
+template <int LO>
+struct TreeSum<LO, 1> {
+    template <typename T, int Q>
+    __device__ __forceinline__ static T of(const T (&g)[Q])
+    {
+        return g[LO];
+    }
+};
+
+// Collision on shifted values g = f - w rho_ref, drho = rho - rho_ref.
+//   Guo:  u = (j + F/2)/rho,  g* = g - (g - geq(u))/tau + (1 - 1/(2 tau)) phihat(u, F)
+//   EDM:  v = j/rho, dv = F/rho,  g* = g - (g - geq(v))/tau + feq(v + dv) - feq(v)
+// with feq = w rho [1 + c.u/cs2 + (c.u)^2/(2 cs2^2) - u^2/(2 cs2)] and
+// phihat = w [(c - u)/cs2 + (c.u) c / cs2^2] . F.  The EDM increment is
+// expanded as a difference (c.dv (2 c.v + c.dv) etc.) so it carries no
+// cancellation of two equilibria.  Both conserve mass exactly; the rest
+// population closes the balance so rounding leaves no drift.
+template <typename T, typename L, bool EDM>
+__device__ __forceinline__ void collide_lat(T (&g)[L::Q], T drho, T Fx, T Fy, const StepArgs<T>& a)
+{
+    constexpr int Q = L::Q;
+    const T rho = a.rho_ref + drho;
+    T jx = T(0), jy = T(0);
+#pragma unroll
+    for (int b = 1; b < Q; ++b) {
+        if (L::cx[b]) jx += T(L::cx[b]) * g[b];
+        if (L::cy[b]) jy += T(L::cy[b]) * g[b];
+    }
+    const T inv = T(1) / rho;
+    constexpr double ics = 1.0 / L::cs2;
+    constexpr double ics2h = 0.5 / (L::cs2 * L::cs2);
+    const T om = a.omega;
+    if (!EDM) {
+        const T ux = (jx + T(0.5) * Fx) * inv;
+        const T uy = (jy + T(0.5) * Fy) * inv;
+        const T usq = T(0.5 * ics) * (ux * ux + uy * uy);
+        const T uF = ux * Fx + uy * Fy;
+        const T gu = a.guo;
+#pragma unroll
+        for (int b = 0; b < Q; ++b) {
+            const T cu = T(L::cx[b]) * ux + T(L::cy[b]) * uy;
+            const T cF = T(L::cx[b]) * Fx + T(L::cy[b]) * Fy;
+            const T w = T(L::w[b]);
+            const T geq = w * (drho + rho * (T(ics) * cu + T(ics2h) * cu * cu - usq));
+            const T phi = gu * w * (T(ics) * (cF - uF) + T(2.0 * ics2h) * cu * cF);
+            g[b] = g[b] - om * (g[b] - geq) + phi;
+        }
+    } else {
+        const T vx = jx * inv, vy = jy * inv;
+        const T dx = Fx * inv, dy = Fy * inv;
+        const T vsq = T(0.5 * ics) * (vx * vx + vy * vy);
+        const T dsq = T(0.5 * ics) * (dx * (T(2) * vx + dx) + dy * (T(2) * vy + dy));
+#pragma unroll
+        for (int b = 0; b < Q; ++b) {
+            const T cv = T(L::cx[b]) * vx + T(L::cy[b]) * vy;
+            const T cd = T(L::cx[b]) * dx + T(L::cy[b]) * dy;
+            const T w = T(L::w[b]);
+            const T geq = w * (drho + rho * (T(ics) * cv + T(ics2h) * cv * cv - vsq));
+            const T dfe = w * rho * (T(ics) * cd + T(ics2h) * cd * (T(2) * cv + cd) - dsq);
+            g[b] = g[b] - om * (g[b] - geq) + dfe;
+        }
+    }
+    g[0] = drho - TreeSum<1, Q - 1>::of(g);
+}
+
+template <typename T, typename L, int ORDER, bool EDM, int TX, int TY, int RPT>
+__global__ void __launch_bounds__(TX*(TY / RPT))
+k_wide_tile(StepArgs<T> a, int nbx)
+{
+    using ST = Stencil<2, ORDER>;
+    constexpr int Q = L::Q;
+    constexpr int M = lattice_reach<L>();
+    constexpr int R = ST::R;
+    constexpr int LW = TX + 2 * R;
+    constexpr int LH = TY + 2 * R;
+    constexpr int NT = TX * (TY / RPT);
+    constexpr int RING = LH * LW - TX * TY;
+    __shared__ T psi_s[LH * LW];
+
+    const int nx = a.nx, ny = a.ny;
+    const int64_t n = a.n;
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int tid = ty * TX + tx;
+    const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int x0 = (blk % nbx) * TX, y0 = (blk / nbx) * TY;
+
+    const uint32_t TS = sizeof(T), rowb = (uint32_t)nx * TS;
+    const int xr = x0 + tx;
+    const bool xin = xr < nx;
+    uint32_t xo[2 * M + 1];
+    offsets_m<M>(xin ? xr : xr % nx, nx, TS, xo);
+
+    T g[RPT][Q];
+    uint32_t own[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int yr = y0 + ty * RPT + k;
+        uint32_t yo[2 * M + 1];
+        offsets_m<M>(yr < ny ? yr : yr % ny, ny, rowb, yo);
+        own[k] = yo[M] + xo[M];
+        pull_lat<T, L, M>(a.fin, n, xo, yo, g[k]);
+    }
+    T dr[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        dr[k] = TreeSum<0, Q>::of(g[k]);
+        psi_s[(ty * RPT + k + R) * LW + tx + R] = psi_of(a.rho_ref + dr[k], a);
+    }
+    // halo ring: R rows above and below at full width, R columns each side
+#pragma unroll 1
+    for (int i = tid; i < RING; i += NT) {
+        int lx, ly;
+        if (i < R * LW) {
+            ly = i / LW;
+            lx = i - ly * LW;
+        } else if (i < 2 * R * LW) {
+            const int j = i - R * LW;
+            ly = TY + R + j / LW;
+            lx = j % LW;
+        } else {
+            const int j = i - 2 * R * LW;
+            ly = R + j / (2 * R);
+            const int c = j % (2 * R);
+            lx = c < R ? c : TX + c;
+        }
+        uint32_t hxo[2 * M + 1], hyo[2 * M + 1];
+        offsets_m<M>(wrap_any(x0 - R + lx, nx), nx, TS, hxo);
+        offsets_m<M>(wrap_any(y0 - R + ly, ny), ny, rowb, hyo);
+        T h[Q];
+        pull_lat<T, L, M>(a.fin, n, hxo, hyo, h);
+        psi_s[ly * LW + lx] = psi_of(a.rho_ref + TreeSum<0, Q>::of(h), a);
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int ly = ty * RPT + k;
+        const T* c = psi_s + (ly + R) * LW + tx + R;
+        T sx = T(0), sy = T(0);
+#pragma unroll
+        for (int p = 0; p < ST::NP; ++p) {
+            constexpr PairList P = ST::P;
+            const int ex = P.e[p][0], ey = P.e[p][1];
+            const T d = c[ey * LW + ex] - c[-ey * LW - ex];
+            const T wd = T(P.w[p]) * d;
+            if (ex) sx += T(ex) * wd;
+            if (ey) sy += T(ey) * wd;
+        }
+        const T pref = -a.gc0 * c[0];
+        collide_lat<T, L, EDM>(g[k], dr[k], pref * sx, pref * sy, a);
+        if (xin && y0 + ly < ny) {
+#pragma unroll
+            for (int b = 0; b < Q; ++b) st_off(a.fout + b * n, own[k], g[k][b]);
+        }
+    }
+}
+
+// Launch shapes of the any-lattice family (names as variant_name_wide()).
+template <typename T, typename L, int ORDER, bool EDM, int TX, int TY, int RPT>
+static hipError_t launch_wide_tile(const StepArgs<T>& a, hipStream_t s)
+{
+    const int nbx = (a.nx + TX - 1) / TX, nby = (a.ny + TY - 1) / TY;
+    hipLaunchKernelGGL((k_wide_tile<T, L, ORDER, EDM, TX, TY, RPT>), dim3(nbx * nby), dim3(TX, TY / RPT), 0, s, a,
+                       nbx);
+    return hipGetLastError();
+}
+
+template <typename T, typename L, int ORDER, bool EDM>
+static hipError_t launch_wide_shape(const StepArgs<T>& a, int variant, hipStream_t s)
+{
+    switch (variant) {
+    case 0: return launch_wide_tile<T, L, ORDER, EDM, 64, 8, 2>(a, s);
+    case 1: return launch_wide_tile<T, L, ORDER, EDM, 32, 8, 1>(a, s);
+    case 2: return launch_wide_tile<T, L, ORDER, EDM, 64, 16, 4>(a, s);
+    case 3: return launch_wide_tile<T, L, ORDER, EDM, 64, 16, 2>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, typename L, bool EDM>
+static hipError_t launch_wide_order(const StepArgs<T>& a, int order, int variant, hipStream_t s)
+{
+    switch (order) {
+    case 4: return launch_wide_shape<T, L, 4, EDM>(a, variant, s);
+    case 6: return launch_wide_shape<T, L, 6, EDM>(a, variant, s);
+    case 8: return launch_wide_shape<T, L, 8, EDM>(a, variant, s);
+    case 10: return launch_wide_shape<T, L, 10, EDM>(a, variant, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, typename L>
+static hipError_t launch_wide_lattice(const StepArgs<T>& a, int order, bool edm, int variant, hipStream_t s)
+{
+    return edm ? launch_wide_order<T, L, true>(a, order, variant, s)
+               : launch_wide_order<T, L, false>(a, order, variant, s);
+}
+
+}  // namespace sclbm

@@ -18,13 +18,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsc_lbm.so")
 
 SC_OK, SC_E_INVAL, SC_E_NOMEM, SC_E_DEVICE, SC_E_UNSUPPORTED, SC_E_NONFINITE = 0, -1, -2, -3, -4, -5
-SC_D2Q9, SC_D3Q19 = 0, 1
-SC_PSI_EXP, SC_PSI_IDENTITY = 0, 1
+SC_D2Q9, SC_D3Q19, SC_D2Q13, SC_D2Q25 = 0, 1, 2, 3
+SC_PSI_EXP, SC_PSI_IDENTITY, SC_PSI_PR = 0, 1, 2
+SC_GUO, SC_EDM = 0, 1
 SC_SRT, SC_MRT = 0, 1
 SC_FP32_SHIFTED, SC_FP64 = 0, 1
 
-LATTICE = {"D2Q9": SC_D2Q9, "D3Q19": SC_D3Q19}
-Q = {SC_D2Q9: 9, SC_D3Q19: 19}
+LATTICE = {"D2Q9": SC_D2Q9, "D3Q19": SC_D3Q19, "D2Q13": SC_D2Q13, "D2Q25": SC_D2Q25}
+Q = {SC_D2Q9: 9, SC_D3Q19: 19, SC_D2Q13: 13, SC_D2Q25: 25}
 
 
 class sc_lbm_params(ctypes.Structure):
@@ -35,7 +36,9 @@ class sc_lbm_params(ctypes.Structure):
         ("rho_psi", ctypes.c_double), ("tau", ctypes.c_double),
         ("collision", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("s_bulk", ctypes.c_double), ("s_ghost", ctypes.c_double), ("rho_ref", ctypes.c_double),
-        ("obs_every", ctypes.c_int32), ("variant", ctypes.c_int32),
+        ("obs_every", ctypes.c_int32), ("variant", ctypes.c_int32), ("forcing", ctypes.c_int32),
+        ("eos_a", ctypes.c_double), ("eos_b", ctypes.c_double), ("eos_R", ctypes.c_double),
+        ("eos_T", ctypes.c_double), ("eos_alpha", ctypes.c_double),
     ]
 
 
@@ -74,7 +77,11 @@ VELOCITIES = {
     SC_D3Q19: [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
                (1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0), (1, 0, 1), (-1, 0, -1),
                (1, 0, -1), (-1, 0, 1), (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)],
+    SC_D2Q13: [(0, 0), (-1, 0), (0, -1), (0, 1), (1, 0), (-1, -1), (-1, 1), (1, -1), (1, 1),
+               (-2, 0), (0, -2), (0, 2), (2, 0)],
 }
+VELOCITIES[SC_D2Q25] = VELOCITIES[SC_D2Q13] + [(-2, -1), (-2, 1), (-1, -2), (-1, 2), (1, -2), (1, 2), (2, -1),
+                                               (2, 1), (-2, -2), (-2, 2), (2, -2), (2, 2)]
 
 _lib = None
 
@@ -115,7 +122,7 @@ def lib():
     L.sc_lbm_state_ptr.restype = vp
     L.sc_lbm_variant_name.argtypes = [vp]
     L.sc_lbm_variant_name.restype = ctypes.c_char_p
-    L.sc_lbm_num_variants.argtypes = [ctypes.c_int32]
+    L.sc_lbm_num_variants.argtypes = [P(sc_lbm_params)]
     L.sc_lbm_num_variants.restype = ctypes.c_int
     L.sc_lbm_destroy.argtypes = [vp]
     L.sc_lbm_destroy.restype = None
@@ -242,8 +249,9 @@ def sc_lbm_variant_name(h):
     return lib().sc_lbm_variant_name(h).decode()
 
 
-def sc_lbm_num_variants(lattice):
-    return lib().sc_lbm_num_variants(lattice)
+def sc_lbm_num_variants(p):
+    """Launch shapes of the kernel family serving parameter set p."""
+    return lib().sc_lbm_num_variants(ctypes.byref(p))
 
 
 def sc_lbm_destroy(h):
@@ -260,14 +268,18 @@ def sc_lbm_strerror(code):
 
 def make_params(lattice="D2Q9", shape=(64, 64), order=4, G=-5.0, c0=1.0 / 3.0, psi="exp",
                 psi0=1.0, rho_psi=1.0, tau=1.0, collision="srt", precision="fp32",
-                s_bulk=1.2, s_ghost=1.2, rho_ref=1.0, obs_every=100, variant=-1):
+                s_bulk=1.2, s_ghost=1.2, rho_ref=1.0, obs_every=100, variant=-1, forcing="guo", eos=None):
+    """eos: for psi == "pr", a dict with a, b, R, T (absolute) and alpha."""
     p = sc_lbm_default_params()
     p.lattice = LATTICE[lattice]
     shape = tuple(int(s) for s in shape)
     p.nx, p.ny = shape[0], shape[1]
     p.nz = shape[2] if len(shape) > 2 else 1
     p.order = order
-    p.psi_kind = {"exp": SC_PSI_EXP, "identity": SC_PSI_IDENTITY}[psi]
+    p.psi_kind = {"exp": SC_PSI_EXP, "identity": SC_PSI_IDENTITY, "pr": SC_PSI_PR}[psi]
+    p.forcing = {"guo": SC_GUO, "edm": SC_EDM}[forcing]
+    if eos:
+        p.eos_a, p.eos_b, p.eos_R, p.eos_T, p.eos_alpha = eos["a"], eos["b"], eos["R"], eos["T"], eos["alpha"]
     p.G, p.c0, p.psi0, p.rho_psi, p.tau = G, c0, psi0, rho_psi, tau
     p.collision = {"srt": SC_SRT, "mrt": SC_MRT}[collision]
     p.precision = {"fp32": SC_FP32_SHIFTED, "fp64": SC_FP64}[precision]
@@ -300,6 +312,11 @@ class Sim:
             import torch
             nbytes = sc_lbm_state_bytes(self.p)
             if nbytes == 0:
+                # invalid parameters: sc_lbm_create validates first and
+                # returns the precise code without touching the device
+                h = ctypes.c_void_p()
+                _check(lib().sc_lbm_create(ctypes.byref(self.p), None, None, None, None, ctypes.byref(h)),
+                       "sc_lbm_create")
                 raise ScError(SC_E_INVAL, "sc_lbm_state_bytes")
             self._bufs = [torch.empty(nbytes, dtype=torch.uint8, device="cuda") for _ in range(2)]
             dev_a, dev_b = self._bufs[0].data_ptr(), self._bufs[1].data_ptr()

@@ -12,10 +12,17 @@ def lib_velocities(sim):
     return np.array(B.VELOCITIES[sim.p.lattice], dtype=np.int64)
 
 
+# lattice weights by |c|^2 (Sec. 3, Table 1; D3Q19 the standard set)
+_W = {"D2Q9": {0: 4 / 9, 1: 1 / 9, 2: 1 / 36},
+      "D2Q13": {0: 2 / 5, 1: 8 / 75, 2: 1 / 25, 4: 1 / 300},
+      "D2Q25": {0: 72 / 245, 1: 16 / 147, 2: 16 / 315, 4: 1 / 105, 5: 8 / 2205, 8: 1 / 8820},
+      "D3Q19": {0: 1 / 3, 1: 1 / 18, 2: 1 / 36}}
+
+
 def lib_weights(lattice):
-    if lattice == "D2Q9":
-        return np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
-    return np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+    """Weights in the library's velocity order."""
+    vel = B.VELOCITIES[B.LATTICE[lattice]]
+    return np.array([_W[lattice][sum(c * c for c in v)] for v in vel])
 
 
 def pre_collision_from_state(sim, oracle_c):

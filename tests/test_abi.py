@@ -101,5 +101,10 @@ def test_single_buffer_rejected():
 def test_strerror():
     for code in (0, -1, -2, -3, -4, -5, -99):
         assert B.sc_lbm_strerror(code)
-    assert B.sc_lbm_num_variants(B.SC_D2Q9) >= 1
-    assert B.sc_lbm_num_variants(B.SC_D3Q19) >= 1
+    n9 = B.sc_lbm_num_variants(B.make_params("D2Q9"))
+    n19 = B.sc_lbm_num_variants(B.make_params("D3Q19", (8, 8, 8)))
+    nw = B.sc_lbm_num_variants(B.make_params("D2Q25"))
+    assert n9 >= 1 and n19 >= 1 and nw >= 1
+    # D2Q9 with the exact difference method runs in the any-lattice family
+    assert B.sc_lbm_num_variants(B.make_params("D2Q9", forcing="edm")) == nw
+    assert B.sc_lbm_num_variants(B.make_params("D2Q9", order=5)) == 0

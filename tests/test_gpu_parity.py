@@ -82,7 +82,7 @@ def test_d2q9_variants(order):
     rho0 = droplet_rho((100, 77), 20, seed=9)
     orc = O.Oracle(rho0, "D2Q9", order=order).step(25)
     ref = None
-    for v in range(B.sc_lbm_num_variants(B.SC_D2Q9)):
+    for v in range(B.sc_lbm_num_variants(B.make_params("D2Q9"))):
         sim = Sim(rho0, "D2Q9", order=order, variant=v, precision="fp64")
         sim.step(25)
         _compare(sim, orc, "fp64", "variant %s" % sim.variant)
@@ -176,7 +176,7 @@ def test_d3q19_droplet(order, collision):
 def test_d3q19_variants_bitwise():
     rho0 = droplet_rho((40, 21, 35), 8, seed=4)
     ref = None
-    for v in range(B.sc_lbm_num_variants(B.SC_D3Q19)):
+    for v in range(B.sc_lbm_num_variants(B.make_params("D3Q19", (8, 8, 8)))):
         sim = Sim(rho0, "D3Q19", order=8, collision="mrt", variant=v)
         sim.step(6)
         st = sim.state()
@@ -354,10 +354,10 @@ def test_batch_convergence_and_quarantine():
 def test_autotune_picks_a_variant_and_is_used():
     p = B.make_params("D2Q9", (96, 80), order=6)
     v, ms = B.sc_lbm_autotune(p, steps=10)
-    assert 0 <= v < B.sc_lbm_num_variants(B.SC_D2Q9) and ms > 0
+    assert 0 <= v < B.sc_lbm_num_variants(p) and ms > 0
     sim = Sim(droplet_rho((96, 80), 20, seed=1), "D2Q9", order=6)
     names = []
-    for k in range(B.sc_lbm_num_variants(B.SC_D2Q9)):
+    for k in range(B.sc_lbm_num_variants(p)):
         s2 = Sim(np.ones((96, 80)), "D2Q9", order=6, variant=k)
         names.append(s2.variant)
         s2.close()
