@@ -9,8 +9,10 @@ interaction force, Guo-forced collision and pull streaming over the grid;
 MLUPS = nodes x steps / time, with the state resident in HBM.
 
 Also reported (same JSON line, key "extra"): the 128^3 D3Q19 MRT E8 droplet,
-the HBM-bound grids 8192^2 (D2Q9 E8) and 320^3 (D3Q19 MRT E8), and the wall
-time of a 64^2 E4 droplet run to its steady state.
+the HBM-bound grids 8192^2 (D2Q9 E8) and 320^3 (D3Q19 MRT E8), the larger
+lattices of Sec. 3 at 8192^2 (D2Q13 E6 and D2Q25 E8 with the Peng-Robinson
+psi and the exact difference method), the wall time of a 64^2 E4 droplet run
+to its steady state and the batched 64-droplet sweep.
 
 Timing: HIP events on the library's stream around K graph-replayed steps,
 bracketed by device synchronisation.  The roofline uses the fused kernel's
@@ -45,7 +47,19 @@ WORKLOADS = {
     "d3q19_mrt_e8_320": dict(lattice="D3Q19", shape=(320, 320, 320), order=8, R=64, seed=8,
                              collision="mrt",
                              desc="D3Q19 MRT 320^3, E8, droplet R=64, FP32 (HBM-bound size)"),
+    # the larger lattices of Sec. 3 in the paper's own set-up: Peng-Robinson
+    # psi at T/Tc = 0.85, exact difference method, droplet at the Maxwell
+    # densities, at an HBM-bound size
+    "d2q13_e6_pr_edm_8192": dict(lattice="D2Q13", shape=(8192, 8192), order=6, R=1600, seed=9, collision="srt",
+                                 pr=0.85, forcing="edm", tau=11.0 / 12.0,
+                                 desc="D2Q13 SRT 8192^2, E6, P-R psi T/Tc=0.85, EDM, tau=11/12, droplet "
+                                      "R=1600, FP32"),
+    "d2q25_e8_pr_edm_8192": dict(lattice="D2Q25", shape=(8192, 8192), order=8, R=1600, seed=10, collision="srt",
+                                 pr=0.85, forcing="edm", tau=19.0 / 24.0,
+                                 desc="D2Q25 SRT 8192^2, E8, P-R psi T/Tc=0.85, EDM, tau=19/24, droplet "
+                                      "R=1600, FP32"),
 }
+Q_OF = {"D2Q9": 9, "D3Q19": 19, "D2Q13": 13, "D2Q25": 25}
 
 
 def log(*a):
@@ -53,27 +67,39 @@ def log(*a):
 
 
 def bytes_per_node(lattice):
-    q = 9 if lattice == "D2Q9" else 19
-    return 2 * q * 4   # read Q + write Q FP32 values (algorithmic traffic)
+    return 2 * Q_OF[lattice] * 4   # read Q + write Q FP32 values (algorithmic traffic)
+
+
+def sim_kwargs(w):
+    """Library parameters of a workload (exp psi unless it names a P-R
+    reduced temperature) and its initial density field."""
+    from paper_1906_11027_amd import eos as P
+    from workload import droplet_rho
+
+    kw = dict(order=w["order"], collision=w["collision"], forcing=w.get("forcing", "guo"), tau=w.get("tau", 1.0))
+    dens = {}
+    if "pr" in w:
+        e = P.params_at(w["pr"])
+        rv, rl = P.maxwell(e)
+        kw.update(psi="pr", eos=e, G=-1.0)
+        dens = dict(rho_l=rl, rho_v=rv)
+    rho0 = droplet_rho(w["shape"], w["R"], seed=w["seed"], **dens)
+    return kw, rho0
 
 
 def measure(name, steps, warmup, kernel_launches=50):
     import torch
 
     from paper_1906_11027_amd import Sim
-    from workload import droplet_rho
-
     from paper_1906_11027_amd import sc_lbm as B
 
     w = WORKLOADS[name]
+    kw, rho0 = sim_kwargs(w)
     # pick the launch shape by timing every candidate (cached for variant -1)
-    tuned = B.sc_lbm_autotune(B.make_params(w["lattice"], w["shape"], order=w["order"],
-                                            collision=w["collision"]), steps=20)
+    tuned = B.sc_lbm_autotune(B.make_params(w["lattice"], w["shape"], **kw), steps=20)
     log("autotune %s: variant %d, %.4f ms/step" % (name, tuned[0], tuned[1]))
-    rho0 = droplet_rho(w["shape"], w["R"], seed=w["seed"])
     stream = torch.cuda.Stream()
-    sim = Sim(rho0, w["lattice"], order=w["order"], collision=w["collision"], precision="fp32",
-              stream=stream)
+    sim = Sim(rho0, w["lattice"], precision="fp32", stream=stream, **kw)
     assert sim.stream == stream.cuda_stream, "library is not on the timed stream"
     n = rho0.size
     del rho0
@@ -223,7 +249,8 @@ def main():
     log("main:", json.dumps(main_r))
     extra = {}
     if not args.no_extra:
-        for name, st in (("d3q19_mrt_e8_128", 200), ("d2q9_e8_8192", 100), ("d3q19_mrt_e8_320", 40)):
+        for name, st in (("d3q19_mrt_e8_128", 200), ("d2q9_e8_8192", 100), ("d3q19_mrt_e8_320", 40),
+                         ("d2q13_e6_pr_edm_8192", 40), ("d2q25_e8_pr_edm_8192", 30)):
             if name == args.workload:
                 continue
             r = measure(name, st, 10, kernel_launches=10)

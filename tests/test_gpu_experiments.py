@@ -1,0 +1,90 @@
+"""The measurements of Sec. 3 through the library (experiments.py): the
+steady droplet's spurious currents and the flat interface, checked against
+the FP64 oracle run for the same number of steps, against the mechanical
+balance a flat interface must satisfy, and against the paper's
+qualitative findings (Sec. 3, Fig. 4-6)."""
+import warnings
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from tests.gpu_helpers import say
+
+pytestmark = pytest.mark.gpu
+warnings.simplefilter("ignore")
+
+torch = pytest.importorskip("torch")
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1906_11027_amd import eos as P  # noqa: E402
+from paper_1906_11027_amd import experiments as X  # noqa: E402
+
+
+def _oracle_run(model, Tr, rho0, steps):
+    lattice, order, tau = X.MODELS[model]
+    e = P.params_at(Tr)
+    o = O.Oracle(rho0, lattice, order=order, tau=tau, G=-1.0, psi="pr", eos=e, forcing="edm")
+    o.step(steps)
+    return o
+
+
+@pytest.mark.parametrize("model", ["D2Q9-ISO4", "D2Q25T"])
+def test_steady_droplet_matches_oracle(model):
+    """GPU steady droplet (60 x 60, r0 = 15, T/Tc = 0.85) vs the oracle run
+    for the same number of steps: spurious max / mean |u| to 1e-9."""
+    Tr = 0.85
+    d = X.droplet(model, Tr)
+    say(model, d)
+    assert d["converged"] and not d["diverged"]
+    rv, rl = P.maxwell(P.params_at(Tr))
+    o = _oracle_run(model, Tr, X.droplet_init((60, 60), 15.0, rl, rv, 4.0), d["steps"])
+    ob = o.observables()
+    say("oracle", ob["max_u"], ob["mean_u"])
+    assert abs(d["max_u"] - ob["max_u"]) < 1e-9 * ob["max_u"]
+    assert abs(d["mean_u"] - ob["mean_u"]) < 1e-9 * ob["mean_u"]
+
+
+def test_spurious_current_ordering():
+    """Fig. 4: at T/Tc = 0.725 and 0.85 the larger lattices cut the spurious
+    speed by about an order of magnitude below Shan's E8 improvement, which
+    itself helps only modestly over E4."""
+    for Tr in (0.725, 0.85):
+        m = {k: X.droplet(k, Tr)["max_u"] for k in ("D2Q9-ISO4", "D2Q9-ISO8", "D2Q13T", "D2Q25T", "D2Q25V")}
+        say(Tr, m)
+        assert m["D2Q9-ISO8"] < m["D2Q9-ISO4"] < 4 * m["D2Q9-ISO8"]
+        assert m["D2Q13T"] < m["D2Q9-ISO8"] / 4
+        assert m["D2Q25T"] < m["D2Q9-ISO8"] / 8 and m["D2Q25V"] < m["D2Q9-ISO8"] / 8
+
+
+def test_flat_interface_balance_thickness_and_oracle():
+    """Flat interface at T/Tc = 0.85: the steady bulk densities satisfy
+    p(rho_l) = p(rho_v) (the normal pressure is uniform across a flat
+    interface), the interface is thicker on the larger stencils (Fig. 6),
+    and a short slab matches the oracle pointwise after 20000 steps."""
+    Tr = 0.85
+    e = P.params_at(Tr)
+    res = {m: X.flat_interface(m, Tr) for m in ("D2Q9-ISO4", "D2Q9-ISO8", "D2Q13T", "D2Q25T")}
+    for m, r in res.items():
+        say(m, r)
+        assert r["converged"]
+        pl, pv = P.pressure(r["rho_l"], e), P.pressure(r["rho_v"], e)
+        assert abs(pl - pv) < 1e-6 * abs(pv)
+    th = {m: r["thickness"] for m, r in res.items()}
+    assert th["D2Q9-ISO4"] < th["D2Q9-ISO8"] < th["D2Q25T"]
+    assert th["D2Q13T"] < th["D2Q25T"]
+    # pointwise against the oracle on a short slab
+    rv, rl = P.maxwell(e)
+    rho0 = X.slab_init(80, 4, 40.0, rl, rv, 4.0)
+    from paper_1906_11027_amd import Sim
+    lattice, order, tau = X.MODELS["D2Q13T"]
+    sim = Sim(rho0, lattice, order=order, tau=tau, G=-1.0, psi="pr", eos=e, forcing="edm", precision="fp64")
+    sim.step(20000)
+    g = sim.observe()["rho"]
+    sim.close()
+    o = _oracle_run("D2Q13T", Tr, rho0, 20000)
+    err = float(np.max(np.abs(g - o.fields()["rho"]) / o.fields()["rho"]))
+    say("slab D2Q13T 20000 steps rel err", err)
+    assert err < 1e-10
