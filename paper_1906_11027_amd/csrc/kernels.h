@@ -31,6 +31,18 @@ struct StepArgs {
     T eos_k;                     // 2 / (G c0)
 };
 
+// exp, 1/x and sqrt for the hot kernels.  The FP32 state uses the hardware
+// instructions (v_exp_f32 computes 2^x, so exp(x) = 2^(x log2 e); v_rcp_f32,
+// v_sqrt_f32; each within 1 ulp): a few operations instead of the
+// correctly rounded sequences, well inside the FP32 state's own rounding.
+// The FP64 state keeps the correctly rounded forms.
+__device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+__device__ __forceinline__ double fast_exp(double x) { return exp(x); }
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fast_sqrt(double x) { return sqrt(x); }
+
 // Pseudo-potential.  The Peng-Robinson form inverts the bulk pressure of the
 // model, p = cs2 rho + G c0 psi^2 / 2 (Sec. 3):
 //   psi = sqrt(2 (p_PR(rho) - cs2 rho) / (G c0)),  0 where the root is not real.
@@ -40,17 +52,26 @@ __device__ __forceinline__ T psi_of(T rho, const StepArgs<T>& a)
     if (a.psi_kind == 1) return rho;
     if (a.psi_kind == 2) {
         const T br = a.eos_b * rho;
-        const T p = rho * a.eos_RT / (T(1) - br) - a.eos_aa * rho * rho / (T(1) + T(2) * br - br * br);
+        const T p = rho * a.eos_RT * fast_rcp(T(1) - br) -
+                    a.eos_aa * rho * rho * fast_rcp(T(1) + T(2) * br - br * br);
         const T arg = (p - a.cs2 * rho) * a.eos_k;
-        return arg > T(0) ? sqrt(arg) : T(0);
+        return arg > T(0) ? fast_sqrt(arg) : T(0);
     }
-    return a.psi0 * (T(1) - exp(-rho * a.inv_rho_psi));
+    return a.psi0 * (T(1) - fast_exp(-rho * a.inv_rho_psi));
 }
 
 __device__ __forceinline__ int wrap_any(int v, int n)
 {
     int r = v % n;
     return r < 0 ? r + n : r;
+}
+
+// v mod n for v at most one period outside [0, n) without a division (halo
+// coordinates of grids wider than the halo); any other v takes wrap_any.
+__device__ __forceinline__ int wrap_near(int v, int n)
+{
+    const int r = v < 0 ? v + n : (v >= n ? v - n : v);
+    return (r >= 0 && r < n) ? r : wrap_any(v, n);
 }
 
 // XCD-aware block order.  Work-groups are dealt round-robin to the 8 XCDs
@@ -63,6 +84,31 @@ __device__ __forceinline__ int xcd_swizzle(int b, int nb)
     const int q = nb >> 3, r = nb & 7;
     const int x = b & 7, i = b >> 3;
     return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// Logical tile order of the 2D tile kernels: vertical strips of `sw` tile
+// columns, tiles advancing along x within a strip row, strip rows down y,
+// strips one after another.  The tile below a tile then starts `sw` tiles
+// later on the same XCD (xcd_swizzle keeps logical ranges together), so the
+// halo rows the two share are still in that XCD's L2; in plain row-major
+// order a full-width tile row of a large grid evicts them first.  A
+// bijection from [0, nbx * nby) onto the tile grid for any sw >= 1.
+constexpr int kStripTiles = 8;   // tile columns per strip
+
+__device__ __forceinline__ void strip_tile(int L, int nbx, int nby, int sw, int& bx, int& by)
+{
+    const int full = nbx / sw;
+    const int per = sw * nby;
+    if (L < full * per) {
+        const int s = L / per, r = L - s * per;
+        by = r / sw;
+        bx = s * sw + (r - by * sw);
+    } else {
+        const int tw = nbx - full * sw;   // width of the last, narrower strip
+        const int r = L - full * per;
+        by = r / tw;
+        bx = full * sw + (r - by * tw);
+    }
 }
 
 // Addressing of the hot kernels: one velocity plane holds N values, fewer
@@ -116,7 +162,7 @@ __device__ __forceinline__ void collide_d2q9_srt(T (&g)[9], T drho, T Fx, T Fy, 
     const T rho = a.rho_ref + drho;
     const T jx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
     const T jy = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
-    const T inv = T(1) / rho;
+    const T inv = fast_rcp(rho);
     const T ux = (jx + T(0.5) * Fx) * inv;
     const T uy = (jy + T(0.5) * Fy) * inv;
     const T usq = T(1.5) * (ux * ux + uy * uy);
@@ -181,7 +227,7 @@ __device__ __forceinline__ void collide_d3q19(T (&g)[19], T drho, T Fx, T Fy, T 
         if (L::cy[b] > 0) jy += g[b]; else if (L::cy[b] < 0) jy -= g[b];
         if (L::cz[b] > 0) jz += g[b]; else if (L::cz[b] < 0) jz -= g[b];
     }
-    const T inv = T(1) / rho;
+    const T inv = fast_rcp(rho);
     const T ux = (jx + T(0.5) * Fx) * inv;
     const T uy = (jy + T(0.5) * Fy) * inv;
     const T uz = (jz + T(0.5) * Fz) * inv;

@@ -16,23 +16,27 @@
 
 namespace sclbm {
 
+template <int ORDER, int TX, int TY>
+struct TileLds {
+    static constexpr int R = Stencil<2, ORDER>::R;
+    static constexpr int LW = TX + 2 * R;
+    static constexpr int LH = TY + 2 * R;
+};
+
+// One tile of the fused step (both phases); psi_s holds LH x LW values.
 template <typename T, int ORDER, int TX, int TY, int RPT>
-__global__ void __launch_bounds__(TX*(TY / RPT))
-k_d2q9_tile(StepArgs<T> a, int nbx)
+__device__ __forceinline__ void d2q9_tile_body(const StepArgs<T>& a, int x0, int y0, T* __restrict__ psi_s)
 {
     using ST = Stencil<2, ORDER>;
     constexpr int R = ST::R;
     constexpr int LW = TX + 2 * R;
     constexpr int LH = TY + 2 * R;
     constexpr int NT = TX * (TY / RPT);
-    __shared__ T psi_s[LH * LW];
 
     const int nx = a.nx, ny = a.ny;
     const int64_t n = a.n;
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = ty * TX + tx;
-    const int L = xcd_swizzle(blockIdx.x, gridDim.x);
-    const int x0 = (L % nbx) * TX, y0 = (L / nbx) * TY;
 
     const uint32_t TS = sizeof(T), rowb = (uint32_t)nx * TS;
     const int xr = x0 + tx;
@@ -66,8 +70,8 @@ k_d2q9_tile(StepArgs<T> a, int nbx)
             lx = c < R ? c : TX + c;
         }
         rl[q] = i < RING ? ly * LW + lx : -1;
-        nbr_offsets<T>(wrap_any(x0 - R + lx, nx), nx, TS, rxo[q]);
-        nbr_offsets<T>(wrap_any(y0 - R + ly, ny), ny, rowb, ryo[q]);
+        nbr_offsets<T>(wrap_near(x0 - R + lx, nx), nx, TS, rxo[q]);
+        nbr_offsets<T>(wrap_near(y0 - R + ly, ny), ny, rowb, ryo[q]);
     }
 
     T g[RPT][9];
@@ -100,15 +104,19 @@ k_d2q9_tile(StepArgs<T> a, int nbx)
         const int ly = ty * RPT + k;
         const int yr = y0 + ly;
         const T* c = psi_s + (ly + R) * LW + tx + R;
-        T sx = T(0), sy = T(0);
+        T sx = T(0), sy = T(0), ax = T(0), ay = T(0);
 #pragma unroll
         for (int p = 0; p < ST::NP; ++p) {
             constexpr PairList P = ST::P;
             const int ex = P.e[p][0], ey = P.e[p][1];
             const T d = c[ey * LW + ex] - c[-ey * LW - ex];
-            const T wd = T(P.w[p]) * d;
-            if (ex) sx += T(ex) * wd;
-            if (ey) sy += T(ey) * wd;
+            if (ex) ax += T(ex) * d;
+            if (ey) ay += T(ey) * d;
+            if (P.shell_end(p)) {
+                sx += T(P.w[p]) * ax;
+                sy += T(P.w[p]) * ay;
+                ax = ay = T(0);
+            }
         }
         const T pref = -a.gc0 * c[0];
         collide_d2q9_srt(g[k], dr[k], pref * sx, pref * sy, a);
@@ -119,6 +127,17 @@ k_d2q9_tile(StepArgs<T> a, int nbx)
     }
 }
 
+// One tile per block, tiles in strip order.
+template <typename T, int ORDER, int TX, int TY, int RPT>
+__global__ void __launch_bounds__(TX*(TY / RPT))
+k_d2q9_tile(StepArgs<T> a, int nbx, int nby, int sw)
+{
+    using LD = TileLds<ORDER, TX, TY>;
+    __shared__ T psi_s[LD::LH * LD::LW];
+    int bx, by;
+    strip_tile(xcd_swizzle(blockIdx.x, gridDim.x), nbx, nby, sw, bx, by);
+    d2q9_tile_body<T, ORDER, TX, TY, RPT>(a, bx * TX, by * TY, psi_s);
+}
 
 // y-marching kernel for large grids.  A block of NT threads owns the
 // NT - 2R output columns [x0, x0 + NT - 2R) and H rows [y0, y0 + H); thread t
@@ -184,15 +203,19 @@ k_d2q9_march(StepArgs<T> a, int H, int nbx)
                     int sl[2 * R + 1];
 #pragma unroll
                     for (int d = -R; d <= R; ++d) sl[d + R] = ((j - R + d) % NS) * NT + t;
-                    T sx = T(0), sy = T(0);
+                    T sx = T(0), sy = T(0), ax = T(0), ay = T(0);
 #pragma unroll
                     for (int p = 0; p < ST::NP; ++p) {
                         constexpr PairList P = ST::P;
                         const int ex = P.e[p][0], ey = P.e[p][1];
                         const T d = psi_s[sl[R + ey] + ex] - psi_s[sl[R - ey] - ex];
-                        const T wd = T(P.w[p]) * d;
-                        if (ex) sx += T(ex) * wd;
-                        if (ey) sy += T(ey) * wd;
+                        if (ex) ax += T(ex) * d;
+                        if (ey) ay += T(ey) * d;
+                        if (P.shell_end(p)) {
+                            sx += T(P.w[p]) * ax;
+                            sy += T(P.w[p]) * ay;
+                            ax = ay = T(0);
+                        }
                     }
                     const T pref = -a.gc0 * psi_s[sl[R]];
                     const T drc = sum9(g[sc]);
@@ -226,7 +249,8 @@ static hipError_t launch_tile(const StepArgs<T>& a, hipStream_t s)
 {
     const int nbx = (a.nx + TX - 1) / TX, nby = (a.ny + TY - 1) / TY;
     dim3 block(TX, TY / RPT);
-    hipLaunchKernelGGL((k_d2q9_tile<T, ORDER, TX, TY, RPT>), dim3(nbx * nby), block, 0, s, a, nbx);
+    hipLaunchKernelGGL((k_d2q9_tile<T, ORDER, TX, TY, RPT>), dim3(nbx * nby), block, 0, s, a, nbx, nby,
+                       kStripTiles);
     return hipGetLastError();
 }
 

@@ -85,8 +85,8 @@ k_d3q19_march(StepArgs<T> a, int H, int nbx, int nby)
             lx = c < R ? c : TX + c;
         }
         rl[q] = i < RING ? ly * LW + lx : -1;
-        nbr_offsets<T>(wrap_any(x0 - R + lx, nx), nx, TS, rxo[q]);
-        nbr_offsets<T>(wrap_any(y0 - R + ly, ny), ny, rowb, ryo[q]);
+        nbr_offsets<T>(wrap_near(x0 - R + lx, nx), nx, TS, rxo[q]);
+        nbr_offsets<T>(wrap_near(y0 - R + ly, ny), ny, rowb, ryo[q]);
     }
 
     T g[W][RPT][19];
@@ -136,7 +136,7 @@ k_d3q19_march(StepArgs<T> a, int H, int nbx, int nby)
 #pragma unroll
                     for (int k = 0; k < RPT; ++k) {
                         const int cidx = (ty * RPT + k + R) * LW + tx + R;
-                        T sx = T(0), sy = T(0), sz = T(0);
+                        T sx = T(0), sy = T(0), sz = T(0), ax = T(0), ay = T(0), az = T(0);
 #pragma unroll
                         for (int p = 0; p < ST::NP; ++p) {
                             constexpr PairList P = ST::P;
@@ -146,10 +146,16 @@ k_d3q19_march(StepArgs<T> a, int H, int nbx, int nby)
                             const int ex = P.e[p][0], ey = P.e[p][1], ez = P.e[p][2];
                             const T vp = psi_s[sl[R + ez] + cidx + ey * LW + ex];
                             const T vm = psi_s[sl[R - ez] + cidx - ey * LW - ex];
-                            const T wd = T(P.w[p]) * (vp - vm);
-                            if (ex) sx += T(ex) * wd;
-                            if (ey) sy += T(ey) * wd;
-                            if (ez) sz += T(ez) * wd;
+                            const T d = vp - vm;
+                            if (ex) ax += T(ex) * d;
+                            if (ey) ay += T(ey) * d;
+                            if (ez) az += T(ez) * d;
+                            if (P.shell_end(p)) {   // one weight per shell
+                                sx += T(P.w[p]) * ax;
+                                sy += T(P.w[p]) * ay;
+                                sz += T(P.w[p]) * az;
+                                ax = ay = az = T(0);
+                            }
                         }
                         const T pref = -a.gc0 * psi_s[sl[R] + cidx];
                         collide_d3q19<T, MRT>(g[sc][k], dr[sc][k], pref * sx, pref * sy, pref * sz, a);
@@ -181,6 +187,7 @@ static const Shape3D kShapes3D[] = {
     {64, 8, 1, 16, "march64x8r1h16pf1"},
     {64, 8, 1, 32, "march64x8r1h32pf1"},
     {64, 8, 2, 32, "march64x16h32"},
+    {64, 8, 1, 64, "march64x8r1h64pf1"},
 };
 constexpr int kNumShapes3D = sizeof(kShapes3D) / sizeof(kShapes3D[0]);
 
@@ -213,6 +220,7 @@ static hipError_t launch_v(const StepArgs<T>& a, int variant, hipStream_t s)
     case 7: return launch_march<T, ORDER, MRT, 64, 8, 1, 1>(a, 16, s);
     case 8: return launch_march<T, ORDER, MRT, 64, 8, 1, 1>(a, 32, s);
     case 9: return launch_march<T, ORDER, MRT, 64, 8, 2, 0>(a, 32, s);
+    case 10: return launch_march<T, ORDER, MRT, 64, 8, 1, 1>(a, 64, s);
     default: return hipErrorInvalidValue;
     }
 }

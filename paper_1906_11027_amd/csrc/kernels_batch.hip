@@ -30,14 +30,19 @@ __device__ __forceinline__ void batch_force(const T* c, int LW, T& sx, T& sy)
     using ST = Stencil<2, ORDER>;
     sx = T(0);
     sy = T(0);
+    T ax = T(0), ay = T(0);
 #pragma unroll
     for (int p = 0; p < ST::NP; ++p) {
         constexpr PairList P = ST::P;
         const int ex = P.e[p][0], ey = P.e[p][1];
         const T d = c[ey * LW + ex] - c[-ey * LW - ex];
-        const T wd = T(P.w[p]) * d;
-        if (ex) sx += T(ex) * wd;
-        if (ey) sy += T(ey) * wd;
+        if (ex) ax += T(ex) * d;
+        if (ey) ay += T(ey) * d;
+        if (P.shell_end(p)) {   // one weight per shell
+            sx += T(P.w[p]) * ax;
+            sy += T(P.w[p]) * ay;
+            ax = ay = T(0);
+        }
     }
 }
 
@@ -100,8 +105,8 @@ k_d2q9_batch(const BatchItem<T>* __restrict__ items, const int2* __restrict__ wo
             lx = c < R ? c : TX + c;
         }
         uint32_t hxo[3], hyo[3];
-        nbr_offsets<T>(wrap_any(x0 - R + lx, nx), nx, TS, hxo);
-        nbr_offsets<T>(wrap_any(y0 - R + ly, ny), ny, rowb, hyo);
+        nbr_offsets<T>(wrap_near(x0 - R + lx, nx), nx, TS, hxo);
+        nbr_offsets<T>(wrap_near(y0 - R + ly, ny), ny, rowb, hyo);
         T h[9];
         pull_d2q9(a.fin, n, hxo, hyo, h);
         psi_s[(ly + RM - R) * LW + lx + RM - R] = psi_of(a.rho_ref + sum9(h), a);

@@ -123,6 +123,11 @@ struct PairList {
     int r;          // largest |e_i| (psi halo width)
     int e[48][3];   // one vector per pair
     double w[48];   // w_hat of the pair's shell
+    int s[48];      // shell index of the pair (pairs are listed shell by shell)
+
+    // true if pair p is the last of its shell: the kernels sum e (psi+ - psi-)
+    // over a shell and multiply by its weight once
+    constexpr bool shell_end(int p) const { return p + 1 >= n || s[p + 1] != s[p]; }
 };
 
 template <int D, int ORDER>
@@ -146,6 +151,7 @@ constexpr PairList make_pairs()
                     p.e[p.n][1] = b;
                     p.e[p.n][2] = c;
                     p.w[p.n] = S::w[k];
+                    p.s[p.n] = k;
                     ++p.n;
                     const int ma = a < 0 ? -a : a, mb = b < 0 ? -b : b, mc = c < 0 ? -c : c;
                     const int mx = ma > mb ? (ma > mc ? ma : mc) : (mb > mc ? mb : mc);

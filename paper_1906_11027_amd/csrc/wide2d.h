@@ -42,11 +42,7 @@ __device__ __forceinline__ void offsets_m(int v, int n, uint32_t stride, uint32_
 #pragma unroll
     for (int k = 0; k <= 2 * M; ++k) {
         int c = v - M + k;
-        if (M == 1) {
-            c = c < 0 ? c + n : (c >= n ? c - n : c);
-        } else {
-            c = wrap_any(c, n);
-        }
+        c = wrap_near(c, n);
         o[k] = (uint32_t)c * stride;
     }
 }
@@ -97,7 +93,7 @@ __device__ __forceinline__ void collide_lat(T (&g)[L::Q], T drho, T Fx, T Fy, co
         if (L::cx[b]) jx += T(L::cx[b]) * g[b];
         if (L::cy[b]) jy += T(L::cy[b]) * g[b];
     }
-    const T inv = T(1) / rho;
+    const T inv = fast_rcp(rho);
     constexpr double ics = 1.0 / L::cs2;
     constexpr double ics2h = 0.5 / (L::cs2 * L::cs2);
     const T om = a.omega;
@@ -136,7 +132,7 @@ __device__ __forceinline__ void collide_lat(T (&g)[L::Q], T drho, T Fx, T Fy, co
 
 template <typename T, typename L, int ORDER, bool EDM, int TX, int TY, int RPT>
 __global__ void __launch_bounds__(TX*(TY / RPT))
-k_wide_tile(StepArgs<T> a, int nbx)
+k_wide_tile(StepArgs<T> a, int nbx, int nby, int sw)
 {
     using ST = Stencil<2, ORDER>;
     constexpr int Q = L::Q;
@@ -152,8 +148,9 @@ k_wide_tile(StepArgs<T> a, int nbx)
     const int64_t n = a.n;
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = ty * TX + tx;
-    const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
-    const int x0 = (blk % nbx) * TX, y0 = (blk / nbx) * TY;
+    int bx, by;
+    strip_tile(xcd_swizzle(blockIdx.x, gridDim.x), nbx, nby, sw, bx, by);
+    const int x0 = bx * TX, y0 = by * TY;
 
     const uint32_t TS = sizeof(T), rowb = (uint32_t)nx * TS;
     const int xr = x0 + tx;
@@ -195,8 +192,8 @@ k_wide_tile(StepArgs<T> a, int nbx)
             lx = c < R ? c : TX + c;
         }
         uint32_t hxo[2 * M + 1], hyo[2 * M + 1];
-        offsets_m<M>(wrap_any(x0 - R + lx, nx), nx, TS, hxo);
-        offsets_m<M>(wrap_any(y0 - R + ly, ny), ny, rowb, hyo);
+        offsets_m<M>(wrap_near(x0 - R + lx, nx), nx, TS, hxo);
+        offsets_m<M>(wrap_near(y0 - R + ly, ny), ny, rowb, hyo);
         T h[Q];
         pull_lat<T, L, M>(a.fin, n, hxo, hyo, h);
         psi_s[ly * LW + lx] = psi_of(a.rho_ref + TreeSum<0, Q>::of(h), a);
@@ -207,15 +204,19 @@ k_wide_tile(StepArgs<T> a, int nbx)
     for (int k = 0; k < RPT; ++k) {
         const int ly = ty * RPT + k;
         const T* c = psi_s + (ly + R) * LW + tx + R;
-        T sx = T(0), sy = T(0);
+        T sx = T(0), sy = T(0), ax = T(0), ay = T(0);
 #pragma unroll
         for (int p = 0; p < ST::NP; ++p) {
             constexpr PairList P = ST::P;
             const int ex = P.e[p][0], ey = P.e[p][1];
             const T d = c[ey * LW + ex] - c[-ey * LW - ex];
-            const T wd = T(P.w[p]) * d;
-            if (ex) sx += T(ex) * wd;
-            if (ey) sy += T(ey) * wd;
+            if (ex) ax += T(ex) * d;
+            if (ey) ay += T(ey) * d;
+            if (P.shell_end(p)) {
+                sx += T(P.w[p]) * ax;
+                sy += T(P.w[p]) * ay;
+                ax = ay = T(0);
+            }
         }
         const T pref = -a.gc0 * c[0];
         collide_lat<T, L, EDM>(g[k], dr[k], pref * sx, pref * sy, a);
@@ -232,7 +233,7 @@ static hipError_t launch_wide_tile(const StepArgs<T>& a, hipStream_t s)
 {
     const int nbx = (a.nx + TX - 1) / TX, nby = (a.ny + TY - 1) / TY;
     hipLaunchKernelGGL((k_wide_tile<T, L, ORDER, EDM, TX, TY, RPT>), dim3(nbx * nby), dim3(TX, TY / RPT), 0, s, a,
-                       nbx);
+                       nbx, nby, kStripTiles);
     return hipGetLastError();
 }
 
