@@ -64,6 +64,8 @@ def lib():
         L.orc_fields.argtypes = [ctypes.c_void_p, dp, dp, dp, dp]
         L.orc_get_f.argtypes = [ctypes.c_void_p, dp]
         L.orc_set_f.argtypes = [ctypes.c_void_p, dp]
+        L.orc_set_walls.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double]
+        L.orc_set_walls.restype = ctypes.c_int
         L.orc_force.argtypes = [ctypes.POINTER(Params), dp, dp]
         L.orc_force.restype = ctypes.c_int
         L.orc_lattice.argtypes = [ctypes.c_int, ip, ip, ip, dp, dp]
@@ -204,23 +206,40 @@ class Oracle:
             raise ValueError("not an MRT simulation")
         return M.reshape(19, 19), nn, S
 
+    def set_walls(self, solid, rho_w):
+        """Solid mask indexed like the fields (nonzero = solid) and virtual
+        wall density (the populations are kept).  None removes the walls."""
+        if solid is None:
+            self.solid = None
+            assert lib().orc_set_walls(self.h, None, 0.0) == 0
+            return self
+        m = np.ascontiguousarray(np.asarray(solid).transpose()).ravel().astype(np.uint8)
+        assert m.size == self.n
+        assert lib().orc_set_walls(self.h, m.ctypes.data_as(ctypes.c_void_p), float(rho_w)) == 0
+        self.solid = np.asarray(solid).astype(bool)
+        return self
+
     def observables(self):
-        return observables(self.fields(), self.cs2, self.G, self.c0)
+        return observables(self.fields(), self.cs2, self.G, self.c0, getattr(self, "solid", None))
 
 
-def observables(fl, cs2, G, c0):
+def observables(fl, cs2, G, c0, solid=None):
     """(The pressure uses the psi definition of Sec. 3 for every psi kind:
-    p = cs2 rho + G c0 psi^2 / 2, which equals the EOS pressure for "pr".)"""
-    return _observables(fl, cs2, G, c0)
+    p = cs2 rho + G c0 psi^2 / 2, which equals the EOS pressure for "pr".)
+    With walls, the velocity norms run over the fluid nodes; the mass
+    counts every population (solid nodes hold those in transit)."""
+    return _observables(fl, cs2, G, c0, solid)
 
 
-def _observables(fl, cs2, G, c0):
+def _observables(fl, cs2, G, c0, solid=None):
     """Reductions every K steps: mass, momentum, spurious-velocity norms
     (maximum and field average, Sec. 3 Fig. 3), Laplace pressure jump
     between the centre node and the corner node, equivalent radius."""
     rho, psi, u = fl["rho"], fl["psi"], fl["u"]
     dim = rho.ndim
     umag = np.sqrt((u ** 2).sum(axis=0))
+    if solid is not None:
+        umag = umag[~solid]
     p = cs2 * rho + 0.5 * G * c0 * psi ** 2
     centre = tuple(s // 2 for s in rho.shape)
     corner = (0,) * dim

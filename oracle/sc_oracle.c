@@ -20,6 +20,15 @@
  *      MRT:  m = M f;  m* = m - S (m - meq) + (I - S/2) M phihat;  f* = M^-1 m*
  *   7. f_b(x + c_b, t+1) = f*_b(x, t)                      (Sec. 2, Eq. (3))
  *
+ * Solid walls (Sec. 3, droplet on a flat wall), when a solid mask is set:
+ * solid nodes take part in the interaction force with the pseudo-potential
+ * of a virtual wall density, psi(rho_w); instead of steps 4-6 a solid node
+ * applies the standard (full-way) bounce-back, f*_b = f_{-b}: whatever
+ * streamed into it is sent back along the link it came from, whatever its
+ * length.  Solid nodes start like every node from feq(rho_init, 0) and hold
+ * the populations in transit through the wall; streaming, bounce-back and
+ * the fluid collision all conserve the total of the populations.
+ *
  * No blocking, fusion or reordering beyond the above; the only parallelism
  * is an OpenMP split of independent node loops, which does not change any
  * result.  Build with -ffp-contract=off so no FMA changes the rounding.
@@ -65,6 +74,9 @@ typedef struct {
     double Mnorm[19];       /* |row|^2 */
     double S[19];           /* relaxation rate per moment */
     double *f, *ftmp, *rho, *psi, *F;
+    int opp[25];            /* index of -c_b */
+    unsigned char *solid;   /* solid mask [N] or NULL */
+    double psi_w;           /* psi(rho_w) of the solid nodes */
 } orc_sim;
 
 /* ------------------------------------------------------------------------ */
@@ -314,7 +326,7 @@ static void macro(orc_sim *s)
         double r = 0.0;
         for (int b = 0; b < s->q; ++b) r += s->f[b * n + i];
         s->rho[i] = r;
-        s->psi[i] = psi_of_cs(&s->p, r, s->cs2);
+        s->psi[i] = (s->solid && s->solid[i]) ? s->psi_w : psi_of_cs(&s->p, r, s->cs2);
     }
     force_from_psi(s, s->psi, s->F);
 }
@@ -365,6 +377,11 @@ static void collide_edm(const orc_sim *s, long i, double *fstar)
 static void collide_node(const orc_sim *s, long i, double *fstar)
 {
     const long n = s->n;
+    if (s->solid && s->solid[i]) {
+        /* full-way bounce-back: reverse what arrived */
+        for (int b = 0; b < s->q; ++b) fstar[b] = s->f[s->opp[b] * n + i];
+        return;
+    }
     const double cs2 = s->cs2, tau = s->p.tau;
     if (s->p.forcing == 1) {
         collide_edm(s, i, fstar);
@@ -425,6 +442,9 @@ orc_sim *orc_create(const orc_params *p, const double *rho0)
         if (s->q != 19 || p->forcing != 0) goto fail;
         build_mrt(s);
     }
+    for (int b = 0; b < s->q; ++b)
+        for (int k = 0; k < s->q; ++k)
+            if (s->c[k][0] == -s->c[b][0] && s->c[k][1] == -s->c[b][1] && s->c[k][2] == -s->c[b][2]) s->opp[b] = k;
     s->n = (long)s->p.nx * s->p.ny * s->p.nz;
     s->f = (double *)malloc(sizeof(double) * s->q * s->n);
     s->ftmp = (double *)malloc(sizeof(double) * s->q * s->n);
@@ -448,8 +468,24 @@ fail:
 void orc_destroy(orc_sim *s)
 {
     if (!s) return;
-    free(s->f); free(s->ftmp); free(s->rho); free(s->psi); free(s->F);
+    free(s->f); free(s->ftmp); free(s->rho); free(s->psi); free(s->F); free(s->solid);
     free(s);
+}
+
+/* Solid mask [N] (nonzero = solid) and virtual wall density rho_w; NULL
+ * removes the walls.  The populations are left as they are. */
+int orc_set_walls(orc_sim *s, const unsigned char *solid, double rho_w)
+{
+    free(s->solid);
+    s->solid = NULL;
+    if (solid) {
+        s->solid = (unsigned char *)malloc(s->n);
+        if (!s->solid) return -1;
+        for (long i = 0; i < s->n; ++i) s->solid[i] = solid[i] ? 1 : 0;
+        s->psi_w = psi_of_cs(&s->p, rho_w, s->cs2);
+    }
+    macro(s);
+    return 0;
 }
 
 void orc_step(orc_sim *s, long nsteps)
@@ -483,11 +519,15 @@ void orc_fields(orc_sim *s, double *rho, double *psi, double *F, double *u)
     if (F) for (int d = 0; d < s->dim; ++d) memcpy(F + d * n, s->F + d * n, sizeof(double) * n);
     if (u) {
         for (long i = 0; i < n; ++i) {
-            double uv[3];
-            velocity(s, i, uv);
+            double uv[3] = {0.0, 0.0, 0.0};
+            if (!(s->solid && s->solid[i])) velocity(s, i, uv);
             for (int d = 0; d < s->dim; ++d) u[d * n + i] = uv[d];
         }
     }
+    if (F && s->solid)
+        for (long i = 0; i < n; ++i)
+            if (s->solid[i])
+                for (int d = 0; d < s->dim; ++d) F[d * n + i] = 0.0;
 }
 
 void orc_get_f(const orc_sim *s, double *f) { memcpy(f, s->f, sizeof(double) * s->q * s->n); }

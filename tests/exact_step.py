@@ -19,14 +19,20 @@ def _add(a, b, shape):
 
 
 def exact_steps(rho0, shape, lattice, order, G, c0, tau, nsteps=1,
-                collision="srt", s_bulk=None, s_ghost=None, forcing="guo"):
+                collision="srt", s_bulk=None, s_ghost=None, forcing="guo", solid=(), rho_w=None):
     """rho0: dict node -> Fraction.  Returns dict node -> list of f (Fractions)
-    after nsteps, with f = feq(rho0, 0) at t = 0."""
+    after nsteps, with f = feq(rho0, 0) at t = 0.
+
+    solid: nodes of a wall (initialised like the rest).  In the force they count with
+    psi = rho_w (the virtual wall density, Sec. 3); in place of a collision
+    they send every population back the way it came (standard bounce-back)."""
     dim, cs2, vel = T.lattice(lattice)
     stencil = T.force_stencil(dim, order)
     tau = Fr(tau)
     G, c0 = Fr(G), Fr(c0)
     nodes = list(product(*[range(n) for n in shape]))
+    solid = set(solid)
+    back = {q: [tuple(-v for v in c) for c, _ in vel].index(tuple(c)) for q, (c, _) in enumerate(vel)}
     f = {x: [w * rho0[x] for _, w in vel] for x in nodes}
     if collision == "mrt":
         rows, groups = T.mrt_gram_schmidt(lattice)
@@ -43,7 +49,8 @@ def exact_steps(rho0, shape, lattice, order, G, c0, tau, nsteps=1,
 
     for _ in range(nsteps):
         rho = {x: sum(f[x]) for x in nodes}
-        psi = rho  # psi = rho (identity) keeps everything rational
+        # psi = rho (identity) keeps everything rational; walls carry rho_w
+        psi = {x: (Fr(rho_w) if x in solid else rho[x]) for x in nodes}
         F = {}
         for x in nodes:
             acc = [Fr(0)] * dim
@@ -55,6 +62,11 @@ def exact_steps(rho0, shape, lattice, order, G, c0, tau, nsteps=1,
         new = {x: [None] * len(vel) for x in nodes}
         for x in nodes:
             fx = f[x]
+            if x in solid:
+                # population q leaves along c_q what arrived along -c_q
+                for q, (c, _) in enumerate(vel):
+                    new[_add(x, c, shape)][q] = fx[back[q]]
+                continue
             mom = [sum(fb * c[d] for fb, (c, _) in zip(fx, vel)) for d in range(dim)]
             u = [(mom[d] + F[x][d] / 2) / rho[x] for d in range(dim)]
             uu = sum(ui * ui for ui in u)
