@@ -120,7 +120,7 @@ typedef struct sc_lbm_obs {
     double mass;          /* sum rho                                              */
     double mom[3];        /* sum rho u                                            */
     double max_u;         /* max |u|        (spurious-velocity maximum, Sec. 3)   */
-    double mean_u;        /* mean |u|       (field-averaged spurious velocity)    */
+    double mean_u;        /* mean |u| over fluid nodes (field-averaged, Sec. 3)   */
     double l2_u;          /* sqrt(mean |u|^2)                                     */
     double rho_in;        /* rho at the centre node (nx/2, ny/2, nz/2)            */
     double rho_out;       /* rho at node 0                                        */
@@ -177,6 +177,24 @@ int sc_lbm_observe(sc_lbm* h, sc_lbm_obs* obs, double* rho_out, double* u_out, v
 /* Restore a state written by sc_lbm_observe(f_out) (checkpoint / resume):
  * f_in host buffer of sc_lbm_state_bytes bytes; step sets the step counter. */
 int sc_lbm_set_state(sc_lbm* h, const void* f_in, int64_t step);
+
+/* Solid walls (Sec. 3, droplet on a flat wall), 2D lattices only.
+ *   solid  host [N] bytes, nonzero = solid node, in node order; NULL removes
+ *          the walls;
+ *   rho_w  virtual wall density: solid nodes enter the interaction force
+ *          with psi(rho_w), which tunes the wettability.
+ * Solid nodes do not collide: they apply the standard (full-way)
+ * bounce-back, sending every population back along the link it arrived on
+ * (any link length, so walls should be at least max |c| = 1 or 2 nodes
+ * thick).  Their populations are those in transit through the wall; they
+ * keep whatever the state holds (sc_lbm_create initialises every node from
+ * rho_init).  Observables: velocities are zero on solid nodes and the |u|
+ * norms run over fluid nodes; the mass counts every node.  With walls every
+ * 2D lattice runs the any-lattice kernels (the launch shape falls back to
+ * the automatic choice when that changes the kernel family).  Synchronises
+ * the stream.  Errors: SC_E_INVAL, SC_E_UNSUPPORTED (D3Q19), SC_E_NOMEM,
+ * SC_E_DEVICE. */
+int sc_lbm_set_walls(sc_lbm* h, const uint8_t* solid, double rho_w);
 
 /* Device pointer of the buffer holding the current state (for callers that
  * keep the data resident); NULL on a NULL handle. */

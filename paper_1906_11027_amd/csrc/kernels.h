@@ -29,6 +29,8 @@ struct StepArgs {
     T cs2;                       // lattice sound speed squared
     T eos_RT, eos_b, eos_aa;     // Peng-Robinson R T, b and a alpha(T)
     T eos_k;                     // 2 / (G c0)
+    const uint8_t* __restrict__ solid;   // wall mask [N] (1 = solid) or null
+    T psi_w;                     // psi of the virtual wall density
 };
 
 // exp, 1/x and sqrt for the hot kernels.  The FP32 state uses the hardware
@@ -168,29 +170,23 @@ __device__ __forceinline__ void collide_d2q9_srt(T (&g)[9], T drho, T Fx, T Fy, 
     const T usq = T(1.5) * (ux * ux + uy * uy);
     const T uF = ux * Fx + uy * Fy;
     const T om = a.omega, gu = a.guo;
+    // Collision conserves mass exactly; the rest population closes the
+    // balance in difference form, g0* = g0 + sum_{b>=1} (g_b - g_b*): the
+    // increments are small, so the node's mass keeps only the rounding of
+    // the stored g0* (not that of two 9-term sums of O(rho) values).
+    T dm = T(0);
 #pragma unroll
-    for (int b = 0; b < 9; ++b) {
+    for (int b = 1; b < 9; ++b) {
         const T cu = T(D2Q9::cx[b]) * ux + T(D2Q9::cy[b]) * uy;
         const T cF = T(D2Q9::cx[b]) * Fx + T(D2Q9::cy[b]) * Fy;
         const T w = T(D2Q9::w[b]);
         const T geq = w * (drho + rho * (T(3) * cu + T(4.5) * cu * cu - usq));
         const T phi = gu * w * (T(3) * (cF - uF) + T(9) * cu * cF);
-        g[b] = g[b] - om * (g[b] - geq) + phi;
+        const T gn = g[b] - om * (g[b] - geq) + phi;
+        dm += g[b] - gn;
+        g[b] = gn;
     }
-    // Collision conserves mass exactly; close the balance through the rest
-    // population so the rounding of feq and phi leaves no systematic drift.
-    g[0] = drho - (((g[1] + g[2]) + (g[3] + g[4])) + ((g[5] + g[6]) + (g[7] + g[8])));
-}
-
-// Sum of populations 1..18 in a fixed order (mass balance of the collision).
-template <typename T>
-__device__ __forceinline__ T sum19_moving(const T (&g)[19])
-{
-    T s0 = (g[1] + g[2]) + (g[3] + g[4]);
-    T s1 = (g[5] + g[6]) + (g[7] + g[8]);
-    T s2 = (g[9] + g[10]) + (g[11] + g[12]);
-    T s3 = (g[13] + g[14]) + (g[15] + g[16]);
-    return ((s0 + s1) + (s2 + s3)) + (g[17] + g[18]);
+    g[0] += dm;
 }
 
 // --------------------------------------------------------------- D3Q19 ----
@@ -233,18 +229,23 @@ __device__ __forceinline__ void collide_d3q19(T (&g)[19], T drho, T Fx, T Fy, T 
     const T uz = (jz + T(0.5) * Fz) * inv;
     const T usq = T(1.5) * (ux * ux + uy * uy + uz * uz);
     const T uF = ux * Fx + uy * Fy + uz * Fz;
+    // mass closure through the rest population in difference form (see
+    // collide_d2q9_srt): dm = sum_{b>=1} (g_b - g_b*), g0* = g0 + dm
+    T dm = T(0);
     if (!MRT) {
         const T om = a.omega, gu = a.guo;
 #pragma unroll
-        for (int b = 0; b < 19; ++b) {
+        for (int b = 1; b < 19; ++b) {
             const T cu = T(L::cx[b]) * ux + T(L::cy[b]) * uy + T(L::cz[b]) * uz;
             const T cF = T(L::cx[b]) * Fx + T(L::cy[b]) * Fy + T(L::cz[b]) * Fz;
             const T w = T(L::w[b]);
             const T geq = w * (drho + rho * (T(3) * cu + T(4.5) * cu * cu - usq));
             const T phi = gu * w * (T(3) * (cF - uF) + T(9) * cu * cF);
-            g[b] = g[b] - om * (g[b] - geq) + phi;
+            const T gn = g[b] - om * (g[b] - geq) + phi;
+            dm += g[b] - gn;
+            g[b] = gn;
         }
-        g[0] = drho - sum19_moving(g);
+        g[0] += dm;
     } else {
         const T sg = a.s_ghost;
         const T gh = T(1) - T(0.5) * sg;
@@ -260,7 +261,11 @@ __device__ __forceinline__ void collide_d3q19(T (&g)[19], T drho, T Fx, T Fy, T 
             const T ph = w * (T(3) * (cF - uF) + T(9) * cu * cF);   // phihat
             const T ne = g[b] - geq;
             v[b] = ne + T(0.5) * ph;
-            g[b] = g[b] - sg * ne + gh * ph;
+            if (b) {   // the rest population is closed below
+                const T gn = g[b] - sg * ne + gh * ph;
+                dm += g[b] - gn;
+                g[b] = gn;
+            }
             const int c2 = cx * cx + cy * cy + cz * cz;
             mb += T(19 * c2 - 30) * v[b];
             const int p1 = 2 * cx * cx - cy * cy - cz * cz, p2 = cy * cy - cz * cz;
@@ -275,7 +280,7 @@ __device__ __forceinline__ void collide_d3q19(T (&g)[19], T drho, T Fx, T Fy, T 
         const T k1 = ks * m1 * T(1.0 / 36.0), k2 = ks * m2 * T(1.0 / 12.0);
         const T k3 = ks * m3 * T(0.25), k4 = ks * m4 * T(0.25), k5 = ks * m5 * T(0.25);
 #pragma unroll
-        for (int b = 0; b < 19; ++b) {
+        for (int b = 1; b < 19; ++b) {
             const int cx = L::cx[b], cy = L::cy[b], cz = L::cz[b];
             const int c2 = cx * cx + cy * cy + cz * cz;
             T d = kb * T(19 * c2 - 30);
@@ -285,9 +290,11 @@ __device__ __forceinline__ void collide_d3q19(T (&g)[19], T drho, T Fx, T Fy, T 
             if (cx * cy) d += k3 * T(cx * cy);
             if (cy * cz) d += k4 * T(cy * cz);
             if (cx * cz) d += k5 * T(cx * cz);
-            g[b] += d;
+            const T gf = g[b] + d;
+            dm += g[b] - gf;
+            g[b] = gf;
         }
-        g[0] = drho - sum19_moving(g);
+        g[0] += dm;
     }
 }
 
@@ -326,14 +333,15 @@ hipError_t launch_init(int lattice, void* f, int precision, const double* rho0, 
                        double rho_ref, hipStream_t s);
 
 // Observables: macroscopic fields of the current state and FP64 reductions.
+constexpr int kObsSlots = 9;   // reduction slots per block (observe.hip)
 struct ObsBuffers {
     double* rho;      // [N]
     void* psi;        // [N] in the state precision
     double* j;        // [D][N] sum_b f_b c_b
     double* F;        // [D][N]
     double* u;        // [D][N]
-    double* partials; // [nblk][8]
-    double* result;   // [8]
+    double* partials; // [nblk][kObsSlots]
+    double* result;   // [kObsSlots]
     int nblk;
 };
 hipError_t launch_macro(int lattice, int precision, const void* f, const void* args, ObsBuffers& ob,
@@ -341,7 +349,7 @@ hipError_t launch_macro(int lattice, int precision, const void* f, const void* a
 hipError_t launch_force(int dim, int precision, int order, const void* args, ObsBuffers& ob,
                         bool with_velocity, hipStream_t s);
 hipError_t launch_psi_from_host(int precision, const double* psi_dev_d, void* psi, int64_t n, hipStream_t s);
-hipError_t launch_reduce(int dim, ObsBuffers& ob, int64_t n, hipStream_t s);
+hipError_t launch_reduce(int dim, ObsBuffers& ob, const uint8_t* solid, int64_t n, hipStream_t s);
 
 // Batched D2Q9 step over a (item, tile) work list (kernels_batch.hip).
 int batch_tile_w();

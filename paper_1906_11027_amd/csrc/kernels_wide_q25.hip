@@ -7,7 +7,8 @@ namespace sclbm {
 template <typename T>
 static hipError_t run(const StepArgs<T>& a, int order, bool edm, int variant, hipStream_t s)
 {
-    return launch_wide_lattice<T, D2Q25>(a, order, edm, variant, s);
+    return a.solid ? launch_wide_lattice<T, D2Q25, true>(a, order, edm, variant, s)
+                   : launch_wide_lattice<T, D2Q25, false>(a, order, edm, variant, s);
 }
 
 hipError_t launch_wide_q25(const StepArgs<float>& a, int order, bool edm, int variant, hipStream_t s)

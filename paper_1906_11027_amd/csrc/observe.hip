@@ -112,7 +112,7 @@ __global__ void k_macro(const T* __restrict__ f, StepArgs<T> a, double* __restri
         }
         const T r = a.rho_ref + dr;
         rho[i] = (double)r;
-        psi[i] = psi_of(r, a);
+        psi[i] = (a.solid && a.solid[i]) ? a.psi_w : psi_of(r, a);
         j[i] = (double)jx;
         j[n + i] = (double)jy;
         if (L::D == 3) j[2 * n + i] = (double)jz;
@@ -152,11 +152,12 @@ __global__ void k_force(const T* __restrict__ psi, StepArgs<T> a, double* __rest
             s[2] += T(ez) * wd;
         }
         const T pref = -a.gc0 * psi[i];
+        const bool wall = a.solid && a.solid[i];   // no force or velocity inside a wall
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            const double Fd = (double)(pref * s[d]);
+            const double Fd = wall ? 0.0 : (double)(pref * s[d]);
             F[d * n + i] = Fd;
-            if (u) u[d * n + i] = (j[d * n + i] + 0.5 * Fd) / rho[i];
+            if (u) u[d * n + i] = wall ? 0.0 : (j[d * n + i] + 0.5 * Fd) / rho[i];
         }
     }
 }
@@ -171,8 +172,10 @@ __global__ void k_psi_convert(const double* __restrict__ src, T* __restrict__ ds
 
 // ------------------------------------------------------------- reduce ----
 // partial[blk] = {sum rho, sum rho u_x, sum rho u_y, sum rho u_z,
-//                 max |u|, sum |u|, sum |u|^2, count of non-finite nodes}
-constexpr int kNR = 8;
+//                 max |u|, sum |u|, sum |u|^2, count of non-finite nodes,
+//                 count of finite fluid nodes}
+// Wall nodes add their rho (populations in transit) to the mass only.
+constexpr int kNR = kObsSlots;
 constexpr int kRedThreads = 256;
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -207,13 +210,18 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[kNR], double* o
 }
 
 __global__ void __launch_bounds__(kRedThreads)
-k_reduce_partials(const double* __restrict__ rho, const double* __restrict__ u, int dim, int64_t n,
-                  double* __restrict__ partials)
+k_reduce_partials(const double* __restrict__ rho, const double* __restrict__ u, const uint8_t* __restrict__ solid,
+                  int dim, int64_t n, double* __restrict__ partials)
 {
-    double acc[kNR] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double acc[kNR] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const double r = rho[i];
+        if (solid && solid[i]) {
+            if (isfinite(r)) acc[0] += r;
+            else acc[7] += 1.0;
+            continue;
+        }
         double uu = 0.0;
         bool fin = isfinite(r);
         for (int d = 0; d < dim; ++d) {
@@ -231,6 +239,7 @@ k_reduce_partials(const double* __restrict__ rho, const double* __restrict__ u, 
         acc[4] = fmax(acc[4], um);
         acc[5] += um;
         acc[6] += uu;
+        acc[8] += 1.0;
     }
     block_reduce_store(acc, partials + (int64_t)blockIdx.x * kNR);
 }
@@ -238,7 +247,7 @@ k_reduce_partials(const double* __restrict__ rho, const double* __restrict__ u, 
 __global__ void __launch_bounds__(kRedThreads)
 k_reduce_final(const double* __restrict__ partials, int nblk, double* __restrict__ out)
 {
-    double acc[kNR] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double acc[kNR] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
         const double* p = partials + (int64_t)b * kNR;
 #pragma unroll
@@ -342,9 +351,9 @@ hipError_t launch_psi_from_host(int precision, const double* psi_dev_d, void* ps
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(int dim, ObsBuffers& ob, int64_t n, hipStream_t s)
+hipError_t launch_reduce(int dim, ObsBuffers& ob, const uint8_t* solid, int64_t n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce_partials, ob.nblk, kRedThreads, 0, s, ob.rho, ob.u, dim, n, ob.partials);
+    hipLaunchKernelGGL(k_reduce_partials, ob.nblk, kRedThreads, 0, s, ob.rho, ob.u, solid, dim, n, ob.partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce_final, 1, kRedThreads, 0, s, ob.partials, ob.nblk, ob.result);

@@ -49,6 +49,7 @@ struct sc_lbm {
     bool graph_failed = false;
     double last_max_u = -1.0;
     int fp32_hits = 0;
+    uint8_t* solid = nullptr;   // device wall mask [N] (null: no walls)
 };
 
 static thread_local char g_detail[256] = "";
@@ -93,6 +94,9 @@ static Family family_of(const sc_lbm_params& p)
     if (p.lattice == SC_D2Q9 && p.forcing == SC_GUO) return kFamD2Q9;
     return kFamWide;
 }
+// With walls every 2D lattice runs the any-lattice kernels.
+static Family handle_family(const sc_lbm* h) { return h->solid ? kFamWide : family_of(h->p); }
+
 static int family_variants(Family f)
 {
     return f == kFamD2Q9 ? num_variants_d2q9() : (f == kFamD3Q19 ? num_variants_d3q19() : num_variants_wide());
@@ -213,7 +217,7 @@ extern "C" int sc_lbm_num_variants(const sc_lbm_params* p)
 extern "C" const char* sc_lbm_variant_name(const sc_lbm* h)
 {
     if (!h) return "";
-    switch (family_of(h->p)) {
+    switch (handle_family(h)) {
     case kFamD2Q9: return variant_name_d2q9(h->variant);
     case kFamD3Q19: return variant_name_d3q19(h->variant);
     default: return variant_name_wide(h->variant);
@@ -361,6 +365,7 @@ static void release(sc_lbm* h)
         hipFree(h->f[1]);
     }
     if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
+    hipFree(h->solid);
     delete h;
 }
 
@@ -470,7 +475,7 @@ template <typename T>
 static hipError_t launch_family(sc_lbm* h, const StepArgs<T>& a)
 {
     const sc_lbm_params& p = h->p;
-    switch (family_of(p)) {
+    switch (handle_family(h)) {
     case kFamD2Q9: return launch_step_d2q9(a, p.order, h->variant, h->stream);
     case kFamD3Q19: return launch_step_d3q19(a, p.order, p.collision == SC_MRT, h->variant, h->stream);
     default: return launch_step_wide(p.lattice, a, p.order, p.forcing == SC_EDM, h->variant, h->stream);
@@ -547,8 +552,8 @@ static int ensure_obs(sc_lbm* h)
     if (e == hipSuccess) e = hipMalloc(&b.j, sizeof(double) * 3 * n);
     if (e == hipSuccess) e = hipMalloc(&b.F, sizeof(double) * 3 * n);
     if (e == hipSuccess) e = hipMalloc(&b.u, sizeof(double) * 3 * n);
-    if (e == hipSuccess) e = hipMalloc(&b.partials, sizeof(double) * 8 * b.nblk);
-    if (e == hipSuccess) e = hipMalloc(&b.result, sizeof(double) * 8);
+    if (e == hipSuccess) e = hipMalloc(&b.partials, sizeof(double) * kObsSlots * b.nblk);
+    if (e == hipSuccess) e = hipMalloc(&b.result, sizeof(double) * kObsSlots);
     if (e != hipSuccess) {
         hipFree(b.rho);
         hipFree(b.psi);
@@ -575,8 +580,8 @@ static int observe_core(sc_lbm* h, sc_lbm_obs* o)
     const sc_lbm_params& p = h->p;
     hipError_t e = launch_macro(p.lattice, p.precision, h->f[h->cur], args_ptr(h), b, h->stream);
     if (e == hipSuccess) e = launch_force(h->dim, p.precision, p.order, args_ptr(h), b, true, h->stream);
-    if (e == hipSuccess) e = launch_reduce(h->dim, b, h->n, h->stream);
-    double res[8];
+    if (e == hipSuccess) e = launch_reduce(h->dim, b, h->solid, h->n, h->stream);
+    double res[kObsSlots];
     if (e == hipSuccess) e = hipMemcpyAsync(res, b.result, sizeof(res), hipMemcpyDeviceToHost, h->stream);
     const int64_t ic = (int64_t)(p.nx / 2) + (int64_t)p.nx * ((int64_t)(p.ny / 2) + (int64_t)p.ny * (p.nz / 2));
     double rin = 0, rout = 0, pin = 0, pout = 0;
@@ -609,7 +614,7 @@ static int observe_core(sc_lbm* h, sc_lbm_obs* o)
     o->mom[1] = res[2];
     o->mom[2] = res[3];
     o->max_u = res[4];
-    const double nfin = (double)h->n - res[7];
+    const double nfin = res[8];   // finite fluid nodes
     o->mean_u = nfin > 0 ? res[5] / nfin : 0.0;
     o->l2_u = nfin > 0 ? std::sqrt(res[6] / nfin) : 0.0;
     o->nonfinite = (int64_t)res[7];
@@ -718,6 +723,67 @@ extern "C" int sc_lbm_set_state(sc_lbm* h, const void* f_in, int64_t step)
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_err(e);
     h->step = step;
+    h->last_max_u = -1.0;
+    h->fp32_hits = 0;
+    return SC_OK;
+}
+
+// psi of the virtual wall density in FP64 (the kernels take it as a value)
+static double host_psi(const sc_lbm_params& p, double rho)
+{
+    if (p.psi_kind == SC_PSI_IDENTITY) return rho;
+    if (p.psi_kind == SC_PSI_PR) {
+        const double br = p.eos_b * rho;
+        const double pr = rho * p.eos_R * p.eos_T / (1.0 - br) -
+                          p.eos_a * p.eos_alpha * rho * rho / (1.0 + 2.0 * br - br * br);
+        const double arg = 2.0 * (pr - lattice_cs2(p.lattice) * rho) / (p.G * p.c0);
+        return arg > 0.0 ? std::sqrt(arg) : 0.0;
+    }
+    return p.psi0 * (1.0 - std::exp(-rho / p.rho_psi));
+}
+
+extern "C" int sc_lbm_set_walls(sc_lbm* h, const uint8_t* solid, double rho_w)
+{
+    if (!h || !std::isfinite(rho_w)) return SC_E_INVAL;
+    if (h->dim != 2) return SC_E_UNSUPPORTED;
+    hipError_t e = hipStreamSynchronize(h->stream);   // kernels in flight may read the old mask
+    if (e != hipSuccess) return hip_err(e);
+    for (int k = 0; k < 2; ++k)   // captured graphs hold the old kernel arguments
+        if (h->gexec[k]) {
+            hipGraphExecDestroy(h->gexec[k]);
+            h->gexec[k] = nullptr;
+        }
+    const Family before = handle_family(h);
+    if (!solid) {
+        hipFree(h->solid);
+        h->solid = nullptr;
+    } else {
+        if (!h->solid) {
+            e = hipMalloc(&h->solid, (size_t)h->n);
+            if (e != hipSuccess) {
+                h->solid = nullptr;
+                return hip_err(e);
+            }
+        }
+        e = hipMemcpyAsync(h->solid, solid, (size_t)h->n, hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_err(e);
+    }
+    const double pw = host_psi(h->p, rho_w);
+    h->af.solid = h->solid;
+    h->ad.solid = h->solid;
+    h->af.psi_w = (float)pw;
+    h->ad.psi_w = pw;
+    // a change of kernel family invalidates the launch shape index: back in
+    // the parameters' own family take the requested (or tuned / automatic)
+    // shape, in the any-lattice family its automatic one
+    const Family now = handle_family(h);
+    if (now != before) {
+        if (now == family_of(h->p))
+            h->variant = h->p.variant >= 0 ? h->p.variant : auto_variant(h->p, h->n);
+        else
+            h->variant = h->n < ((int64_t)1 << 20) ? 1 : 0;
+    }
     h->last_max_u = -1.0;
     h->fp32_hits = 0;
     return SC_OK;

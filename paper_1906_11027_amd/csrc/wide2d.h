@@ -17,6 +17,10 @@
 //            difference method (Sec. 3), coalesced store at the own address.
 // Ragged tiles: out-of-grid threads still supply wrapped psi and skip the
 // store, so any nx, ny >= 1 works.
+// Walls (WALLS = true): solid nodes put psi(rho_w) into the force (the
+// virtual wall density of Sec. 3) and, instead of colliding, send back what
+// arrived: g*_b = g_{-b} (standard bounce-back; the rest-weight shift is
+// symmetric, so it commutes with the reversal).
 #pragma once
 #include "kernels.h"
 
@@ -56,6 +60,15 @@ __device__ __forceinline__ void pull_lat(const T* __restrict__ f, int64_t n, con
     for (int b = 0; b < L::Q; ++b) g[b] = ld_off(f + b * n, yo[M - L::cy[b]] + xo[M - L::cx[b]]);
 }
 
+// index of -c_b in the lattice's velocity list
+template <typename L>
+constexpr int opposite(int b)
+{
+    for (int k = 0; k < L::Q; ++k)
+        if (L::cx[k] == -L::cx[b] && L::cy[k] == -L::cy[b]) return k;
+    return b;
+}
+
 // pairwise sum of g[LO .. LO + N) in a fixed tree order
 template <int LO, int N>
 struct TreeSum {
@@ -80,8 +93,13 @@ struct TreeSum<LO, 1> {
 // with feq = w rho [1 + c.u/cs2 + (c.u)^2/(2 cs2^2) - u^2/(2 cs2)] and
 // phihat = w [(c - u)/cs2 + (c.u) c / cs2^2] . F.  The EDM increment is
 // expanded as a difference (c.dv (2 c.v + c.dv) etc.) so it carries no
-// cancellation of two equilibria.  Both conserve mass exactly; the rest
-// population closes the balance so rounding leaves no drift.
+// cancellation of two equilibria.  Both conserve mass exactly.  The rest
+// population closes the balance in difference form,
+//   g0* = g0 + sum_{b>=1} (g_b - g_b*),
+// whose terms are the small collision increments: the only rounding left in
+// the node's mass is that of the stored g0*, where summing the populations
+// before and after would add the rounding of two Q-term sums of O(rho)
+// values, repeated identically every step near a steady state.
 template <typename T, typename L, bool EDM>
 __device__ __forceinline__ void collide_lat(T (&g)[L::Q], T drho, T Fx, T Fy, const StepArgs<T>& a)
 {
@@ -94,6 +112,7 @@ __device__ __forceinline__ void collide_lat(T (&g)[L::Q], T drho, T Fx, T Fy, co
         if (L::cy[b]) jy += T(L::cy[b]) * g[b];
     }
     const T inv = fast_rcp(rho);
+    T dm = T(0);   // sum of g_b - g_b* over b >= 1
     constexpr double ics = 1.0 / L::cs2;
     constexpr double ics2h = 0.5 / (L::cs2 * L::cs2);
     const T om = a.omega;
@@ -104,13 +123,15 @@ __device__ __forceinline__ void collide_lat(T (&g)[L::Q], T drho, T Fx, T Fy, co
         const T uF = ux * Fx + uy * Fy;
         const T gu = a.guo;
 #pragma unroll
-        for (int b = 0; b < Q; ++b) {
+        for (int b = 1; b < Q; ++b) {
             const T cu = T(L::cx[b]) * ux + T(L::cy[b]) * uy;
             const T cF = T(L::cx[b]) * Fx + T(L::cy[b]) * Fy;
             const T w = T(L::w[b]);
             const T geq = w * (drho + rho * (T(ics) * cu + T(ics2h) * cu * cu - usq));
             const T phi = gu * w * (T(ics) * (cF - uF) + T(2.0 * ics2h) * cu * cF);
-            g[b] = g[b] - om * (g[b] - geq) + phi;
+            const T gn = g[b] - om * (g[b] - geq) + phi;
+            dm += g[b] - gn;
+            g[b] = gn;
         }
     } else {
         const T vx = jx * inv, vy = jy * inv;
@@ -118,19 +139,21 @@ __device__ __forceinline__ void collide_lat(T (&g)[L::Q], T drho, T Fx, T Fy, co
         const T vsq = T(0.5 * ics) * (vx * vx + vy * vy);
         const T dsq = T(0.5 * ics) * (dx * (T(2) * vx + dx) + dy * (T(2) * vy + dy));
 #pragma unroll
-        for (int b = 0; b < Q; ++b) {
+        for (int b = 1; b < Q; ++b) {
             const T cv = T(L::cx[b]) * vx + T(L::cy[b]) * vy;
             const T cd = T(L::cx[b]) * dx + T(L::cy[b]) * dy;
             const T w = T(L::w[b]);
             const T geq = w * (drho + rho * (T(ics) * cv + T(ics2h) * cv * cv - vsq));
             const T dfe = w * rho * (T(ics) * cd + T(ics2h) * cd * (T(2) * cv + cd) - dsq);
-            g[b] = g[b] - om * (g[b] - geq) + dfe;
+            const T gn = g[b] - om * (g[b] - geq) + dfe;
+            dm += g[b] - gn;
+            g[b] = gn;
         }
     }
-    g[0] = drho - TreeSum<1, Q - 1>::of(g);
+    g[0] += dm;
 }
 
-template <typename T, typename L, int ORDER, bool EDM, int TX, int TY, int RPT>
+template <typename T, typename L, int ORDER, bool EDM, bool WALLS, int TX, int TY, int RPT>
 __global__ void __launch_bounds__(TX*(TY / RPT))
 k_wide_tile(StepArgs<T> a, int nbx, int nby, int sw)
 {
@@ -155,24 +178,28 @@ k_wide_tile(StepArgs<T> a, int nbx, int nby, int sw)
     const uint32_t TS = sizeof(T), rowb = (uint32_t)nx * TS;
     const int xr = x0 + tx;
     const bool xin = xr < nx;
+    const int xw = xin ? xr : xr % nx;
     uint32_t xo[2 * M + 1];
-    offsets_m<M>(xin ? xr : xr % nx, nx, TS, xo);
+    offsets_m<M>(xw, nx, TS, xo);
 
     T g[RPT][Q];
     uint32_t own[RPT];
+    bool wall[RPT];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
         const int yr = y0 + ty * RPT + k;
+        const int yw = yr < ny ? yr : yr % ny;
         uint32_t yo[2 * M + 1];
-        offsets_m<M>(yr < ny ? yr : yr % ny, ny, rowb, yo);
+        offsets_m<M>(yw, ny, rowb, yo);
         own[k] = yo[M] + xo[M];
+        wall[k] = WALLS && a.solid[(int64_t)yw * nx + xw];
         pull_lat<T, L, M>(a.fin, n, xo, yo, g[k]);
     }
     T dr[RPT];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
         dr[k] = TreeSum<0, Q>::of(g[k]);
-        psi_s[(ty * RPT + k + R) * LW + tx + R] = psi_of(a.rho_ref + dr[k], a);
+        psi_s[(ty * RPT + k + R) * LW + tx + R] = wall[k] ? a.psi_w : psi_of(a.rho_ref + dr[k], a);
     }
     // halo ring: R rows above and below at full width, R columns each side
 #pragma unroll 1
@@ -191,9 +218,14 @@ k_wide_tile(StepArgs<T> a, int nbx, int nby, int sw)
             const int c = j % (2 * R);
             lx = c < R ? c : TX + c;
         }
+        const int hx = wrap_near(x0 - R + lx, nx), hy = wrap_near(y0 - R + ly, ny);
+        if (WALLS && a.solid[(int64_t)hy * nx + hx]) {
+            psi_s[ly * LW + lx] = a.psi_w;
+            continue;
+        }
         uint32_t hxo[2 * M + 1], hyo[2 * M + 1];
-        offsets_m<M>(wrap_near(x0 - R + lx, nx), nx, TS, hxo);
-        offsets_m<M>(wrap_near(y0 - R + ly, ny), ny, rowb, hyo);
+        offsets_m<M>(hx, nx, TS, hxo);
+        offsets_m<M>(hy, ny, rowb, hyo);
         T h[Q];
         pull_lat<T, L, M>(a.fin, n, hxo, hyo, h);
         psi_s[ly * LW + lx] = psi_of(a.rho_ref + TreeSum<0, Q>::of(h), a);
@@ -219,7 +251,15 @@ k_wide_tile(StepArgs<T> a, int nbx, int nby, int sw)
             }
         }
         const T pref = -a.gc0 * c[0];
-        collide_lat<T, L, EDM>(g[k], dr[k], pref * sx, pref * sy, a);
+        if (wall[k]) {
+            T r[Q];
+#pragma unroll
+            for (int b = 0; b < Q; ++b) r[b] = g[k][opposite<L>(b)];
+#pragma unroll
+            for (int b = 0; b < Q; ++b) g[k][b] = r[b];
+        } else {
+            collide_lat<T, L, EDM>(g[k], dr[k], pref * sx, pref * sy, a);
+        }
         if (xin && y0 + ly < ny) {
 #pragma unroll
             for (int b = 0; b < Q; ++b) st_off(a.fout + b * n, own[k], g[k][b]);
@@ -228,44 +268,44 @@ k_wide_tile(StepArgs<T> a, int nbx, int nby, int sw)
 }
 
 // Launch shapes of the any-lattice family (names as variant_name_wide()).
-template <typename T, typename L, int ORDER, bool EDM, int TX, int TY, int RPT>
+template <typename T, typename L, int ORDER, bool EDM, bool WALLS, int TX, int TY, int RPT>
 static hipError_t launch_wide_tile(const StepArgs<T>& a, hipStream_t s)
 {
     const int nbx = (a.nx + TX - 1) / TX, nby = (a.ny + TY - 1) / TY;
-    hipLaunchKernelGGL((k_wide_tile<T, L, ORDER, EDM, TX, TY, RPT>), dim3(nbx * nby), dim3(TX, TY / RPT), 0, s, a,
-                       nbx, nby, kStripTiles);
+    hipLaunchKernelGGL((k_wide_tile<T, L, ORDER, EDM, WALLS, TX, TY, RPT>), dim3(nbx * nby), dim3(TX, TY / RPT), 0,
+                       s, a, nbx, nby, kStripTiles);
     return hipGetLastError();
 }
 
-template <typename T, typename L, int ORDER, bool EDM>
+template <typename T, typename L, int ORDER, bool EDM, bool WALLS>
 static hipError_t launch_wide_shape(const StepArgs<T>& a, int variant, hipStream_t s)
 {
     switch (variant) {
-    case 0: return launch_wide_tile<T, L, ORDER, EDM, 64, 8, 2>(a, s);
-    case 1: return launch_wide_tile<T, L, ORDER, EDM, 32, 8, 1>(a, s);
-    case 2: return launch_wide_tile<T, L, ORDER, EDM, 64, 16, 4>(a, s);
-    case 3: return launch_wide_tile<T, L, ORDER, EDM, 64, 16, 2>(a, s);
+    case 0: return launch_wide_tile<T, L, ORDER, EDM, WALLS, 64, 8, 2>(a, s);
+    case 1: return launch_wide_tile<T, L, ORDER, EDM, WALLS, 32, 8, 1>(a, s);
+    case 2: return launch_wide_tile<T, L, ORDER, EDM, WALLS, 64, 16, 4>(a, s);
+    case 3: return launch_wide_tile<T, L, ORDER, EDM, WALLS, 64, 16, 2>(a, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <typename T, typename L, bool EDM>
+template <typename T, typename L, bool EDM, bool WALLS>
 static hipError_t launch_wide_order(const StepArgs<T>& a, int order, int variant, hipStream_t s)
 {
     switch (order) {
-    case 4: return launch_wide_shape<T, L, 4, EDM>(a, variant, s);
-    case 6: return launch_wide_shape<T, L, 6, EDM>(a, variant, s);
-    case 8: return launch_wide_shape<T, L, 8, EDM>(a, variant, s);
-    case 10: return launch_wide_shape<T, L, 10, EDM>(a, variant, s);
+    case 4: return launch_wide_shape<T, L, 4, EDM, WALLS>(a, variant, s);
+    case 6: return launch_wide_shape<T, L, 6, EDM, WALLS>(a, variant, s);
+    case 8: return launch_wide_shape<T, L, 8, EDM, WALLS>(a, variant, s);
+    case 10: return launch_wide_shape<T, L, 10, EDM, WALLS>(a, variant, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <typename T, typename L>
+template <typename T, typename L, bool WALLS>
 static hipError_t launch_wide_lattice(const StepArgs<T>& a, int order, bool edm, int variant, hipStream_t s)
 {
-    return edm ? launch_wide_order<T, L, true>(a, order, variant, s)
-               : launch_wide_order<T, L, false>(a, order, variant, s);
+    return edm ? launch_wide_order<T, L, true, WALLS>(a, order, variant, s)
+               : launch_wide_order<T, L, false, WALLS>(a, order, variant, s);
 }
 
 }  // namespace sclbm

@@ -62,7 +62,7 @@ class sc_lbm_obs(ctypes.Structure):
 EXPORTS = [
     "sc_lbm_default_params", "sc_lbm_state_bytes", "sc_lbm_create", "sc_lbm_step",
     "sc_lbm_force", "sc_lbm_observe", "sc_lbm_set_state", "sc_lbm_state_ptr",
-    "sc_lbm_variant_name", "sc_lbm_num_variants", "sc_lbm_destroy", "sc_lbm_strerror",
+    "sc_lbm_variant_name", "sc_lbm_num_variants", "sc_lbm_destroy", "sc_lbm_strerror", "sc_lbm_set_walls",
     "sc_lbm_last_error_detail", "sc_lbm_stream",
     "sc_lbm_batch_create", "sc_lbm_batch_step", "sc_lbm_batch_observe", "sc_lbm_batch_status",
     "sc_lbm_batch_active", "sc_lbm_batch_destroy", "sc_lbm_autotune",
@@ -123,6 +123,8 @@ def lib():
     L.sc_lbm_variant_name.argtypes = [vp]
     L.sc_lbm_variant_name.restype = ctypes.c_char_p
     L.sc_lbm_num_variants.argtypes = [P(sc_lbm_params)]
+    L.sc_lbm_set_walls.argtypes = [vp, vp, ctypes.c_double]
+    L.sc_lbm_set_walls.restype = ctypes.c_int
     L.sc_lbm_num_variants.restype = ctypes.c_int
     L.sc_lbm_destroy.argtypes = [vp]
     L.sc_lbm_destroy.restype = None
@@ -232,6 +234,15 @@ def sc_lbm_observe(h, rho_out=None, u_out=None, f_out=None):
 
 def sc_lbm_set_state(h, f_in, step):
     _check(lib().sc_lbm_set_state(h, f_in.ctypes.data_as(ctypes.c_void_p), int(step)), "sc_lbm_set_state")
+
+
+def sc_lbm_set_walls(h, solid, rho_w):
+    """solid: flat uint8 [N] in node order, or None to remove the walls."""
+    ptr = None
+    if solid is not None:
+        solid = np.ascontiguousarray(solid, dtype=np.uint8)
+        ptr = solid.ctypes.data_as(ctypes.c_void_p)
+    _check(lib().sc_lbm_set_walls(h, ptr, float(rho_w)), "sc_lbm_set_walls")
 
 
 def sc_lbm_state_ptr(h):
@@ -364,6 +375,15 @@ class Sim:
         f = np.zeros(self.q * self.n, dtype=dt)
         sc_lbm_observe(self.h, None, None, f)
         return f
+
+    def set_walls(self, solid, rho_w):
+        """Solid mask indexed [x, y] (nonzero = solid) and virtual wall
+        density; None removes the walls."""
+        flat = None
+        if solid is not None:
+            flat = np.ascontiguousarray(np.asarray(solid).transpose()).ravel().astype(np.uint8)
+        sc_lbm_set_walls(self.h, flat, rho_w)
+        return self
 
     def set_state(self, f, step):
         sc_lbm_set_state(self.h, np.ascontiguousarray(f), step)

@@ -1,0 +1,179 @@
+"""GPU parity of solid walls (standard bounce-back, virtual wall density in
+the force; Sec. 3, droplet on a flat wall) against the FP64 oracle.
+
+Tolerances as elsewhere: FP64 state <= 1e-11 pointwise at any horizon
+tested; FP32 state density <= 1e-5 relative, velocity <= 1e-3 of max |u|
+plus the FP32 momentum resolution (1e-7 max rho), up to 100 steps."""
+import warnings
+
+import numpy as np
+import pytest
+
+from oracle import eos as E
+from oracle import oracle as O
+from tests.gpu_helpers import rel_err, say
+from workload import droplet_rho
+
+pytestmark = pytest.mark.gpu
+warnings.simplefilter("ignore")
+
+torch = pytest.importorskip("torch")
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1906_11027_amd import Sim  # noqa: E402
+from paper_1906_11027_amd import sc_lbm as B  # noqa: E402
+
+TOL = {"fp32": (1e-5, 1e-3), "fp64": (1e-11, 1e-9)}
+UFLOOR = {"fp32": 1e-7, "fp64": 1e-15}
+CS2 = {"D2Q9": 1 / 3, "D2Q13": 2 / 5, "D2Q25": 4 / 7}
+
+
+def _compare(sim, orc, prec, label, solid):
+    got = sim.observe()
+    ref = orc.fields()
+    er = rel_err(got["rho"], ref["rho"])
+    umax = max(np.max(np.abs(ref["u"])), 1e-12)
+    du = float(np.max(np.abs(got["u"] - ref["u"])))
+    say("%s: rho rel err %.3e, u err / max|u| %.3e (max|u| %.3e)" % (label, er, du / umax, umax))
+    tr, tu = TOL[prec]
+    assert er <= tr, (label, er)
+    assert du <= tu * umax + UFLOOR[prec] * float(np.max(ref["rho"])), (label, du / umax)
+    assert np.all(got["u"][:, solid] == 0.0)
+    ob, oo = got["obs"], orc.observables()
+    for k in ("max_u", "mean_u"):
+        assert abs(ob[k] - oo[k]) <= (tu * oo[k] + UFLOOR[prec]), (k, ob[k], oo[k])
+    return got, ref
+
+
+def _channel(shape, layers=2, block=None):
+    m = np.zeros(shape, dtype=bool)
+    m[:, :layers] = True
+    m[:, shape[1] - layers:] = True
+    if block is not None:
+        (x0, x1), (y0, y1) = block
+        m[x0:x1, y0:y1] = True
+    return m
+
+
+def _wall_droplet(shape, r0, rl, rv, width=4.0, yc=2.0):
+    x, y = np.meshgrid(np.arange(shape[0]), np.arange(shape[1]), indexing="ij")
+    r = np.sqrt((x - shape[0] / 2.0) ** 2 + (y - yc) ** 2)
+    return 0.5 * (rl + rv) - 0.5 * (rl - rv) * np.tanh(2.0 * (r - r0) / width)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("lattice,order,forcing", [("D2Q9", 4, "guo"), ("D2Q9", 8, "edm"),
+                                                   ("D2Q13", 6, "edm"), ("D2Q25", 8, "guo")])
+def test_wall_droplet_parity(lattice, order, forcing, prec):
+    """Droplet on the bottom wall of a ragged 70 x 41 channel with an extra
+    obstacle block, exp psi with G scaled to the lattice's cs2."""
+    say("case walls", lattice, order, forcing, prec)
+    shape = (70, 41)
+    solid = _channel(shape, 2, block=((5, 9), (20, 27)))
+    rho0 = _wall_droplet(shape, 12.0, 2.0, 0.15, width=3.0)
+    kw = dict(order=order, G=-15.0 * CS2[lattice], tau=0.9, forcing=forcing)
+    sim = Sim(rho0, lattice, precision=prec, **kw).set_walls(solid, 1.1)
+    orc = O.Oracle(rho0, lattice, **kw).set_walls(solid, 1.1)
+    steps = (1, 99) if prec == "fp32" else (1, 99, 200)
+    for st in steps:
+        sim.step(st)
+        orc.step(st)
+        _compare(sim, orc, prec, "%s E%d %s %s t=%d" % (lattice, order, forcing, prec, orc.steps), solid)
+    sim.close()
+
+
+@pytest.mark.parametrize("lattice", ["D2Q9", "D2Q25"])
+def test_wall_variants(lattice):
+    """Every launch shape with walls against the oracle (FP64 state)."""
+    shape = (77, 45)
+    solid = _channel(shape, 2)
+    rho0 = _wall_droplet(shape, 11.0, 2.0, 0.15, width=3.0)
+    kw = dict(order=8, G=-15.0 * CS2[lattice], tau=1.0, forcing="edm")
+    orc = O.Oracle(rho0, lattice, **kw).set_walls(solid, 0.9)
+    orc.step(40)
+    nv = B.sc_lbm_num_variants(B.make_params(lattice, forcing="edm"))
+    for v in range(nv):
+        sim = Sim(rho0, lattice, variant=v, precision="fp64", **kw).set_walls(solid, 0.9)
+        sim.step(40)
+        _compare(sim, orc, "fp64", "%s variant %s" % (lattice, sim.variant), solid)
+        sim.close()
+
+
+def test_rest_state_between_walls_is_exact():
+    shape = (40, 24)
+    solid = _channel(shape, 2)
+    for lattice in ("D2Q9", "D2Q25"):
+        sim = Sim(np.full(shape, 1.3), lattice, order=8, G=-4.0, precision="fp64")
+        sim.set_walls(solid, 1.3)
+        sim.step(300)
+        got = sim.observe()
+        say(lattice, "rest max|u|", got["obs"]["max_u"])
+        assert got["obs"]["max_u"] < 1e-15
+        assert np.max(np.abs(got["rho"] - 1.3)) < 1e-14
+        sim.close()
+
+
+def test_walls_removed_restore_the_periodic_run():
+    """set_walls(None) goes back to the periodic kernels (and family)."""
+    shape = (64, 48)
+    rho0 = droplet_rho(shape, 12, seed=21)
+    a = Sim(rho0, "D2Q9", order=6, precision="fp64")
+    name = a.variant
+    a.set_walls(_channel(shape, 2), 1.0)
+    assert a.variant.startswith("wide")
+    a.set_walls(None, 0.0)
+    a.step(50)
+    b = Sim(rho0, "D2Q9", order=6, precision="fp64")
+    b.step(50)
+    assert np.array_equal(a.state(), b.state())
+    a.close()
+    b.close()
+    assert name.startswith("tile")
+
+
+def test_wall_mass_conservation_fp32():
+    shape = (96, 64)
+    solid = _channel(shape, 2)
+    sim = Sim(_wall_droplet(shape, 18.0, 2.0, 0.15), "D2Q25", order=8, G=-15.0 * 4 / 7, tau=1.0, forcing="edm")
+    sim.set_walls(solid, 1.2)
+    m0 = sim.observe()["obs"]["mass"]
+    sim.step(3000)
+    ob = sim.observe()["obs"]
+    say("wall fp32 mass drift", (ob["mass"] - m0) / m0)
+    assert abs(ob["mass"] - m0) < 2e-6 * m0 and ob["nonfinite"] == 0
+    sim.close()
+
+
+def test_wettability_runs_match_oracle():
+    """The Peng-Robinson wall droplet (T = 0.9 Tc, D2Q9 E4, EDM) for the
+    two virtual densities of Sec. 3 (1.5 and 4.5): the GPU fields after
+    6000 steps equal the oracle's, and the denser wall is wetted more."""
+    e = E.eos_params(0.9)
+    eos = {k: e[k] for k in ("a", "b", "R", "T", "alpha")}
+    rv, rl = E.maxwell(e)
+    shape = (80, 48)
+    solid = _channel(shape, 2)
+    rho0 = _wall_droplet(shape, 15.0, rl, rv)
+    kw = dict(order=4, G=-1.0, psi="pr", eos=eos, forcing="edm", tau=1.0)
+    spread = {}
+    for rw in (1.5, 4.5):
+        sim = Sim(rho0, "D2Q9", precision="fp64", **kw).set_walls(solid, rw)
+        orc = O.Oracle(rho0, "D2Q9", **kw).set_walls(solid, rw)
+        sim.step(6000)
+        orc.step(6000)
+        got, _ = _compare(sim, orc, "fp64", "P-R wall rho_w=%.1f" % rw, solid)
+        mid = 0.5 * (rl + rv)
+        spread[rw] = (int((got["rho"][:, 2] > mid).sum()), int((got["rho"][40, 2:-2] > mid).sum()))
+        sim.close()
+    say("base width, height", spread)
+    assert spread[4.5][0] > spread[1.5][0] and spread[4.5][1] < spread[1.5][1]
+
+
+def test_walls_rejected_in_3d():
+    sim = Sim(np.ones((8, 8, 8)), "D3Q19", order=4)
+    with pytest.raises(B.ScError) as ei:
+        sim.set_walls(np.zeros((8, 8, 8), dtype=bool), 1.0)
+    assert ei.value.code == B.SC_E_UNSUPPORTED
+    sim.close()
