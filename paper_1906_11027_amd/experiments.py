@@ -16,10 +16,13 @@ as 1 / (G c0)), so G = -1 and c0 = 1/3 are placeholders.
 
 Droplet (Sec. 3): 60 x 60 periodic, r0 = 15 at the centre, tanh profile
 between the Maxwell densities.  Flat interface: a liquid slab across a
-periodic strip.  Runs use the FP64 state and stop when max |u| changes by
-less than `tol` between checks.
+periodic strip.  Wall droplet (Sec. 3, last experiment): a drop on the
+bottom wall of a channel (walls two nodes thick, standard bounce-back) at
+T = 0.9 Tc, wettability set by the virtual wall density rho_w.  Runs use
+the FP64 state and stop when max |u| changes by less than `tol` between
+checks.
 
-Usage: python -m paper_1906_11027_amd.experiments [--droplet] [--flat] [--out FILE]
+Usage: python -m paper_1906_11027_amd.experiments [--droplet] [--flat] [--wall] [--out FILE]
 """
 import argparse
 import json
@@ -58,11 +61,13 @@ def slab_init(n, ny, thickness, rho_l, rho_v, width):
     return np.repeat(tanh_profile(d, rho_l, rho_v, width)[:, None], ny, axis=1)
 
 
-def run_model(model, Tr, rho0, max_steps, tol, precision="fp64", obs_every=500):
+def run_model(model, Tr, rho0, max_steps, tol, precision="fp64", obs_every=500, solid=None, rho_w=None):
     lattice, order, tau = MODELS[model]
     e = P.params_at(Tr)
     sim = Sim(rho0, lattice, order=order, tau=tau, G=-1.0, psi="pr", eos=e, forcing="edm",
               precision=precision, obs_every=obs_every)
+    if solid is not None:
+        sim.set_walls(solid, rho_w)
     rc, steps = sim.step(max_steps, tol=tol)
     out = sim.observe()
     sim.close()
@@ -112,17 +117,102 @@ def flat_interface(model, Tr, n=200, ny=4, thickness=100.0, width=4.0, max_steps
             "diverged": bool(r["diverged"]), "maxwell": [rv, rl]}
 
 
+def channel(shape, layers=2):
+    """Solid mask: walls `layers` nodes thick at the bottom and top (y)."""
+    m = np.zeros(shape, dtype=bool)
+    m[:, :layers] = True
+    m[:, shape[1] - layers:] = True
+    return m
+
+
+def _crossing(prof, level, start, step):
+    """Fractional index where prof crosses `level` walking from `start`."""
+    i = start
+    while 0 <= i + step < len(prof):
+        a, b = prof[i], prof[i + step]
+        if (a - level) * (b - level) <= 0 and a != b:
+            return i + step * (level - a) / (b - a)
+        i += step
+    return float("nan")
+
+
+def contact_angle(rho, layers, rho_l, rho_v, skip=3):
+    """Contact angle (degrees, through the liquid) of a drop on the bottom
+    wall.  The mid-density contour is located on every row from `skip`
+    nodes above the wall up (the rows next to the wall carry the wall's own
+    adsorption layer), fitted with a circle by linear least squares, and
+    intersected with the wall plane y_w (half-way between the last solid
+    and the first fluid row): cos(theta) = (y_w - y_c) / R.  A drop whose
+    fitted circle stays clear of the wall reads 180 degrees, liquid across
+    the whole width 0.  Returns (theta, circle radius, centre height)."""
+    mid = 0.5 * (rho_l + rho_v)
+    yw = layers - 0.5
+    ny = rho.shape[1]
+    top_fluid = ny - layers
+    if rho[:, layers + skip].min() > mid:
+        return 0.0, float("inf"), float("nan")
+    pts = []
+    for y in range(layers + skip, top_fluid - skip):
+        row = rho[:, y]
+        if row.max() < mid or row.min() > mid:
+            continue
+        xc = int(np.argmax(row))
+        for step in (-1, +1):
+            xcr = _crossing(row, mid, xc, step)
+            if np.isfinite(xcr):
+                pts.append((xcr, float(y)))
+    if len(pts) < 6:
+        return 180.0, float("nan"), float("nan")
+    P_ = np.array(pts)
+    A = np.column_stack([P_[:, 0], P_[:, 1], np.ones(len(P_))])
+    bvec = -(P_[:, 0] ** 2 + P_[:, 1] ** 2)
+    (D, E, F), *_ = np.linalg.lstsq(A, bvec, rcond=None)
+    xc0, yc0 = -D / 2.0, -E / 2.0
+    R = float(np.sqrt(xc0 * xc0 + yc0 * yc0 - F))
+    c = (yw - yc0) / R
+    if c <= -1.0:
+        return 180.0, R, float(yc0 - yw)
+    return float(np.degrees(np.arccos(min(1.0, c)))), R, float(yc0 - yw)
+
+
+def wall_droplet(model, rho_w, Tr=0.9, shape=(200, 100), r0=35.0, width=4.0, max_steps=400000, tol=1e-11):
+    """Steady drop on a flat wall: contact angle and spurious speeds.  The
+    wall nodes start at the vapour density: under full-way bounce-back the
+    rest and wall-parallel populations of a solid node never leave it, so
+    they should not carry the drop's liquid."""
+    rv, rl = P.maxwell(P.params_at(Tr))
+    x = np.arange(shape[0])[:, None] - shape[0] / 2.0
+    y = np.arange(shape[1])[None, :] - 2.0
+    rho0 = tanh_profile(np.sqrt(x * x + y * y) - r0, rl, rv, width)
+    solid = channel(shape, 2)
+    rho0[solid] = rv
+    r = run_model(model, Tr, rho0, max_steps, tol, solid=solid, rho_w=rho_w)
+    theta, R, hc = contact_angle(r["rho"], 2, rl, rv)
+    o = r["obs"]
+    return {"model": model, "Tr": Tr, "rho_w": rho_w, "theta_deg": theta, "cap_radius": R, "centre_height": hc,
+            "max_u": o["max_u"], "mean_u": o["mean_u"], "steps": r["steps"], "converged": bool(r["converged"]),
+            "diverged": bool(r["diverged"])}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--droplet", action="store_true")
     ap.add_argument("--flat", action="store_true")
+    ap.add_argument("--wall", action="store_true")
+    ap.add_argument("--wall-densities", default="1.5,2.0,2.5,3.0,3.5,4.0,4.5")
     ap.add_argument("--models", default=",".join(MODELS))
     ap.add_argument("--temps", default=",".join(str(t) for t in TEMPERATURES))
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     models = args.models.split(",")
     temps = [float(t) for t in args.temps.split(",")]
-    res = {"droplet": [], "flat": []}
+    res = {"droplet": [], "flat": [], "wall": []}
+    if args.wall:
+        for rw in [float(v) for v in args.wall_densities.split(",")]:
+            for m in ("D2Q9-ISO4", "D2Q9-ISO8", "D2Q13T", "D2Q25T"):
+                d = wall_droplet(m, rw)
+                print("wall", json.dumps(d), flush=True)
+                res["wall"].append(d)
     for Tr in temps:
         for m in models:
             if args.droplet:

@@ -88,3 +88,14 @@ def test_flat_interface_balance_thickness_and_oracle():
     err = float(np.max(np.abs(g - o.fields()["rho"]) / o.fields()["rho"]))
     say("slab D2Q13T 20000 steps rel err", err)
     assert err < 1e-10
+
+
+def test_wall_contact_angle_tunable_by_wall_density():
+    """Sec. 3, drop on a flat wall (P-R psi, T = 0.9 Tc, standard
+    bounce-back): the virtual wall density tunes the contact angle on the
+    larger lattices as on D2Q9 -- from non-wetting at rho_w = 1.5 to wetting
+    at 4.5, monotonically."""
+    for model in ("D2Q9-ISO4", "D2Q25T"):
+        th = [X.wall_droplet(model, rw)["theta_deg"] for rw in (1.5, 3.0, 4.5)]
+        say(model, th)
+        assert th[0] > 120.0 and th[2] < 50.0 and th[0] > th[1] > th[2]
