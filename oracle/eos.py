@@ -29,15 +29,20 @@ def kappa(omega=OMEGA):
 
 
 def critical_point(a=A, b=B, R=RGAS):
-    """(Tc, rho_c) from dp/drho = 0 and d2p/drho2 = 0 with alpha = 1."""
-    def dp(rho, T, h=1e-6):
-        return (pressure(rho + h, T, 1.0, a, b, R) - pressure(rho - h, T, 1.0, a, b, R)) / (2 * h)
+    """(Tc, rho_c) from dp/drho = 0 and d2p/drho2 = 0 with alpha = 1, both
+    derivatives written out: with D = 1 + 2 b rho - b^2 rho^2,
+        dp/drho   = R T / (1 - b rho)^2 - 2 a rho (1 + b rho) / D^2
+        d2p/drho2 = 2 b R T / (1 - b rho)^3
+                    - 2 a [(1 + 2 b rho) D - 4 rho (1 + b rho)(b - b^2 rho)] / D^3."""
+    def eqs(v):
+        T, rho = v
+        D = 1.0 + 2.0 * b * rho - b * b * rho * rho
+        d1 = R * T / (1.0 - b * rho) ** 2 - 2.0 * a * rho * (1.0 + b * rho) / D ** 2
+        d2 = (2.0 * b * R * T / (1.0 - b * rho) ** 3
+              - 2.0 * a * ((1.0 + 2.0 * b * rho) * D - 4.0 * rho * (1.0 + b * rho) * (b - b * b * rho)) / D ** 3)
+        return [d1, d2]
 
-    def d2p(rho, T, h=1e-4):
-        return (pressure(rho + h, T, 1.0, a, b, R) - 2 * pressure(rho, T, 1.0, a, b, R)
-                + pressure(rho - h, T, 1.0, a, b, R)) / (h * h)
-
-    sol = fsolve(lambda v: [dp(v[1], v[0]) * 1e2, d2p(v[1], v[0]) * 1e2], [0.07, 2.5], xtol=1e-13)
+    sol = fsolve(eqs, [0.07, 2.5], xtol=1e-14)
     return float(sol[0]), float(sol[1])
 
 
