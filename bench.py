@@ -61,6 +61,27 @@ WORKLOADS = {
 }
 Q_OF = {"D2Q9": 9, "D3Q19": 19, "D2Q13": 13, "D2Q25": 25}
 
+# HBM traffic per launch relative to the algorithmic bytes, (fetch, write), from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this script (one counter per run) scaled
+# by what the same counters read for a 256 MiB device copy (the counter
+# summary under profiles/).  Keyed by workload and launch shape; a shape
+# without an entry reports traffic null.  Re-measure after a kernel change.
+TRAFFIC_RATIO = {
+    ("d2q9_e8_256", "tile32x8r1"): (1.161, 1.000),
+    ("d2q9_e8_256", "tile64x4r1"): (1.166, 1.000),
+    ("d2q9_e8_256", "tile64x16r4"): (1.210, 1.000),
+    ("d2q9_e8_256", "tile64x8r2"): (1.183, 1.000),
+    ("d2q9_e8_8192", "tile64x16r4"): (1.526, 1.000),
+    ("d2q9_e8_8192", "tile64x8r2"): (1.304, 1.000),
+    ("d3q19_mrt_e8_320", "march64x8r1h64pf1"): (1.244, 1.000),
+    ("d3q19_mrt_e8_320", "march64x8r1h32pf1"): (1.335, 1.000),
+    ("d2q13_e6_pr_edm_8192", "wide64x16r2"): (1.823, 1.000),
+    ("d2q13_e6_pr_edm_8192", "wide64x16r4"): (1.867, 1.000),
+    ("d2q25_e8_pr_edm_8192", "wide64x16r2"): (1.798, 1.000),
+    ("d2q25_e8_pr_edm_8192", "wide64x16r4"): (2.094, 1.000),
+}
+
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -138,14 +159,36 @@ def measure(name, steps, warmup, kernel_launches=50):
     # one fused launch per step: its average duration is the graph-timed
     # per-step time (an upper bound: it includes the gap between launches)
     achieved = bpn * n / (ms / steps * 1e-3) / 1e9
+    tr = TRAFFIC_RATIO.get((name, variant))
+    traffic = None if tr is None else (tr[0] + tr[1]) * bpn * n / 2.0
     return {
         "workload": name, "desc": w["desc"], "nodes": n, "steps": steps, "ms_total": ms,
         "ms_per_step": ms / steps, "wall_s": wall, "mlups": mlups,
         "single_launch_ms_mean": kmean, "single_launch_ms_median": kms[len(kms) // 2],
         "bytes_per_node": bpn,
         "achieved_gbs": achieved, "frac": achieved / HBM_PEAK_GBS, "variant": variant,
-        "finite": bool(ok), "max_u": ob["max_u"],
+        "finite": bool(ok), "max_u": ob["max_u"], "traffic_bytes": traffic,
+        "traffic_ratio": None if tr is None else (tr[0] + tr[1]) / 2.0,
     }
+
+
+def copy_ceiling(nbytes=1 << 30, reps=8):
+    """Streaming ceiling of the GPU: a device-to-device copy of 1 GiB timed
+    with events (read + write bytes per second, best of `reps`)."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = 1e30
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    return {"bytes": 2 * nbytes, "ms": best, "gbs": 2 * nbytes / (best * 1e-3) / 1e9}
 
 
 def steady_droplet():
@@ -256,7 +299,10 @@ def main():
             r = measure(name, st, 10, kernel_launches=10)
             log(name + ":", json.dumps(r))
             extra[name] = {k: r[k] for k in ("mlups", "ms_per_step", "single_launch_ms_mean",
-                                             "achieved_gbs", "frac", "variant", "finite")}
+                                             "achieved_gbs", "frac", "variant", "finite", "traffic_ratio")}
+        cc = copy_ceiling()
+        log("copy:", json.dumps(cc))
+        extra["copy_ceiling"] = cc
         sd = steady_droplet()
         log("steady:", json.dumps(sd))
         extra["steady_droplet"] = sd
@@ -286,7 +332,8 @@ def main():
                    "grid": list(w["shape"]), "stencil_order": w["order"], "variant": main_r["variant"]},
         "roofline": {"bound": "hbm", "achieved": round(main_r["achieved_gbs"], 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(main_r["frac"], 4),
-                     "traffic": None,
+                     "traffic": main_r["traffic_bytes"],
+                     "traffic_ratio": main_r["traffic_ratio"],
                      "kernel": "k_d2q9_tile<float, %d, ...> (%s)" % (w["order"], main_r["variant"]),
                      "kernel_ms_mean": main_r["ms_per_step"],
                      "bytes_per_launch": main_r["bytes_per_node"] * main_r["nodes"]},
