@@ -307,6 +307,7 @@ hipError_t launch_step_d2q9(const StepArgs<double>& a, int order, int variant, h
 hipError_t launch_step_d3q19(const StepArgs<float>& a, int order, bool mrt, int variant, hipStream_t s);
 hipError_t launch_step_d3q19(const StepArgs<double>& a, int order, bool mrt, int variant, hipStream_t s);
 int num_variants_d2q9();
+int variant_steps_d2q9(int v);   // time steps one launch of the shape advances (1 or 2)
 int num_variants_d3q19();
 const char* variant_name_d2q9(int v);
 const char* variant_name_d3q19(int v);

@@ -231,6 +231,150 @@ k_d2q9_march(StepArgs<T> a, int H, int nbx)
     }
 }
 
+// Two time steps per launch (temporal blocking) for small, latency-bound
+// grids, where the launch itself costs as much as a step.  A block owns a
+// TX x TY tile and computes, with R the force-stencil radius:
+//   phase 1  psi at t+1 on the tile + (2R+1) halo: pull the 9 values of each
+//            node from the state (L2 / MALL), sum, psi -> LDS psi1;
+//   phase 2  step t -> t+1 on the tile + (R+1) halo: pull again (now cache
+//            hits), force from psi1, collide -> LDS s1 (post-collision);
+//   phase 3  psi at t+2 on the tile + R halo, pulling from s1 -> LDS psi2;
+//   phase 4  step t+1 -> t+2 on the tile: pull from s1, force from psi2,
+//            collide, store.
+// The halo nodes are recomputed by the neighbouring tiles (about 1.9x the
+// node updates at 16 x 16), so this shape pays off only where launches
+// dominate.  Every region is walked by a bounded loop over its node count;
+// nodes outside the grid are computed on wrapped coordinates and not stored.
+template <typename T, int ORDER, int TX, int TY>
+__global__ void __launch_bounds__(TX* TY)
+k_d2q9_tile2(StepArgs<T> a, int nbx, int nby, int sw)
+{
+    using ST = Stencil<2, ORDER>;
+    constexpr int R = ST::R;
+    constexpr int NT = TX * TY;
+    constexpr int H1 = 2 * R + 1, P1W = TX + 2 * H1, P1H = TY + 2 * H1, P1N = P1W * P1H;   // psi1
+    constexpr int HC = R + 1, C1W = TX + 2 * HC, C1H = TY + 2 * HC, C1N = C1W * C1H;       // s1
+    constexpr int P2W = TX + 2 * R, P2H = TY + 2 * R, P2N = P2W * P2H;                     // psi2
+    __shared__ T psi1[P1N];
+    __shared__ T psi2[P2N];
+    __shared__ T s1[9 * C1N];
+
+    const int nx = a.nx, ny = a.ny;
+    const int64_t n = a.n;
+    const uint32_t TS = sizeof(T), rowb = (uint32_t)nx * TS;
+    const int tid = threadIdx.y * TX + threadIdx.x;
+    int bx, by;
+    strip_tile(xcd_swizzle(blockIdx.x, gridDim.x), nbx, nby, sw, bx, by);
+    const int x0 = bx * TX, y0 = by * TY;
+
+    auto pull_global = [&](int gx, int gy, T (&g)[9]) {
+        uint32_t xo[3], yo[3];
+        nbr_offsets<T>(wrap_near(gx, nx), nx, TS, xo);
+        nbr_offsets<T>(wrap_near(gy, ny), ny, rowb, yo);
+        pull_d2q9(a.fin, n, xo, yo, g);
+    };
+    auto force_at = [&](const T* c, int LW, T& Fx, T& Fy) {
+        T sx = T(0), sy = T(0), ax = T(0), ay = T(0);
+#pragma unroll
+        for (int p = 0; p < ST::NP; ++p) {
+            constexpr PairList P = ST::P;
+            const int ex = P.e[p][0], ey = P.e[p][1];
+            const T d = c[ey * LW + ex] - c[-ey * LW - ex];
+            if (ex) ax += T(ex) * d;
+            if (ey) ay += T(ey) * d;
+            if (P.shell_end(p)) {
+                sx += T(P.w[p]) * ax;
+                sy += T(P.w[p]) * ay;
+                ax = ay = T(0);
+            }
+        }
+        const T pref = -a.gc0 * c[0];
+        Fx = pref * sx;
+        Fy = pref * sy;
+    };
+
+    // phase 1: psi at t+1 on the tile + (2R+1) halo.  The per-thread node
+    // loop has a compile-time bound and is unrolled, so the pulls of all its
+    // nodes are in flight together.
+    constexpr int K1 = (P1N + NT - 1) / NT;
+    {
+        T g[K1][9];
+#pragma unroll
+        for (int q = 0; q < K1; ++q) {
+            const int i = tid + q * NT;
+            if (i < P1N) {
+                const int ly = i / P1W, lx = i - ly * P1W;
+                pull_global(x0 - H1 + lx, y0 - H1 + ly, g[q]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < K1; ++q) {
+            const int i = tid + q * NT;
+            if (i < P1N) psi1[i] = psi_of(a.rho_ref + sum9(g[q]), a);
+        }
+    }
+    __syncthreads();
+    // phase 2: step t -> t+1 on the tile + (R+1) halo (pulls again: cache hits)
+    constexpr int K2 = (C1N + NT - 1) / NT;
+    {
+        T g[K2][9];
+#pragma unroll
+        for (int q = 0; q < K2; ++q) {
+            const int i = tid + q * NT;
+            if (i < C1N) {
+                const int ly = i / C1W, lx = i - ly * C1W;
+                pull_global(x0 - HC + lx, y0 - HC + ly, g[q]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < K2; ++q) {
+            const int i = tid + q * NT;
+            if (i < C1N) {
+                const int ly = i / C1W, lx = i - ly * C1W;
+                T Fx, Fy;
+                force_at(psi1 + (ly + R) * P1W + lx + R, P1W, Fx, Fy);
+                collide_d2q9_srt(g[q], sum9(g[q]), Fx, Fy, a);
+#pragma unroll
+                for (int b = 0; b < 9; ++b) s1[b * C1N + i] = g[q][b];
+            }
+        }
+    }
+    __syncthreads();
+    // pull at t+2 of the node at s1 coordinates (cx, cy): value b from (cx - c_b, cy - c_b)
+    auto pull_s1 = [&](int cx, int cy, T (&g)[9]) {
+#pragma unroll
+        for (int b = 0; b < 9; ++b) g[b] = s1[b * C1N + (cy - D2Q9::cy[b]) * C1W + cx - D2Q9::cx[b]];
+    };
+    // phase 3: psi at t+2 on the tile + R halo
+    constexpr int K3 = (P2N + NT - 1) / NT;
+#pragma unroll
+    for (int q = 0; q < K3; ++q) {
+        const int i = tid + q * NT;
+        if (i < P2N) {
+            const int ly = i / P2W, lx = i - ly * P2W;
+            T g[9];
+            pull_s1(lx + 1, ly + 1, g);
+            psi2[i] = psi_of(a.rho_ref + sum9(g), a);
+        }
+    }
+    __syncthreads();
+    // phase 4: step t+1 -> t+2 on the tile, store
+    {
+        const int lx = threadIdx.x, ly = threadIdx.y;
+        T g[9];
+        pull_s1(lx + HC, ly + HC, g);
+        T Fx, Fy;
+        force_at(psi2 + (ly + R) * P2W + lx + R, P2W, Fx, Fy);
+        collide_d2q9_srt(g, sum9(g), Fx, Fy, a);
+        const int xr = x0 + lx, yr = y0 + ly;
+        if (xr < nx && yr < ny) {
+            const uint32_t off = (uint32_t)yr * rowb + (uint32_t)xr * TS;
+#pragma unroll
+            for (int b = 0; b < 9; ++b) st_off(a.fout + b * n, off, g[b]);
+        }
+    }
+}
+
 // ------------------------------------------------------------ dispatch ----
 struct Shape2D {
     const char* name;
@@ -238,10 +382,12 @@ struct Shape2D {
 static const Shape2D kShapes2D[] = {
     {"tile64x16r4"}, {"tile64x8r2"}, {"tile32x8r1"}, {"tile64x4r1"},
     {"march256h128"}, {"march256h128pf2"}, {"march512h128"}, {"march256h128pf3"}, {"march512h128pf2"},
+    {"tile2x16x16"}, {"tile2x32x8"}, {"tile2x32x16"}, {"tile2x64x8"}, {"tile2x64x16"}, {"tile2x32x32"},
 };
 constexpr int kNumShapes2D = sizeof(kShapes2D) / sizeof(kShapes2D[0]);
 
 int num_variants_d2q9() { return kNumShapes2D; }
+int variant_steps_d2q9(int v) { return (v >= 9 && v <= 14) ? 2 : 1; }
 const char* variant_name_d2q9(int v) { return (v >= 0 && v < kNumShapes2D) ? kShapes2D[v].name : "?"; }
 
 template <typename T, int ORDER, int TX, int TY, int RPT>
@@ -250,6 +396,15 @@ static hipError_t launch_tile(const StepArgs<T>& a, hipStream_t s)
     const int nbx = (a.nx + TX - 1) / TX, nby = (a.ny + TY - 1) / TY;
     dim3 block(TX, TY / RPT);
     hipLaunchKernelGGL((k_d2q9_tile<T, ORDER, TX, TY, RPT>), dim3(nbx * nby), block, 0, s, a, nbx, nby,
+                       kStripTiles);
+    return hipGetLastError();
+}
+
+template <typename T, int ORDER, int TX, int TY>
+static hipError_t launch_tile2(const StepArgs<T>& a, hipStream_t s)
+{
+    const int nbx = (a.nx + TX - 1) / TX, nby = (a.ny + TY - 1) / TY;
+    hipLaunchKernelGGL((k_d2q9_tile2<T, ORDER, TX, TY>), dim3(nbx * nby), dim3(TX, TY), 0, s, a, nbx, nby,
                        kStripTiles);
     return hipGetLastError();
 }
@@ -278,6 +433,12 @@ static hipError_t launch_order(const StepArgs<T>& a, int variant, hipStream_t s)
     case 6: return launch_march<T, ORDER, 512, 1>(a, 128, s);
     case 7: return launch_march<T, ORDER, 256, 3>(a, 128, s);
     case 8: return launch_march<T, ORDER, 512, 2>(a, 128, s);
+    case 9: return launch_tile2<T, ORDER, 16, 16>(a, s);
+    case 10: return launch_tile2<T, ORDER, 32, 8>(a, s);
+    case 11: return launch_tile2<T, ORDER, 32, 16>(a, s);
+    case 12: return launch_tile2<T, ORDER, 64, 8>(a, s);
+    case 13: return launch_tile2<T, ORDER, 64, 16>(a, s);
+    case 14: return launch_tile2<T, ORDER, 32, 32>(a, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -471,31 +471,44 @@ extern "C" void* sc_lbm_state_ptr(sc_lbm* h) { return h ? h->f[h->cur] : nullptr
 
 extern "C" void* sc_lbm_stream(sc_lbm* h) { return h ? (void*)h->stream : nullptr; }
 
+// Time steps one launch of the handle's shape advances (the two-step D2Q9
+// shapes fuse two steps per launch).
+static int steps_per_launch(const sc_lbm* h)
+{
+    return handle_family(h) == kFamD2Q9 ? variant_steps_d2q9(h->variant) : 1;
+}
+
+// single-step D2Q9 shape used for the odd step of a two-step shape
+constexpr int kSingleStepD2Q9 = 2;   // tile32x8r1
+
 template <typename T>
-static hipError_t launch_family(sc_lbm* h, const StepArgs<T>& a)
+static hipError_t launch_family(sc_lbm* h, const StepArgs<T>& a, bool single = false)
 {
     const sc_lbm_params& p = h->p;
     switch (handle_family(h)) {
-    case kFamD2Q9: return launch_step_d2q9(a, p.order, h->variant, h->stream);
+    case kFamD2Q9:
+        return launch_step_d2q9(a, p.order, single && variant_steps_d2q9(h->variant) != 1 ? kSingleStepD2Q9 : h->variant,
+                                h->stream);
     case kFamD3Q19: return launch_step_d3q19(a, p.order, p.collision == SC_MRT, h->variant, h->stream);
     default: return launch_step_wide(p.lattice, a, p.order, p.forcing == SC_EDM, h->variant, h->stream);
     }
 }
 
-// one fused step from f[cur] into f[cur ^ 1] (no swap)
-static hipError_t enqueue_step(sc_lbm* h, int from)
+// one fused launch from f[from] into f[from ^ 1] (no swap): steps_per_launch(h)
+// steps, or exactly one step when `single` is set
+static hipError_t enqueue_step(sc_lbm* h, int from, bool single = false)
 {
     const sc_lbm_params& p = h->p;
     if (p.precision == SC_FP32_SHIFTED) {
         StepArgs<float> a = h->af;
         a.fin = (const float*)h->f[from];
         a.fout = (float*)h->f[from ^ 1];
-        return launch_family(h, a);
+        return launch_family(h, a, single);
     }
     StepArgs<double> a = h->ad;
     a.fin = (const double*)h->f[from];
     a.fout = (double*)h->f[from ^ 1];
-    return launch_family(h, a);
+    return launch_family(h, a, single);
 }
 
 static hipError_t build_graph(sc_lbm* h, int from)
@@ -504,7 +517,8 @@ static hipError_t build_graph(sc_lbm* h, int from)
     hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     hipError_t le = hipSuccess;
-    for (int k = 0; k < kGraphSteps && le == hipSuccess; ++k) le = enqueue_step(h, from ^ (k & 1));
+    const int launches = kGraphSteps / steps_per_launch(h);   // even: the graph keeps the buffer parity
+    for (int k = 0; k < launches && le == hipSuccess; ++k) le = enqueue_step(h, from ^ (k & 1));
     e = hipStreamEndCapture(h->stream, &g);
     if (le != hipSuccess) e = le;
     if (e == hipSuccess) e = hipGraphInstantiate(&h->gexec[from], g, nullptr, nullptr, 0);
@@ -531,11 +545,15 @@ static hipError_t run_steps(sc_lbm* h, int64_t count)
         count -= kGraphSteps;
         h->step += kGraphSteps;
     }
-    for (; count > 0; --count) {
-        e = enqueue_step(h, h->cur);
+    const int spl = steps_per_launch(h);
+    while (count > 0) {
+        const bool single = count < spl;
+        e = enqueue_step(h, h->cur, single);
         if (e != hipSuccess) return e;
+        const int adv = single ? 1 : spl;
         h->cur ^= 1;
-        h->step += 1;
+        h->step += adv;
+        count -= adv;
     }
     return hipSuccess;
 }

@@ -1,7 +1,8 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
 
 Tolerances.  FP32 state: density <= 1e-5 relative pointwise and velocity
-<= 1e-3 of max |u| up to 100 steps.  Beyond that the FP32 rounding drives a
+<= 1e-3 of max |u| (plus the FP32 momentum resolution, 1e-7 max rho, where
+max |u| is itself near round-off) up to 100 steps.  Beyond that the FP32 rounding drives a
 slow drift of the interface (measured: ~1e-5 at 200 steps, ~2e-4 at 3000,
 largest at interface nodes, for every storage shift), so long runs are
 compared on the observables the method reports (spurious max / mean |u|
@@ -28,6 +29,9 @@ from paper_1906_11027_amd import Sim  # noqa: E402
 from paper_1906_11027_amd import sc_lbm as B  # noqa: E402
 
 TOL = {"fp32": (1e-5, 1e-3), "fp64": (1e-11, 1e-9)}
+# absolute velocity floor: the FP32 state resolves momentum to about its ulp
+# times rho (2^-24 ~ 6e-8), which matters where max |u| itself is tiny
+UFLOOR = {"fp32": 1e-7, "fp64": 1e-15}
 
 
 def _compare(sim, orc, prec, label):
@@ -35,11 +39,12 @@ def _compare(sim, orc, prec, label):
     ref = orc.fields()
     er = rel_err(got["rho"], ref["rho"])
     umax = max(np.max(np.abs(ref["u"])), 1e-12)
-    eu = float(np.max(np.abs(got["u"] - ref["u"])) / umax)
+    du = float(np.max(np.abs(got["u"] - ref["u"])))
+    eu = du / umax
     say("%s: rho rel err %.3e, u err / max|u| %.3e (max|u| %.3e)" % (label, er, eu, umax))
     tr, tu = TOL[prec]
     assert er <= tr, (label, er)
-    assert eu <= tu, (label, eu)
+    assert du <= tu * umax + UFLOOR[prec] * float(np.max(ref["rho"])), (label, eu)
     return got, ref
 
 
@@ -58,6 +63,27 @@ def test_d2q9_droplet_64(order, prec):
         orc.step(steps)
         _compare(sim, orc, prec, "E%d %s t=%d" % (order, prec, orc.steps))
     sim.close()
+
+
+@pytest.mark.parametrize("variant", [9, 10, 11, 12, 13, 14])
+@pytest.mark.parametrize("shape,order", [((37, 29), 10), ((3, 5), 4), ((1, 16), 6), ((64, 64), 8)])
+def test_d2q9_two_step_shapes(shape, order, variant):
+    """Shapes that fuse two steps per launch, on ragged and tiny grids, with
+    odd step counts (the last step runs single) and graph-replayed runs."""
+    say("case two-step shape", variant, shape, order)
+    rho0 = droplet_rho(shape, min(shape) / 3.0, seed=6)
+    orc = O.Oracle(rho0, "D2Q9", order=order, tau=0.9)
+    sim = Sim(rho0, "D2Q9", order=order, precision="fp64", tau=0.9, variant=variant)
+    sim32 = Sim(rho0, "D2Q9", order=order, precision="fp32", tau=0.9, variant=variant)
+    assert sim.variant.startswith("tile2")
+    for steps in (1, 6, 33, 40):
+        sim.step(steps)
+        sim32.step(steps)
+        orc.step(steps)
+        _compare(sim, orc, "fp64", "%s %s E%d fp64 t=%d" % (sim.variant, shape, order, orc.steps))
+        _compare(sim32, orc, "fp32", "%s %s E%d fp32 t=%d" % (sim.variant, shape, order, orc.steps))
+    sim.close()
+    sim32.close()
 
 
 @pytest.mark.parametrize("shape,order", [((37, 29), 10), ((8, 8), 8), ((3, 5), 4), ((1, 16), 6),
