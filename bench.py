@@ -61,24 +61,34 @@ WORKLOADS = {
 }
 Q_OF = {"D2Q9": 9, "D3Q19": 19, "D2Q13": 13, "D2Q25": 25}
 
-# HBM traffic per launch relative to the algorithmic bytes, (fetch, write), from
+# HBM traffic per launch relative to the algorithmic bytes of the launch
+# (steps per launch x read Q + write Q per node), (fetch, write), from
 # rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this script (one counter per run) scaled
 # by what the same counters read for a 256 MiB device copy (the counter
 # summary under profiles/).  Keyed by workload and launch shape; a shape
 # without an entry reports traffic null.  Re-measure after a kernel change.
 TRAFFIC_RATIO = {
-    ("d2q9_e8_256", "tile32x8r1"): (1.161, 1.000),
-    ("d2q9_e8_256", "tile64x4r1"): (1.166, 1.000),
-    ("d2q9_e8_256", "tile64x16r4"): (1.210, 1.000),
-    ("d2q9_e8_256", "tile64x8r2"): (1.183, 1.000),
-    ("d2q9_e8_8192", "tile64x16r4"): (1.526, 1.000),
-    ("d2q9_e8_8192", "tile64x8r2"): (1.304, 1.000),
-    ("d3q19_mrt_e8_320", "march64x8r1h64pf1"): (1.244, 1.000),
-    ("d3q19_mrt_e8_320", "march64x8r1h32pf1"): (1.335, 1.000),
     ("d2q13_e6_pr_edm_8192", "wide64x16r2"): (1.823, 1.000),
     ("d2q13_e6_pr_edm_8192", "wide64x16r4"): (1.867, 1.000),
     ("d2q25_e8_pr_edm_8192", "wide64x16r2"): (1.798, 1.000),
     ("d2q25_e8_pr_edm_8192", "wide64x16r4"): (2.094, 1.000),
+    ("d2q9_e8_256", "tile2x16x16"): (0.907, 0.500),
+    ("d2q9_e8_256", "tile2x32x16"): (0.696, 0.500),
+    ("d2q9_e8_256", "tile2x32x32"): (0.695, 0.500),
+    ("d2q9_e8_256", "tile2x32x8"): (0.705, 0.500),
+    ("d2q9_e8_256", "tile2x64x16"): (0.695, 0.500),
+    ("d2q9_e8_256", "tile2x64x8"): (0.698, 0.500),
+    ("d2q9_e8_256", "tile32x8r1"): (1.161, 1.000),
+    ("d2q9_e8_256", "tile64x4r1"): (1.166, 1.000),
+    ("d2q9_e8_8192", "tile2x16x16"): (2.855, 0.519),
+    ("d2q9_e8_8192", "tile2x32x16"): (1.025, 0.500),
+    ("d2q9_e8_8192", "tile2x32x32"): (0.873, 0.500),
+    ("d2q9_e8_8192", "tile2x32x8"): (0.767, 0.500),
+    ("d2q9_e8_8192", "tile2x64x16"): (0.574, 0.500),
+    ("d2q9_e8_8192", "tile2x64x8"): (0.565, 0.500),
+    ("d2q9_e8_8192", "tile64x16r4"): (1.526, 1.000),
+    ("d3q19_mrt_e8_320", "march64x8r1h32pf1"): (1.335, 1.000),
+    ("d3q19_mrt_e8_320", "march64x8r1h64pf1"): (1.244, 1.000),
 }
 
 
@@ -152,6 +162,7 @@ def measure(name, steps, warmup, kernel_launches=50):
     kmean = sum(kms) / len(kms)
     ob = sim.observe(fields=False)["obs"]
     variant = sim.variant
+    sim_spl = sim.steps_per_launch
     sim.close()
     ok = ob["nonfinite"] == 0 and ob["mass"] > 0
     mlups = n * steps / (ms * 1e-3) / 1e6
@@ -159,8 +170,9 @@ def measure(name, steps, warmup, kernel_launches=50):
     # one fused launch per step: its average duration is the graph-timed
     # per-step time (an upper bound: it includes the gap between launches)
     achieved = bpn * n / (ms / steps * 1e-3) / 1e9
+    spl = sim_spl
     tr = TRAFFIC_RATIO.get((name, variant))
-    traffic = None if tr is None else (tr[0] + tr[1]) * bpn * n / 2.0
+    traffic = None if tr is None else (tr[0] + tr[1]) * spl * bpn * n / 2.0
     return {
         "workload": name, "desc": w["desc"], "nodes": n, "steps": steps, "ms_total": ms,
         "ms_per_step": ms / steps, "wall_s": wall, "mlups": mlups,
@@ -169,6 +181,7 @@ def measure(name, steps, warmup, kernel_launches=50):
         "achieved_gbs": achieved, "frac": achieved / HBM_PEAK_GBS, "variant": variant,
         "finite": bool(ok), "max_u": ob["max_u"], "traffic_bytes": traffic,
         "traffic_ratio": None if tr is None else (tr[0] + tr[1]) / 2.0,
+        "steps_per_launch": spl, "launch_ms": spl * ms / steps, "bytes_per_launch": spl * bpn * n,
     }
 
 
@@ -299,7 +312,8 @@ def main():
             r = measure(name, st, 10, kernel_launches=10)
             log(name + ":", json.dumps(r))
             extra[name] = {k: r[k] for k in ("mlups", "ms_per_step", "single_launch_ms_mean",
-                                             "achieved_gbs", "frac", "variant", "finite", "traffic_ratio")}
+                                             "achieved_gbs", "frac", "variant", "finite", "traffic_ratio",
+                                             "steps_per_launch")}
         cc = copy_ceiling()
         log("copy:", json.dumps(cc))
         extra["copy_ceiling"] = cc
@@ -334,9 +348,11 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(main_r["frac"], 4),
                      "traffic": main_r["traffic_bytes"],
                      "traffic_ratio": main_r["traffic_ratio"],
-                     "kernel": "k_d2q9_tile<float, %d, ...> (%s)" % (w["order"], main_r["variant"]),
-                     "kernel_ms_mean": main_r["ms_per_step"],
-                     "bytes_per_launch": main_r["bytes_per_node"] * main_r["nodes"]},
+                     "kernel": "%s<float, %d, ...> (%s)" % ("k_d2q9_tile2" if main_r["steps_per_launch"] == 2
+                                                             else "k_d2q9_tile", w["order"], main_r["variant"]),
+                     "steps_per_launch": main_r["steps_per_launch"],
+                     "kernel_ms_mean": main_r["launch_ms"],
+                     "bytes_per_launch": main_r["bytes_per_launch"]},
         "cpu_baseline": cpu,
         "extra": extra,
     }

@@ -218,6 +218,11 @@ int sc_lbm_autotune(const sc_lbm_params* p, int32_t steps, int32_t* best_variant
 const char* sc_lbm_variant_name(const sc_lbm* h);
 int sc_lbm_num_variants(const sc_lbm_params* p);
 
+/* Time steps one kernel launch of the handle's launch shape advances: 1, or
+ * 2 for the D2Q9 shapes that fuse two steps per launch (temporal blocking;
+ * sc_lbm_step still advances exactly the steps asked for).  0 on NULL. */
+int sc_lbm_steps_per_launch(const sc_lbm* h);
+
 void sc_lbm_destroy(sc_lbm* h);
 const char* sc_lbm_strerror(int code);
 

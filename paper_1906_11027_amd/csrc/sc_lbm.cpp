@@ -214,6 +214,15 @@ extern "C" int sc_lbm_num_variants(const sc_lbm_params* p)
     return family_variants(family_of(*p));
 }
 
+// Time steps one launch of the handle's shape advances (the two-step D2Q9
+// shapes fuse two steps per launch).
+static int steps_per_launch(const sc_lbm* h)
+{
+    return handle_family(h) == kFamD2Q9 ? variant_steps_d2q9(h->variant) : 1;
+}
+
+extern "C" int sc_lbm_steps_per_launch(const sc_lbm* h) { return h ? steps_per_launch(h) : 0; }
+
 extern "C" const char* sc_lbm_variant_name(const sc_lbm* h)
 {
     if (!h) return "";
@@ -471,12 +480,6 @@ extern "C" void* sc_lbm_state_ptr(sc_lbm* h) { return h ? h->f[h->cur] : nullptr
 
 extern "C" void* sc_lbm_stream(sc_lbm* h) { return h ? (void*)h->stream : nullptr; }
 
-// Time steps one launch of the handle's shape advances (the two-step D2Q9
-// shapes fuse two steps per launch).
-static int steps_per_launch(const sc_lbm* h)
-{
-    return handle_family(h) == kFamD2Q9 ? variant_steps_d2q9(h->variant) : 1;
-}
 
 // single-step D2Q9 shape used for the odd step of a two-step shape
 constexpr int kSingleStepD2Q9 = 2;   // tile32x8r1

@@ -63,6 +63,7 @@ EXPORTS = [
     "sc_lbm_default_params", "sc_lbm_state_bytes", "sc_lbm_create", "sc_lbm_step",
     "sc_lbm_force", "sc_lbm_observe", "sc_lbm_set_state", "sc_lbm_state_ptr",
     "sc_lbm_variant_name", "sc_lbm_num_variants", "sc_lbm_destroy", "sc_lbm_strerror", "sc_lbm_set_walls",
+    "sc_lbm_steps_per_launch",
     "sc_lbm_last_error_detail", "sc_lbm_stream",
     "sc_lbm_batch_create", "sc_lbm_batch_step", "sc_lbm_batch_observe", "sc_lbm_batch_status",
     "sc_lbm_batch_active", "sc_lbm_batch_destroy", "sc_lbm_autotune",
@@ -123,6 +124,8 @@ def lib():
     L.sc_lbm_variant_name.argtypes = [vp]
     L.sc_lbm_variant_name.restype = ctypes.c_char_p
     L.sc_lbm_num_variants.argtypes = [P(sc_lbm_params)]
+    L.sc_lbm_steps_per_launch.argtypes = [vp]
+    L.sc_lbm_steps_per_launch.restype = ctypes.c_int
     L.sc_lbm_set_walls.argtypes = [vp, vp, ctypes.c_double]
     L.sc_lbm_set_walls.restype = ctypes.c_int
     L.sc_lbm_num_variants.restype = ctypes.c_int
@@ -396,6 +399,11 @@ class Sim:
     @property
     def variant(self):
         return sc_lbm_variant_name(self.h)
+
+    @property
+    def steps_per_launch(self):
+        """Time steps one kernel launch of the current shape advances."""
+        return lib().sc_lbm_steps_per_launch(self.h)
 
 
 # ---------------------------------------------------------------------------
