@@ -15,10 +15,12 @@ psi and the exact difference method), the wall time of a 64^2 E4 droplet run
 to its steady state and the batched 64-droplet sweep.
 
 Timing: HIP events on the library's stream around K graph-replayed steps,
-bracketed by device synchronisation.  The roofline uses the fused kernel's
-average duration from events around single launches.  The CPU baseline is
-the FP64 oracle on the host cores, on a bounded number of steps of the same
-workload.
+bracketed by device synchronisation.  The roofline takes the fused kernel's
+time per launch as steps per launch (1, or 2 for the D2Q9 shapes that block
+two steps in time) x the event-timed time per step, which includes the gap
+between launches; its traffic is the tuned shape's measured HBM bytes per
+launch (TRAFFIC_RATIO).  The CPU baseline is the FP64 oracle on the host
+cores, on a bounded number of steps of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extra] [--no-cpu]
 """
@@ -205,7 +207,7 @@ def copy_ceiling(nbytes=1 << 30, reps=8):
 
 
 def steady_droplet():
-    """Config-1 droplet (64^2, E4, R = 16) run to steady state on the GPU."""
+    """The 64^2 E4 droplet (R = 16) run to steady state on the GPU."""
     import torch
 
     from paper_1906_11027_amd import Sim
@@ -287,7 +289,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the step would shard)", file=sys.stderr)
+              "(a domain would shard into slabs along its slowest axis with a halo exchange per step; "
+              "not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -151,7 +151,9 @@ int sc_lbm_create(const sc_lbm_params* p, const double* rho_init, void* dev_a, v
                   void* hip_stream, sc_lbm** out);
 
 /* Advance the state (Sec. 2, Eq. (1), (3), (4): psi, force, collision and
- * pull streaming fused in one kernel per step).
+ * pull streaming fused in one kernel per step, or per two steps for the
+ * D2Q9 launch shapes that block two steps in time; see
+ * sc_lbm_steps_per_launch).
  *   max_steps  steps to run (>= 0);
  *   tol        0: run exactly max_steps, asynchronously (nothing is read
  *              back); > 0: every K = obs_every steps reduce max |u| and stop
@@ -268,7 +270,7 @@ void sc_lbm_batch_destroy(sc_lbm_batch* b);
 /* ---- learned warm start: network kernels -------------------------------- */
 /* Not part of the paper's method: a small convolutional net predicts the
  * steady density of a droplet from its parameters so the iteration above
- * starts closer to its fixed point (the iteration stays the judge of the
+ * starts closer to its fixed point (the iteration alone decides the
  * steady state).  Every pointer below is DEVICE memory owned by the caller;
  * every call is asynchronous on `stream` (a hipStream_t or NULL) and returns
  * SC_OK, SC_E_INVAL (bad size or NULL pointer) or SC_E_DEVICE.

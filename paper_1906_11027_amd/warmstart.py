@@ -10,7 +10,7 @@ start and training moves it towards the steady state.  The prediction
 (tanh start + residual), clamped to a physical range and shifted to the mass
 of the tanh start (mass is conserved by the step, so the steady state is
 fixed by it), becomes the initial condition; the lattice Boltzmann iteration
-still runs to its own steady state and remains the judge of it.
+still runs to its own steady state and alone decides when it is reached.
 
 Every arithmetic step runs in the library's kernels (sc_nn_* for the net,
 sc_lbm_batch_* for the data); torch only allocates device memory and
@@ -304,7 +304,7 @@ def evaluate(ds, epochs=20, batch=16, lr=2e-3, fp64_baseline=8, seed=2026, log=p
 
 def run_experiment(n_train=2000, n_test=64, side=256, tol=1e-8, epochs=20, batch=16, lr=2e-3,
                    max_steps=150000, obs_every=200, chunk=64, fp64_baseline=8, seed=2026, log=print):
-    """Config-5 experiment: dataset from batched sweeps, then evaluate()."""
+    """The 256^2 warm-start experiment: dataset from batched sweeps, then evaluate()."""
     ds = make_dataset(n_train, n_test, side, tol, max_steps, obs_every, chunk, seed, log=log)
     return evaluate(ds, epochs=epochs, batch=batch, lr=lr, fp64_baseline=fp64_baseline, seed=seed, log=log)
 

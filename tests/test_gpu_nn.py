@@ -175,7 +175,7 @@ def test_training_reduces_loss():
 
 
 def test_warm_start_gain_small():
-    """Scaled-down config-5 run on 64^2 droplets.  What the trained net gains
+    """Scaled-down warm-start experiment on 64^2 droplets.  What the trained net gains
     over the tanh start: an initial density field several times closer to the
     steady state; both starts reach the same steady field.  Steps to the
     max|u| criterion are reported, not asserted: that criterion is governed by

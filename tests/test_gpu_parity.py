@@ -53,7 +53,7 @@ def _compare(sim, orc, prec, label):
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 @pytest.mark.parametrize("order", [4, 6, 8, 10])
 def test_d2q9_droplet_64(order, prec):
-    """Config-1 geometry (64^2, R = 16, G = -5, tau = 1) at a short horizon."""
+    """The 64^2 droplet (R = 16, G = -5, tau = 1) at a short horizon."""
     say("case d2q9 64x64 order", order, prec)
     rho0 = droplet_rho((64, 64), 16, seed=1)
     sim = Sim(rho0, "D2Q9", order=order, precision=prec)
@@ -290,7 +290,7 @@ def test_mass_conservation_fp64():
 
 
 @pytest.mark.parametrize("order", [4, 8])
-def test_config1_long_horizon_observables(order):
+def test_droplet_64_long_horizon_observables(order):
     """64^2 droplet (R = 16, G = -5, tau = 1) for 10,000 steps: FP32 GPU
     spurious-velocity norms and Laplace jump against the FP64 oracle; the
     FP64 GPU state pointwise."""
