@@ -83,6 +83,11 @@ extern "C" {
 #define SC_FP32_SHIFTED 0      /* float state stored as f - w rho_ref       */
 #define SC_FP64 1              /* double state (same shift)                 */
 
+#define SC_INIT_EQUILIBRIUM 0  /* f = feq(rho_init, 0)                      */
+#define SC_INIT_REST 1         /* f = feq(rho_init, -F / (2 rho_init)): the
+                                  forced velocity (sum f c + F/2) / rho is
+                                  zero at t = 0                              */
+
 /* ---- problem statement -------------------------------------------------- */
 typedef struct sc_lbm_params {
     int32_t lattice;      /* SC_D2Q9, SC_D3Q19, SC_D2Q13 or SC_D2Q25             */
@@ -103,7 +108,7 @@ typedef struct sc_lbm_params {
     int32_t obs_every;    /* K: steps between convergence checks (default 100)    */
     int32_t variant;      /* launch shape of the fused kernel; -1 = automatic     */
     int32_t forcing;      /* SC_GUO or SC_EDM                                     */
-    /* (4 bytes of padding) */
+    int32_t init;         /* SC_INIT_EQUILIBRIUM or SC_INIT_REST (sc_lbm_create)   */
     double eos_a, eos_b;  /* Peng-Robinson a, b (SC_PSI_PR; Sec. 3: 2/49, 2/21)   */
     double eos_R, eos_T;  /* gas constant and absolute temperature                */
     double eos_alpha;     /* alpha(T) of the Peng-Robinson attraction term        */
@@ -111,7 +116,8 @@ typedef struct sc_lbm_params {
 
 /* Fills *p with the defaults: D2Q9 64x64, E4, G = -5, c0 = 1/3, exp psi with
  * psi0 = rho_psi = 1, tau = 1, SRT, Guo forcing, FP32 shifted, MRT rates 1.2,
- * rho_ref = 1, K = 100, automatic variant, EOS fields zero. */
+ * rho_ref = 1, K = 100, automatic variant, EOS fields zero,
+ * SC_INIT_EQUILIBRIUM. */
 void sc_lbm_default_params(sc_lbm_params* p);
 
 /* ---- observables (FP64 reductions) -------------------------------------- */
@@ -138,8 +144,16 @@ typedef struct sc_lbm sc_lbm;
 /* Bytes of one state buffer: Q * nx * ny * nz * (4 or 8); 0 if *p is invalid. */
 size_t sc_lbm_state_bytes(const sc_lbm_params* p);
 
-/* Validate *p, take the device buffers and initialise the state to
- * f = feq(rho_init, u = 0) (the droplet test of Sec. 3 starts this way).
+/* Validate *p, take the device buffers and initialise the state.
+ * p->init == SC_INIT_EQUILIBRIUM: f = feq(rho_init, u = 0), the usual start
+ * of the droplet test (Sec. 3; the paper does not state its initial
+ * populations).
+ * p->init == SC_INIT_REST: f = feq(rho_init, -F / (2 rho_init)) with F the
+ * interaction force (Eq. (1)) of psi(rho_init) on the periodic grid, so
+ * that the velocity the forcing schemes report, (sum_b f_b c_b + F/2) / rho
+ * (Guo, Eq. (4); the exact difference method the same), is zero at t = 0:
+ * the fluid starts at rest in the forced sense.  Both keep rho = rho_init;
+ * walls set later do not change the initial state.
  *   rho_init  host [N] doubles, or NULL for rho = 1 everywhere;
  *   dev_a/b   two device buffers of sc_lbm_state_bytes(p) bytes each, owned
  *             by the caller and kept until sc_lbm_destroy; both NULL makes
@@ -317,10 +331,27 @@ int sc_nn_adam(float* p, const float* g, float* m, float* v, uint16_t* p_bf16, i
 int sc_nn_to_bf16(const float* x, uint16_t* y, int64_t n, void* stream);
 
 /* Network input: out [batch][5][h][w] with channel 0 = distance of the node to
- * the domain centre (w/2, h/2) divided by scale_r and channels 1..4 the four
- * per-image values params[batch][4] broadcast over the grid. */
+ * the domain centre (w/2, h/2) divided by scale_r, minus params[b][0] (the
+ * droplet radius in the same units, so channel 0 is of order one across the
+ * interface and bfloat16 weights place it to a fraction of a node), and
+ * channels 1..4 the four per-image values params[batch][4] broadcast over
+ * the grid. */
 int sc_nn_features(const float* params, float* out, int32_t batch, int32_t h, int32_t wd, float scale_r,
                    void* stream);
+
+/* Initial density of a learned start (device buffers, one image per
+ * workgroup): out[b] = the average over the 8 symmetries of the square
+ * about node (h/2, h/2) (mirror of either axis, transpose) of
+ * base[b] + inv_scale * resid[b], clamped to [lo, hi], then shifted
+ * uniformly so that its sum equals mass[b].  A droplet centred on that node
+ * of a periodic square grid keeps this symmetry under the step, so the
+ * average removes only asymmetric error of the prediction.
+ *   resid  float [batch][h][w] (the net's output), base and out double
+ *          [batch][h][w], mass double [batch]; h must equal w.
+ * Errors: SC_E_INVAL (NULL pointer, h != w, batch outside 1..65535,
+ * lo > hi), SC_E_DEVICE. */
+int sc_nn_start_field(const float* resid, const double* base, const double* mass, double* out, int32_t batch,
+                      int32_t h, int32_t wd, float inv_scale, double lo, double hi, void* stream);
 
 /* Detail of the last HIP failure seen by this host thread (which call, the
  * HIP error string and code); "" if none.  Valid until the next failure. */

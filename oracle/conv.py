@@ -11,6 +11,11 @@ Definitions (NCHW arrays, circular padding):
             gbias[o]      = sum_{b, p} gout[b, o, p]
     net:    five 3x3 convolutions, tanh after the first four.
     loss:   mean squared error.
+    input:  channel 0 = |node - (w/2, h/2)| / scale_r - params[0], channels
+            1..4 = params broadcast.
+    start:  the initial field of a learned start: the average over the eight
+            symmetries of the square about node (n/2, n/2) of
+            base + resid / scale, clamped, then shifted to a given mass.
 """
 import numpy as np
 
@@ -88,3 +93,40 @@ def net_backward(params, acts, gout):
         grads[li] = (gw, gb)
         g = gin
     return grads
+
+
+def features(params, h, w, scale_r):
+    """params [B][4] -> input [B][5][h][w]."""
+    yy, xx = np.meshgrid(np.arange(h), np.arange(w), indexing="ij")
+    r = np.sqrt((xx - w // 2) ** 2.0 + (yy - h // 2) ** 2.0) / scale_r
+    params = np.asarray(params, dtype=np.float64)
+    out = np.empty((len(params), 5, h, w))
+    for b, p in enumerate(params):
+        out[b, 0] = r - p[0]
+        for c in range(4):
+            out[b, c + 1] = p[c]
+    return out
+
+
+def square_images(a):
+    """The eight images of an n x n field under the symmetries of the square
+    about node (c, c), c = n // 2: index i -> 2c - i (mod n) on either axis,
+    and the transpose."""
+    n = a.shape[0]
+    c = n // 2
+    m = (2 * c - np.arange(n)) % n
+    out = []
+    for t in (a, a.T):
+        for fi in (False, True):
+            for fj in (False, True):
+                im = t[m] if fi else t
+                out.append(im[:, m] if fj else im)
+    return out
+
+
+def start_field(resid, base, mass, scale, lo, hi):
+    """resid, base [n][n]; returns the learned start's initial density."""
+    v = base + np.asarray(resid, dtype=np.float64) / scale
+    v = np.mean(square_images(v), axis=0)
+    v = np.clip(v, lo, hi)
+    return v + (mass - v.sum()) / v.size

@@ -43,6 +43,7 @@ class Params(ctypes.Structure):
         ("s_ghost", ctypes.c_double), ("forcing", ctypes.c_int),
         ("pr_a", ctypes.c_double), ("pr_b", ctypes.c_double), ("pr_R", ctypes.c_double),
         ("pr_T", ctypes.c_double), ("pr_alpha", ctypes.c_double),
+        ("init", ctypes.c_int),
     ]
 
 
@@ -112,8 +113,10 @@ def stencil_table(dim, order):
 
 def make_params(lattice="D2Q9", shape=(64, 64), order=4, G=-5.0, c0=1.0 / 3.0,
                 psi="exp", psi0=1.0, rho_psi=1.0, tau=1.0, collision="srt",
-                s_bulk=1.2, s_ghost=1.2, forcing="guo", eos=None):
-    """eos: for psi == "pr", a dict with a, b, R, T (absolute) and alpha."""
+                s_bulk=1.2, s_ghost=1.2, forcing="guo", eos=None, init="equilibrium"):
+    """eos: for psi == "pr", a dict with a, b, R, T (absolute) and alpha.
+    init: "equilibrium" (f = feq(rho0, 0)) or "rest" (f = feq(rho0, -F/(2 rho0)),
+    zero forced velocity at t = 0)."""
     shape = tuple(shape)
     nx, ny = shape[0], shape[1]
     nz = shape[2] if len(shape) > 2 else 1
@@ -122,7 +125,8 @@ def make_params(lattice="D2Q9", shape=(64, 64), order=4, G=-5.0, c0=1.0 / 3.0,
                   {"exp": 0, "identity": 1, "pr": 2}[psi], psi0, rho_psi, tau,
                   {"srt": 0, "mrt": 1}[collision], s_bulk, s_ghost,
                   {"guo": 0, "edm": 1}[forcing], eos.get("a", 0.0), eos.get("b", 0.0),
-                  eos.get("R", 0.0), eos.get("T", 0.0), eos.get("alpha", 0.0))
+                  eos.get("R", 0.0), eos.get("T", 0.0), eos.get("alpha", 0.0),
+                  {"equilibrium": 0, "rest": 1}[init])
 
 
 def force(psi_field, lattice="D2Q9", order=4, G=-5.0, c0=1.0 / 3.0):
@@ -144,7 +148,7 @@ class Oracle:
 
     def __init__(self, rho0, lattice="D2Q9", order=4, G=-5.0, c0=1.0 / 3.0,
                  psi="exp", psi0=1.0, rho_psi=1.0, tau=1.0, collision="srt",
-                 s_bulk=1.2, s_ghost=1.2, forcing="guo", eos=None):
+                 s_bulk=1.2, s_ghost=1.2, forcing="guo", eos=None, init="equilibrium"):
         rho0 = np.asarray(rho0, dtype=np.float64)
         self.shape = rho0.shape
         self.dim = DIMS[lattice]
@@ -153,7 +157,7 @@ class Oracle:
         self.psi_kind, self.psi0, self.rho_psi = psi, psi0, rho_psi
         self.tau = tau
         self.p = make_params(lattice, self.shape, order, G, c0, psi, psi0, rho_psi,
-                             tau, collision, s_bulk, s_ghost, forcing, eos)
+                             tau, collision, s_bulk, s_ghost, forcing, eos, init)
         self.eos = eos
         self.n = rho0.size
         self._dim, self.c, self.w, self.cs2 = lattice_table(lattice)

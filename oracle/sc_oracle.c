@@ -58,6 +58,8 @@ typedef struct {
     double s_bulk, s_ghost; /* MRT rates of the c^2 moment and the ghosts */
     int forcing;            /* 0 Guo (Sec. 2, Eq. (4)); 1 exact difference method */
     double pr_a, pr_b, pr_R, pr_T, pr_alpha;  /* P-R EOS: a, b, R, T, alpha(T) */
+    int init;               /* 0: f = feq(rho0, 0); 1: at rest in the forced
+                               sense, f = feq(rho0, -F / (2 rho0)) */
 } orc_params;
 
 typedef struct {
@@ -456,6 +458,20 @@ orc_sim *orc_create(const orc_params *p, const double *rho0)
     for (int b = 0; b < s->q; ++b)
         for (long i = 0; i < s->n; ++i) s->f[b * s->n + i] = s->w[b] * rho0[i];
     macro(s);
+    if (p->init == 1) {
+        /* The forcing schemes report u = (sum f c + F/2) / rho; starting
+         * from the equilibrium of v = -F / (2 rho) makes that zero.  rho is
+         * unchanged (the equilibrium keeps the density), so F is too. */
+        double v[3], fe[25];
+        for (long i = 0; i < s->n; ++i) {
+            for (int d = 0; d < 3; ++d) v[d] = d < s->dim ? -s->F[d * s->n + i] / (2.0 * rho0[i]) : 0.0;
+            feq_of(s, rho0[i], v, fe);
+            for (int b = 0; b < s->q; ++b) s->f[b * s->n + i] = fe[b];
+        }
+        macro(s);
+    } else if (p->init != 0) {
+        goto fail;
+    }
     return s;
 fail:
     if (s) {

@@ -332,6 +332,9 @@ hipError_t launch_wide_q25(const StepArgs<double>& a, int order, bool edm, int v
 // the next step sees f = feq(rho0, u = 0) everywhere.  lattice: SC_* id.
 hipError_t launch_init(int lattice, void* f, int precision, const double* rho0, int nx, int ny, int nz,
                        double rho_ref, hipStream_t s);
+// f = feq(rho0, -F / (2 rho0)) with F [D][N] (device doubles), placed like launch_init.
+hipError_t launch_init_rest(int lattice, void* f, int precision, const double* rho0, const double* F, int nx,
+                            int ny, int nz, double rho_ref, hipStream_t s);
 
 // Observables: macroscopic fields of the current state and FP64 reductions.
 constexpr int kObsSlots = 9;   // reduction slots per block (observe.hip)

@@ -265,9 +265,58 @@ __global__ void k_features(const float* __restrict__ prm, float* __restrict__ ou
         const int y = (int)(p / wd), x = (int)(p % wd);
         const float dx = (float)(x - wd / 2), dy = (float)(y - h / 2);
         float* ob = out + (int64_t)b * 5 * plane + p;
-        ob[0] = sqrtf(dx * dx + dy * dy) / scale_r;
+        // distance to the centre relative to the radius carried in params[b][0]
+        ob[0] = sqrtf(dx * dx + dy * dy) / scale_r - prm[b * 4];
         for (int c = 0; c < 4; ++c) ob[(int64_t)(c + 1) * plane] = prm[b * 4 + c];
     }
+}
+
+// Initial field of a learned start, one workgroup per image (n x n):
+// v = mean over the 8 symmetries of the square about node (c, c), c = n/2,
+// of base + inv_scale * resid; clamp to [lo, hi]; then shift uniformly to
+// the target mass.  Sums in double.
+constexpr int kStartThreads = 1024;
+
+__global__ void __launch_bounds__(kStartThreads)
+k_start_field(const float* __restrict__ resid, const double* __restrict__ base, const double* __restrict__ mass,
+              double* __restrict__ out, int n, float inv_scale, double lo, double hi)
+{
+    __shared__ double red[kStartThreads / 64];
+    __shared__ double shift;
+    const int64_t plane = (int64_t)n * n;
+    const float* r = resid + blockIdx.x * plane;
+    const double* bs = base + blockIdx.x * plane;
+    double* o = out + blockIdx.x * plane;
+    const int c2 = 2 * (n / 2);
+    double acc = 0.0;
+    for (int64_t p = threadIdx.x; p < plane; p += blockDim.x) {
+        const int i = (int)(p / n), j = (int)(p % n);
+        const int ii[2] = {i, (c2 - i + n) % n};
+        const int jj[2] = {j, (c2 - j + n) % n};
+        double v = 0.0;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                const int64_t q0 = (int64_t)ii[a] * n + jj[b];
+                const int64_t q1 = (int64_t)jj[b] * n + ii[a];
+                v += (bs[q0] + (double)(inv_scale * r[q0])) + (bs[q1] + (double)(inv_scale * r[q1]));
+            }
+        v *= 0.125;
+        v = v < lo ? lo : (v > hi ? hi : v);
+        o[p] = v;
+        acc += v;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < kStartThreads / 64; ++k) t += red[k];
+        shift = (mass[blockIdx.x] - t) / (double)plane;
+    }
+    __syncthreads();
+    const double d = shift;
+    for (int64_t p = threadIdx.x; p < plane; p += blockDim.x) o[p] += d;
 }
 
 static int grid_for(int64_t n)
@@ -391,5 +440,17 @@ extern "C" int sc_nn_features(const float* params, float* out, int32_t batch, in
     if (!params || !out || batch < 1 || h < 1 || wd < 1 || !(scale_r > 0.f)) return SC_E_INVAL;
     hipLaunchKernelGGL(k_features, grid_for((int64_t)batch * h * wd), 256, 0, (hipStream_t)stream, params, out, batch,
                        h, wd, scale_r);
+    return nn_status(hipGetLastError());
+}
+
+extern "C" int sc_nn_start_field(const float* resid, const double* base, const double* mass, double* out,
+                                 int32_t batch, int32_t h, int32_t wd, float inv_scale, double lo, double hi,
+                                 void* stream)
+{
+    if (!resid || !base || !mass || !out || batch < 1 || batch > 65535 || h < 1 || h != wd || !(lo <= hi) ||
+        (int64_t)h * wd > ((int64_t)1 << 31))
+        return SC_E_INVAL;
+    hipLaunchKernelGGL(k_start_field, batch, kStartThreads, 0, (hipStream_t)stream, resid, base, mass, out, h,
+                       inv_scale, lo, hi);
     return nn_status(hipGetLastError());
 }

@@ -76,6 +76,45 @@ __global__ void k_init(T* __restrict__ f, const double* __restrict__ rho0, int n
     }
 }
 
+// Rest start: the equilibrium of velocity v = -F / (2 rho) at every node,
+// so that (sum_b f_b c_b + F/2) / rho = 0.  Same placement as k_init; the
+// shifted value w_b [(rho - rho_ref) + rho (c.v / cs2 + (c.v)^2 / (2 cs2^2)
+// - v.v / (2 cs2))] is formed in double before the store.
+template <typename T, typename L, int M>
+__global__ void k_init_rest(T* __restrict__ f, const double* __restrict__ rho0, const double* __restrict__ F,
+                            int nx, int ny, int nz, double rho_ref)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    const double ics2 = 1.0 / L::cs2;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t zo[3] = {0, 0, 0}, yo[3] = {0, 0, 0};
+        int xo[3] = {0, 0, 0};
+        int x = 0, y = 0, z = 0;
+        if constexpr (M == 1)
+            neighbours<L>(i, nx, ny, nz, zo, yo, xo);
+        else
+            coords(i, nx, ny, x, y, z);
+#pragma unroll
+        for (int b = 0; b < L::Q; ++b) {
+            int64_t src;
+            if constexpr (M == 1)
+                src = zo[1 + L::cz[b]] + yo[1 + L::cy[b]] + xo[1 + L::cx[b]];
+            else
+                src = shifted_node(x, y, z, L::cx[b], L::cy[b], L::cz[b], nx, ny, nz);
+            const double r = rho0[src];
+            const double h = -0.5 / r;
+            const double vx = h * F[src];
+            const double vy = h * F[n + src];
+            const double vz = L::D == 3 ? h * F[2 * n + src] : 0.0;
+            const double cv = L::cx[b] * vx + L::cy[b] * vy + L::cz[b] * vz;
+            const double vv = vx * vx + vy * vy + vz * vz;
+            const double e = cv * ics2 + 0.5 * cv * cv * ics2 * ics2 - 0.5 * vv * ics2;
+            f[b * n + i] = (T)(L::w[b] * ((r - rho_ref) + r * e));
+        }
+    }
+}
+
 // --------------------------------------------------------------- macro ----
 // rho, psi and j = sum_b f_b c_b of the pulled (pre-collision) state.
 template <typename T, typename L, int M>
@@ -285,6 +324,28 @@ hipError_t launch_init(int lattice, void* f, int precision, const double* rho0, 
 {
     return precision == 0 ? init_t<float>(lattice, (float*)f, rho0, nx, ny, nz, rho_ref, s)
                           : init_t<double>(lattice, (double*)f, rho0, nx, ny, nz, rho_ref, s);
+}
+
+template <typename T>
+static hipError_t init_rest_t(int lattice, T* f, const double* rho0, const double* F, int nx, int ny, int nz,
+                              double rho_ref, hipStream_t s)
+{
+    const int g = grid_for((int64_t)nx * ny * nz, 256);
+    switch (lattice) {
+    case 0: hipLaunchKernelGGL((k_init_rest<T, D2Q9, 1>), g, 256, 0, s, f, rho0, F, nx, ny, nz, rho_ref); break;
+    case 1: hipLaunchKernelGGL((k_init_rest<T, D3Q19, 1>), g, 256, 0, s, f, rho0, F, nx, ny, nz, rho_ref); break;
+    case 2: hipLaunchKernelGGL((k_init_rest<T, D2Q13, 2>), g, 256, 0, s, f, rho0, F, nx, ny, nz, rho_ref); break;
+    case 3: hipLaunchKernelGGL((k_init_rest<T, D2Q25, 2>), g, 256, 0, s, f, rho0, F, nx, ny, nz, rho_ref); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_init_rest(int lattice, void* f, int precision, const double* rho0, const double* F, int nx,
+                            int ny, int nz, double rho_ref, hipStream_t s)
+{
+    return precision == 0 ? init_rest_t<float>(lattice, (float*)f, rho0, F, nx, ny, nz, rho_ref, s)
+                          : init_rest_t<double>(lattice, (double*)f, rho0, F, nx, ny, nz, rho_ref, s);
 }
 
 template <typename T>

@@ -189,6 +189,7 @@ static int validate_problem(const sc_lbm_params* p)
         if (!(p->s_bulk > 0.0 && p->s_bulk < 2.0) || !(p->s_ghost > 0.0 && p->s_ghost < 2.0)) return SC_E_INVAL;
     }
     if (p->obs_every < 0) return SC_E_INVAL;
+    if (p->init != SC_INIT_EQUILIBRIUM && p->init != SC_INIT_REST) return SC_E_INVAL;
     return SC_OK;
 }
 
@@ -378,6 +379,9 @@ static void release(sc_lbm* h)
     delete h;
 }
 
+static int ensure_obs(sc_lbm* h);
+static const void* args_ptr(sc_lbm* h);
+
 extern "C" int sc_lbm_create(const sc_lbm_params* p, const double* rho_init, void* dev_a, void* dev_b,
                              void* hip_stream, sc_lbm** out)
 {
@@ -454,6 +458,23 @@ extern "C" int sc_lbm_create(const sc_lbm_params* p, const double* rho_init, voi
     if (e == hipSuccess) {
         where = "init kernel";
         e = launch_init(p->lattice, h->f[0], p->precision, rho_d, p->nx, p->ny, p->nz, p->rho_ref, h->stream);
+    }
+    if (e == hipSuccess && p->init == SC_INIT_REST) {
+        // F of psi(rho_init) from the equilibrium state just written, then
+        // the populations again at the equilibrium of -F / (2 rho)
+        rc = ensure_obs(h);
+        if (rc != SC_OK) {
+            hipFree(rho_d);
+            release(h);
+            return rc;
+        }
+        ObsBuffers& b = h->obs.b;
+        where = "rest initialisation";
+        e = launch_macro(p->lattice, p->precision, h->f[0], args_ptr(h), b, h->stream);
+        if (e == hipSuccess) e = launch_force(h->dim, p->precision, p->order, args_ptr(h), b, false, h->stream);
+        if (e == hipSuccess)
+            e = launch_init_rest(p->lattice, h->f[0], p->precision, rho_d, b.F, p->nx, p->ny, p->nz, p->rho_ref,
+                                 h->stream);
     }
     if (e == hipSuccess) {
         where = "hipStreamSynchronize(create)";

@@ -23,6 +23,7 @@ SC_PSI_EXP, SC_PSI_IDENTITY, SC_PSI_PR = 0, 1, 2
 SC_GUO, SC_EDM = 0, 1
 SC_SRT, SC_MRT = 0, 1
 SC_FP32_SHIFTED, SC_FP64 = 0, 1
+SC_INIT_EQUILIBRIUM, SC_INIT_REST = 0, 1
 
 LATTICE = {"D2Q9": SC_D2Q9, "D3Q19": SC_D3Q19, "D2Q13": SC_D2Q13, "D2Q25": SC_D2Q25}
 Q = {SC_D2Q9: 9, SC_D3Q19: 19, SC_D2Q13: 13, SC_D2Q25: 25}
@@ -37,6 +38,7 @@ class sc_lbm_params(ctypes.Structure):
         ("collision", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("s_bulk", ctypes.c_double), ("s_ghost", ctypes.c_double), ("rho_ref", ctypes.c_double),
         ("obs_every", ctypes.c_int32), ("variant", ctypes.c_int32), ("forcing", ctypes.c_int32),
+        ("init", ctypes.c_int32),
         ("eos_a", ctypes.c_double), ("eos_b", ctypes.c_double), ("eos_R", ctypes.c_double),
         ("eos_T", ctypes.c_double), ("eos_alpha", ctypes.c_double),
     ]
@@ -69,7 +71,7 @@ EXPORTS = [
     "sc_lbm_batch_active", "sc_lbm_batch_destroy", "sc_lbm_autotune",
     "sc_nn_conv3x3_fwd", "sc_nn_conv3x3_bwd_data", "sc_nn_bwd_weight_scratch_floats",
     "sc_nn_conv3x3_bwd_weight", "sc_nn_tanh_fwd", "sc_nn_tanh_bwd", "sc_nn_mse", "sc_nn_adam",
-    "sc_nn_to_bf16", "sc_nn_features",
+    "sc_nn_to_bf16", "sc_nn_features", "sc_nn_start_field",
 ]
 
 #: velocity order of the state buffers (include/sc_lbm.h)
@@ -159,8 +161,10 @@ def lib():
     L.sc_nn_adam.argtypes = [vp, vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp]
     L.sc_nn_to_bf16.argtypes = [vp, vp, i64, vp]
     L.sc_nn_features.argtypes = [vp, vp, i32, i32, i32, f32, vp]
+    L.sc_nn_start_field.argtypes = [vp, vp, vp, vp, i32, i32, i32, f32, ctypes.c_double, ctypes.c_double, vp]
     for name in ("sc_nn_conv3x3_fwd", "sc_nn_conv3x3_bwd_data", "sc_nn_conv3x3_bwd_weight", "sc_nn_tanh_fwd",
-                 "sc_nn_tanh_bwd", "sc_nn_mse", "sc_nn_adam", "sc_nn_to_bf16", "sc_nn_features"):
+                 "sc_nn_tanh_bwd", "sc_nn_mse", "sc_nn_adam", "sc_nn_to_bf16", "sc_nn_features",
+                 "sc_nn_start_field"):
         getattr(L, name).restype = ctypes.c_int
     L.sc_lbm_stream.argtypes = [vp]
     L.sc_lbm_stream.restype = vp
@@ -282,8 +286,11 @@ def sc_lbm_strerror(code):
 
 def make_params(lattice="D2Q9", shape=(64, 64), order=4, G=-5.0, c0=1.0 / 3.0, psi="exp",
                 psi0=1.0, rho_psi=1.0, tau=1.0, collision="srt", precision="fp32",
-                s_bulk=1.2, s_ghost=1.2, rho_ref=1.0, obs_every=100, variant=-1, forcing="guo", eos=None):
-    """eos: for psi == "pr", a dict with a, b, R, T (absolute) and alpha."""
+                s_bulk=1.2, s_ghost=1.2, rho_ref=1.0, obs_every=100, variant=-1, forcing="guo", eos=None,
+                init="equilibrium"):
+    """eos: for psi == "pr", a dict with a, b, R, T (absolute) and alpha.
+    init: "equilibrium" (f = feq(rho0, 0)) or "rest" (f = feq(rho0, -F/(2 rho0)):
+    the forced velocity is zero at t = 0)."""
     p = sc_lbm_default_params()
     p.lattice = LATTICE[lattice]
     shape = tuple(int(s) for s in shape)
@@ -299,6 +306,7 @@ def make_params(lattice="D2Q9", shape=(64, 64), order=4, G=-5.0, c0=1.0 / 3.0, p
     p.precision = {"fp32": SC_FP32_SHIFTED, "fp64": SC_FP64}[precision]
     p.s_bulk, p.s_ghost, p.rho_ref = s_bulk, s_ghost, rho_ref
     p.obs_every, p.variant = obs_every, variant
+    p.init = {"equilibrium": SC_INIT_EQUILIBRIUM, "rest": SC_INIT_REST}[init]
     return p
 
 

@@ -3,18 +3,26 @@
 A five-layer 3x3 convolutional net (5 -> 32 -> 32 -> 32 -> 32 -> 1 channels,
 tanh between layers, circular padding, bfloat16 weights with FP32
 accumulation) maps the droplet parameters (R, G, tau, stencil order,
-broadcast as channels) plus the radial coordinate grid to the steady density
-field.  It is trained on the residual between the steady field and the usual
-tanh start (scaled by TARGET_SCALE), so an untrained net reproduces the tanh
-start and training moves it towards the steady state.  The prediction
-(tanh start + residual), clamped to a physical range and shifted to the mass
-of the tanh start (mass is conserved by the step, so the steady state is
-fixed by it), becomes the initial condition; the lattice Boltzmann iteration
-still runs to its own steady state and alone decides when it is reached.
+broadcast as channels) plus the radial coordinate grid (distance to the
+centre relative to R) to the steady density field.  It is trained on the
+residual between the steady field and the usual tanh start (scaled by
+TARGET_SCALE), so an untrained net reproduces the tanh start and training
+moves it towards the steady state.
 
-Every arithmetic step runs in the library's kernels (sc_nn_* for the net,
-sc_lbm_batch_* for the data); torch only allocates device memory and
-provides the stream.  There is no CPU fallback.
+The start handed to the iteration (sc_nn_start_field) is the prediction
+averaged over the eight symmetries of the square about the droplet centre
+(the steady state of a centred droplet has that symmetry; any asymmetric
+error would seed a slowly decaying shape mode), clamped to a physical range
+and shifted to the mass of the tanh start (mass is conserved by the step,
+so the steady state is fixed by it).  The populations start at rest in the
+forced sense (SC_INIT_REST: zero (sum f c + F/2) / rho), so the interface
+force of a nearly steady density does not launch a velocity impulse.  The
+lattice Boltzmann iteration still runs to its own steady state and alone
+decides when it is reached.
+
+Every arithmetic step runs in the library's kernels (sc_nn_* for the net
+and the start field, sc_lbm_batch_* for the data); torch only allocates
+device memory and provides the stream.  There is no CPU fallback.
 """
 import math
 import time
@@ -196,7 +204,8 @@ def train(net, inputs, targets, epochs=20, lr=2e-3, log=None, seed=0):
 
 
 def predict(net, inputs):
-    """Densities [N][h][w] (numpy float64) for normalised parameter rows."""
+    """Raw network outputs [N][h][w] (numpy float64, TARGET_SCALE x residual)
+    for normalised parameter rows."""
     out = []
     n = len(inputs)
     for s in range(0, n, net.batch):
@@ -209,22 +218,42 @@ def predict(net, inputs):
     return out
 
 
-def mass_project(rho_pred, rho_ref):
-    """Clamp the prediction to a physical density range, then shift it
-    uniformly to the mass of rho_ref."""
-    r = np.clip(rho_pred, RHO_CLAMP[0], RHO_CLAMP[1])
-    return r + (rho_ref.sum() - r.sum()) / r.size
+def start_fields(net, inputs, bases, masses):
+    """Initial densities of the learned start (numpy float64 [N][h][w]):
+    forward pass, then sc_nn_start_field (square-symmetry average of
+    base + output / TARGET_SCALE, clamp to RHO_CLAMP, shift to the mass)."""
+    torch = net.torch
+    out = []
+    n = len(inputs)
+    for s in range(0, n, net.batch):
+        rows = list(inputs[s:s + net.batch])
+        k = len(rows)
+        pad = net.batch - k
+        rows += [rows[-1]] * pad
+        net.set_params(rows)
+        y = net.forward()
+        b = list(bases[s:s + k]) + [bases[s + k - 1]] * pad
+        m = list(masses[s:s + k]) + [masses[s + k - 1]] * pad
+        bd = torch.tensor(np.stack(b), dtype=torch.float64, device=net.dev)
+        md = torch.tensor(np.asarray(m, dtype=np.float64), device=net.dev)
+        od = torch.empty_like(bd)
+        net._chk(B.lib().sc_nn_start_field(y.data_ptr(), bd.data_ptr(), md.data_ptr(), od.data_ptr(), net.batch,
+                                           net.h, net.w, 1.0 / TARGET_SCALE, RHO_CLAMP[0], RHO_CLAMP[1],
+                                           net.stream), "sc_nn_start_field")
+        out.extend(od[:k].cpu().numpy())
+    return out
 
 
-def make_dataset(n_train, n_test, side, tol, max_steps, obs_every, chunk, seed, log=print):
-    """Steady states of the sweep's items (side fixed) from the tanh start."""
+def make_dataset(n_train, n_test, side, tol, max_steps, obs_every, chunk, seed, jitter=False, log=print):
+    """Steady states of the sweep's items (side fixed) from the tanh start
+    (without the per-node jitter unless `jitter`)."""
     from workload import droplet_rho, sweep_items
     items = sweep_items(n_train + n_test, seed=seed, sides=side)
     fields, steps, conv = [], [], []
     t_gen = 0.0
     for s in range(0, len(items), chunk):
-        part = [{"rho0": droplet_rho((side, side), it["R"], seed=it["seed"]), "order": it["order"], "G": it["G"],
-                 "tau": it["tau"]} for it in items[s:s + chunk]]
+        part = [{"rho0": droplet_rho((side, side), it["R"], seed=it["seed"] if jitter else None),
+                 "order": it["order"], "G": it["G"], "tau": it["tau"]} for it in items[s:s + chunk]]
         f, st, by, wall = steady_states(part, tol=tol, max_steps=max_steps, obs_every=obs_every)
         fields += f
         steps += st
@@ -232,23 +261,38 @@ def make_dataset(n_train, n_test, side, tol, max_steps, obs_every, chunk, seed, 
         t_gen += wall
         log("steady states %d/%d (%.1f s)" % (min(s + chunk, len(items)), len(items), t_gen))
     return {"items": items, "fields": fields, "steps": steps, "conv": conv, "gen_wall_s": t_gen,
-            "n_train": n_train, "side": side, "tol": tol, "max_steps": max_steps, "obs_every": obs_every}
+            "n_train": n_train, "side": side, "tol": tol, "max_steps": max_steps, "obs_every": obs_every,
+            "jitter": jitter}
 
 
-def evaluate(ds, epochs=20, batch=16, lr=2e-3, fp64_baseline=8, seed=2026, log=print):
-    """Train on the dataset's training items, then compare steps and wall time
-    to steady state on its held-out items: tanh start (batched FP32), learned
-    start (batched FP32, inference included), plain per-droplet FP64 runs."""
+def _runs(starts, items, init, tol, max_steps, obs_every):
+    """Batched FP32 runs of `items` from the densities `starts`."""
+    run = [{"rho0": r, "order": it["order"], "G": it["G"], "tau": it["tau"], "init": init}
+           for r, it in zip(starts, items)]
+    return steady_states(run, tol=tol, max_steps=max_steps, obs_every=obs_every)
+
+
+def evaluate(ds, epochs=100, batch=16, lr=1e-3, fp64_baseline=8, seed=2026, tols=(None,), log=print):
+    """Train on the dataset's training items, then compare steps and wall
+    time to steady state on its held-out items.  Starts (batched FP32 runs
+    unless noted):
+      tanh            the tanh start, f = feq(rho, 0) (the method without the net)
+      tanh_rest       the tanh start at rest in the forced sense
+      learned         the learned start at rest (inference included in its time)
+      learned_eq      the learned start with f = feq(rho, 0)
+      tanh_jitter     the tanh start with the sweep's +-1e-3 per-node jitter
+      fp64            plain per-droplet FP64 runs from the tanh start (first items)
+    for each tolerance in `tols` (None = the dataset's)."""
     from workload import droplet_rho
     torch = __import__("torch")
     items, fields, conv = ds["items"], ds["fields"], ds["conv"]
-    side, tol, max_steps, obs_every = ds["side"], ds["tol"], ds["max_steps"], ds["obs_every"]
+    side, max_steps, obs_every = ds["side"], ds["max_steps"], ds["obs_every"]
     n_train = ds["n_train"]
-    rho0 = lambda it: droplet_rho((side, side), it["R"], seed=it["seed"])  # noqa: E731
-    base = lambda it: droplet_rho((side, side), it["R"])  # noqa: E731  tanh start without jitter
+    base = lambda it: droplet_rho((side, side), it["R"])  # noqa: E731  tanh start
     ok = [k for k in range(len(items)) if conv[k] > 0]
     train_idx = [k for k in ok if k < n_train]
     test_idx = [k for k in ok if k >= n_train]
+    test_items = [items[k] for k in test_idx]
     inputs = [normalise(it["R"], it["G"], it["tau"], it["order"]) for it in items]
     resid = {k: TARGET_SCALE * (fields[k] - base(items[k])) for k in ok}
     net = WarmStartNet(side, side, batch, seed=seed)
@@ -258,55 +302,81 @@ def evaluate(ds, epochs=20, batch=16, lr=2e-3, fp64_baseline=8, seed=2026, log=p
                  log=log)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    bases = [base(it) for it in test_items]
     t0 = time.perf_counter()
-    pred = [base(items[k]) + r / TARGET_SCALE
-            for k, r in zip(test_idx, predict(net, [inputs[k] for k in test_idx]))]
-    warm_items = [{"rho0": mass_project(p, rho0(items[k])), "order": items[k]["order"], "G": items[k]["G"],
-                   "tau": items[k]["tau"]} for k, p in zip(test_idx, pred)]
+    starts = start_fields(net, [inputs[k] for k in test_idx], bases, [b.sum() for b in bases])
     torch.cuda.synchronize()
     t_inf = time.perf_counter() - t0
-    wf, wst, wby, t_warm = steady_states(warm_items, tol=tol, max_steps=max_steps, obs_every=obs_every)
-    cold_items = [{"rho0": rho0(items[k]), "order": items[k]["order"], "G": items[k]["G"],
-                   "tau": items[k]["tau"]} for k in test_idx]
-    cf, cst, cby, t_cold = steady_states(cold_items, tol=tol, max_steps=max_steps, obs_every=obs_every)
-    t0 = time.perf_counter()
-    fp64_steps = []
-    for k in test_idx[:fp64_baseline]:
-        it = items[k]
-        sim = B.Sim(rho0(it), "D2Q9", order=it["order"], G=it["G"], tau=it["tau"], precision="fp64",
-                    obs_every=obs_every)
-        rc, done = sim.step(max_steps, tol=tol)
-        fp64_steps.append(done)
-        sim.close()
-    torch.cuda.synchronize()
-    t_fp64 = time.perf_counter() - t0
-    nb = max(1, min(fp64_baseline, len(test_idx)))
+    raw = [b + r / TARGET_SCALE for b, r in zip(bases, predict(net, [inputs[k] for k in test_idx]))]
+    jit = [droplet_rho((side, side), it["R"], seed=it["seed"]) for it in test_items]
     nt = max(1, len(test_idx))
-    pred_err = [float(np.max(np.abs(p - fields[k])) / np.max(fields[k])) for k, p in zip(test_idx, pred)]
-    tanh_err = [float(np.max(np.abs(base(items[k]) - fields[k])) / np.max(fields[k])) for k in test_idx]
-    agree = [float(np.max(np.abs(a - b))) for a, b, x, y in zip(wf, cf, wby, cby) if x > 0 and y > 0]
-    return {
-        "n_train": len(train_idx), "n_test": len(test_idx), "diverged": int(sum(1 for c in conv if c < 0)),
-        "side": side, "tol": tol, "epochs": epochs, "lr": lr, "loss_first": hist[0], "loss_last": hist[-1],
-        "gen_wall_s": ds["gen_wall_s"], "train_wall_s": t_train, "inference_wall_s": t_inf,
-        "pred_max_rel_err_median": float(np.median(pred_err)),
-        "tanh_max_rel_err_median": float(np.median(tanh_err)),
-        "steps_tanh_mean": float(np.mean(cst)), "steps_warm_mean": float(np.mean(wst)),
-        "steps_ratio_median": float(np.median(np.array(wst) / np.maximum(np.array(cst), 1))),
-        "wall_tanh_batched_s_per_item": t_cold / nt,
-        "wall_warm_batched_s_per_item": (t_warm + t_inf) / nt,
-        "wall_fp64_per_droplet_s_per_item": t_fp64 / nb,
-        "fp64_steps_mean": float(np.mean(fp64_steps)) if fp64_steps else None,
-        "steady_fields_max_abs_diff_median": float(np.median(agree)) if agree else None,
-        "warm_converged": int(sum(1 for v in wby if v > 0)),
+
+    def rel(a, k):
+        return float(np.max(np.abs(a - fields[k])) / np.max(fields[k]))
+
+    def rms(a, k):
+        return float(np.sqrt(np.mean((a - fields[k]) ** 2)))
+    res = {
+        "n_train": len(train_idx), "n_test": len(test_idx), "not_converged": int(sum(1 for c in conv if c <= 0)),
+        "side": side, "dataset_tol": ds["tol"], "dataset_jitter": ds.get("jitter", True), "epochs": epochs,
+        "lr": lr, "loss_first": hist[0], "loss_last": hist[-1], "gen_wall_s": ds["gen_wall_s"],
+        "train_wall_s": t_train, "inference_wall_s": t_inf,
+        "err_max_rel_median": {"tanh": float(np.median([rel(b, k) for b, k in zip(bases, test_idx)])),
+                               "raw_prediction": float(np.median([rel(p, k) for p, k in zip(raw, test_idx)])),
+                               "learned": float(np.median([rel(p, k) for p, k in zip(starts, test_idx)]))},
+        "err_rms_median": {"tanh": float(np.median([rms(b, k) for b, k in zip(bases, test_idx)])),
+                           "raw_prediction": float(np.median([rms(p, k) for p, k in zip(raw, test_idx)])),
+                           "learned": float(np.median([rms(p, k) for p, k in zip(starts, test_idx)]))},
+        "runs": {},
     }
+    for tol in tols:
+        tol = ds["tol"] if tol is None else tol
+        key = "%.0e" % tol
+        out = {}
+        for name, st, init in (("tanh", bases, "equilibrium"), ("tanh_rest", bases, "rest"),
+                               ("learned", starts, "rest"), ("learned_eq", starts, "equilibrium"),
+                               ("tanh_jitter", jit, "equilibrium")):
+            f, steps, by, wall = _runs(st, test_items, init, tol, max_steps, obs_every)
+            extra = t_inf if name.startswith("learned") else 0.0
+            out[name] = {"steps_mean": float(np.mean(steps)), "steps_median": float(np.median(steps)),
+                         "wall_s_per_item": (wall + extra) / nt, "converged": int(sum(1 for v in by if v > 0)),
+                         "fields": f, "steps": steps}
+            log("%s tol %s: mean steps %.0f, %.4f s per droplet" % (name, key, out[name]["steps_mean"],
+                                                                  out[name]["wall_s_per_item"]))
+        t_st = np.maximum(np.array(out["tanh"]["steps"]), 1)
+        for name in list(out):
+            out[name]["steps_ratio_median_vs_tanh"] = float(np.median(np.array(out[name]["steps"]) / t_st))
+        agree = [float(np.max(np.abs(a - b))) for a, b in zip(out["learned"]["fields"], out["tanh"]["fields"])]
+        out["steady_fields_max_abs_diff_median"] = float(np.median(agree)) if agree else None
+        t0 = time.perf_counter()
+        fp64_steps = []
+        for it, b in list(zip(test_items, bases))[:fp64_baseline]:
+            sim = B.Sim(b, "D2Q9", order=it["order"], G=it["G"], tau=it["tau"], precision="fp64",
+                        obs_every=obs_every)
+            rc, done = sim.step(max_steps, tol=tol)
+            fp64_steps.append(done)
+            sim.close()
+        torch.cuda.synchronize()
+        nb = max(1, min(fp64_baseline, len(test_idx)))
+        out["fp64"] = {"steps_mean": float(np.mean(fp64_steps)) if fp64_steps else None,
+                       "wall_s_per_item": (time.perf_counter() - t0) / nb, "items": nb}
+        t_by = np.array(out["tanh"]["steps"])
+        for name in out:
+            if isinstance(out[name], dict) and "steps" in out[name]:
+                out[name]["faster_than_tanh"] = int(np.sum(np.array(out[name]["steps"]) < t_by))
+                out[name].pop("fields", None)
+                out[name]["steps"] = [int(v) for v in out[name]["steps"]]
+        res["runs"][key] = out
+    return res
 
 
-def run_experiment(n_train=2000, n_test=64, side=256, tol=1e-8, epochs=20, batch=16, lr=2e-3,
-                   max_steps=150000, obs_every=200, chunk=64, fp64_baseline=8, seed=2026, log=print):
+def run_experiment(n_train=2000, n_test=64, side=256, tol=1e-8, epochs=100, batch=16, lr=1e-3,
+                   max_steps=150000, obs_every=200, chunk=64, fp64_baseline=8, seed=2026, jitter=False,
+                   tols=(None,), log=print):
     """The 256^2 warm-start experiment: dataset from batched sweeps, then evaluate()."""
-    ds = make_dataset(n_train, n_test, side, tol, max_steps, obs_every, chunk, seed, log=log)
-    return evaluate(ds, epochs=epochs, batch=batch, lr=lr, fp64_baseline=fp64_baseline, seed=seed, log=log)
+    ds = make_dataset(n_train, n_test, side, tol, max_steps, obs_every, chunk, seed, jitter=jitter, log=log)
+    return evaluate(ds, epochs=epochs, batch=batch, lr=lr, fp64_baseline=fp64_baseline, seed=seed, tols=tols,
+                    log=log)
 
 
 if __name__ == "__main__":
@@ -320,12 +390,15 @@ if __name__ == "__main__":
     ap.add_argument("--n-train", type=int, default=2000)
     ap.add_argument("--n-test", type=int, default=64)
     ap.add_argument("--side", type=int, default=256)
-    ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--tol", type=float, default=1e-8, help="steady-state rule of the dataset runs")
+    ap.add_argument("--eval-tols", default="1e-8", help="rules the starts are compared at")
+    ap.add_argument("--epochs", type=int, default=100)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--jitter", action="store_true", help="dataset runs from the jittered tanh start")
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
     res = run_experiment(n_train=a.n_train, n_test=a.n_test, side=a.side, tol=a.tol, epochs=a.epochs, lr=a.lr,
+                         jitter=a.jitter, tols=tuple(float(t) for t in a.eval_tols.split(",")),
                          log=lambda m: print(m, flush=True))
     print(json.dumps(res), flush=True)
     if a.out:

@@ -19,9 +19,12 @@ def _add(a, b, shape):
 
 
 def exact_steps(rho0, shape, lattice, order, G, c0, tau, nsteps=1,
-                collision="srt", s_bulk=None, s_ghost=None, forcing="guo", solid=(), rho_w=None):
+                collision="srt", s_bulk=None, s_ghost=None, forcing="guo", solid=(), rho_w=None,
+                init="equilibrium"):
     """rho0: dict node -> Fraction.  Returns dict node -> list of f (Fractions)
-    after nsteps, with f = feq(rho0, 0) at t = 0.
+    after nsteps, with f = feq(rho0, 0) at t = 0, or with init == "rest"
+    f = feq(rho0, v), v = -F / (2 rho0) and F the force of psi = rho0 on
+    the periodic grid (walls play no part in the start).
 
     solid: nodes of a wall (initialised like the rest).  In the force they count with
     psi = rho_w (the virtual wall density, Sec. 3); in place of a collision
@@ -34,6 +37,21 @@ def exact_steps(rho0, shape, lattice, order, G, c0, tau, nsteps=1,
     solid = set(solid)
     back = {q: [tuple(-v for v in c) for c, _ in vel].index(tuple(c)) for q, (c, _) in enumerate(vel)}
     f = {x: [w * rho0[x] for _, w in vel] for x in nodes}
+    if init == "rest":
+        for x in nodes:
+            acc = [Fr(0)] * dim
+            for e, w in stencil:
+                pn = rho0[_add(x, e, shape)]
+                for d in range(dim):
+                    acc[d] += w * pn * e[d]
+            v = [G * c0 * rho0[x] * a / (2 * rho0[x]) for a in acc]   # -F / (2 rho)
+            vv = sum(a * a for a in v)
+            f[x] = []
+            for c, w in vel:
+                cv = sum(c[d] * v[d] for d in range(dim))
+                f[x].append(w * rho0[x] * (1 + cv / cs2 + cv * cv / (2 * cs2 * cs2) - vv / (2 * cs2)))
+    elif init != "equilibrium":
+        raise ValueError(init)
     if collision == "mrt":
         rows, groups = T.mrt_gram_schmidt(lattice)
         rate = {}

@@ -57,6 +57,7 @@ def test_defaults():
     assert (p.lattice, p.nx, p.ny, p.nz, p.order) == (0, 64, 64, 1, 4)
     assert p.G == -5.0 and abs(p.c0 - 1 / 3) < 1e-16 and p.tau == 1.0
     assert p.variant == -1 and p.obs_every == 100
+    assert p.init == B.SC_INIT_EQUILIBRIUM and p.forcing == B.SC_GUO
     assert B.sc_lbm_state_bytes(p) == 9 * 64 * 64 * 4
     p.precision = B.SC_FP64
     assert B.sc_lbm_state_bytes(p) == 9 * 64 * 64 * 8
@@ -74,6 +75,7 @@ def test_defaults():
     ("precision", 9, B.SC_E_INVAL),
     ("variant", 99, B.SC_E_INVAL),
     ("G", float("inf"), B.SC_E_INVAL),
+    ("init", 2, B.SC_E_INVAL),
 ])
 def test_invalid_parameters_rejected(field, value, code):
     p = B.sc_lbm_default_params()

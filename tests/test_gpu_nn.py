@@ -98,7 +98,8 @@ def test_pointwise_kernels():
     t = rng.normal(size=n).astype(np.float32)
     part = torch.empty(16, dtype=torch.float64, device="cuda")
     grad = torch.empty(n, device="cuda")
-    assert B.lib().sc_nn_mse(_dev(x).data_ptr(), _dev(t).data_ptr(), grad.data_ptr(), part.data_ptr(), 16, n,
+    xd2, td = _dev(x), _dev(t)   # referenced until the kernel has run
+    assert B.lib().sc_nn_mse(xd2.data_ptr(), td.data_ptr(), grad.data_ptr(), part.data_ptr(), 16, n,
                              _stream()) == 0
     loss, gref = C.mse(x.astype(np.float64), t.astype(np.float64))
     assert abs(part.cpu().numpy().sum() / n - loss) < 1e-6 * loss
@@ -110,7 +111,8 @@ def test_pointwise_kernels():
     p, m, v = p0.astype(np.float64), np.zeros(n), np.zeros(n)
     for t_ in (1, 2):
         gg = rng.normal(size=n).astype(np.float32)
-        assert B.lib().sc_nn_adam(pd.data_ptr(), _dev(gg).data_ptr(), md.data_ptr(), vd.data_ptr(), bits.data_ptr(),
+        ggd = _dev(gg)
+        assert B.lib().sc_nn_adam(pd.data_ptr(), ggd.data_ptr(), md.data_ptr(), vd.data_ptr(), bits.data_ptr(),
                                   n, 1e-2, 0.9, 0.999, 1e-8, t_, _stream()) == 0
         m = 0.9 * m + 0.1 * gg
         v = 0.999 * v + 0.001 * gg.astype(np.float64) ** 2
@@ -123,13 +125,41 @@ def test_features():
     prm = np.array([[0.3, -0.2, 0.5, 1.0], [0.1, 0.0, -1.0, -1.0]], dtype=np.float32)
     h, w = 13, 10
     out = torch.empty((2, 5, h, w), device="cuda")
-    assert B.lib().sc_nn_features(_dev(prm).data_ptr(), out.data_ptr(), 2, h, w, 100.0, _stream()) == 0
+    prmd = _dev(prm)
+    assert B.lib().sc_nn_features(prmd.data_ptr(), out.data_ptr(), 2, h, w, 10.0, _stream()) == 0
     o = out.cpu().numpy()
-    yy, xx = np.meshgrid(np.arange(h), np.arange(w), indexing="ij")
-    r = np.sqrt((xx - w // 2) ** 2 + (yy - h // 2) ** 2) / 100.0
-    assert np.allclose(o[:, 0], r[None], atol=1e-7)
+    ref = C.features(prm.astype(np.float64), h, w, 10.0)
+    assert np.max(np.abs(o[:, 0] - ref[:, 0])) < 1e-6
     for c in range(4):
         assert np.all(o[:, c + 1] == prm[:, c][:, None, None])
+
+
+@pytest.mark.parametrize("n", [20, 21])
+def test_start_field(n):
+    """sc_nn_start_field against the oracle's definition: the average of
+    the eight square symmetries of base + resid / scale, clamped, shifted to
+    the target mass (FP64 sums on both sides; resid is float32)."""
+    rng = np.random.default_rng(n)
+    bsz = 3
+    resid = rng.normal(scale=3.0, size=(bsz, n, n)).astype(np.float32)
+    base = rng.uniform(0.1, 2.0, size=(bsz, n, n))
+    mass = base.reshape(bsz, -1).sum(axis=1) + rng.normal(size=bsz)
+    out = torch.empty((bsz, n, n), dtype=torch.float64, device="cuda")
+    # the inputs stay referenced until the kernel has run: a temporary freed
+    # after data_ptr() could be handed to the next allocation on the stream
+    rd, bd, md = _dev(resid), _dev(base, torch.float64), _dev(mass, torch.float64)
+    rc = B.lib().sc_nn_start_field(rd.data_ptr(), bd.data_ptr(), md.data_ptr(), out.data_ptr(), bsz, n, n, 0.1,
+                                   0.05, 2.5, _stream())
+    assert rc == 0
+    got = out.cpu().numpy()
+    for b in range(bsz):
+        ref = C.start_field(resid[b].astype(np.float64), base[b], mass[b], 10.0, 0.05, 2.5)
+        err = np.max(np.abs(got[b] - ref))
+        say("start field n=%d item %d: max err %.2e" % (n, b, err))
+        assert err < 1e-7
+        assert abs(got[b].sum() - mass[b]) < 1e-10 * abs(mass[b])
+    assert B.lib().sc_nn_start_field(rd.data_ptr(), bd.data_ptr(), md.data_ptr(), out.data_ptr(), bsz, n, n + 1,
+                                     0.1, 0.05, 2.5, _stream()) == B.SC_E_INVAL
 
 
 def test_network_gradients_against_oracle():
@@ -175,19 +205,21 @@ def test_training_reduces_loss():
 
 
 def test_warm_start_gain_small():
-    """Scaled-down warm-start experiment on 64^2 droplets.  What the trained net gains
-    over the tanh start: an initial density field several times closer to the
-    steady state; both starts reach the same steady field.  Steps to the
-    max|u| criterion are reported, not asserted: that criterion is governed by
-    re-growing the spurious velocity field from rest, which no density-only
-    start shortens by much (starting from the exact steady density saves
-    10-30% of the steps in the oracle)."""
+    """Scaled-down warm-start experiment on 64^2 droplets.  What the trained
+    net gains over the tanh start: an initial density field several times
+    closer to the steady state and, started at rest in the forced sense,
+    fewer steps to the steady-state rule; both starts reach the same steady
+    field."""
     res = WS.run_experiment(n_train=128, n_test=12, side=64, tol=1e-8, epochs=400, batch=16, lr=1e-3,
-                            max_steps=80000, obs_every=100, chunk=64, fp64_baseline=2, seed=77,
+                            max_steps=80000, obs_every=100, chunk=64, fp64_baseline=2, seed=77, tols=(None,),
                             log=lambda m: None)
+    runs = res.pop("runs")["1e-08"]
     say("warm start:", res)
+    for name, r in runs.items():
+        say("  ", name, r)
     assert res["n_test"] >= 8
-    assert res["warm_converged"] >= res["n_test"] - 1
+    assert runs["learned"]["converged"] >= res["n_test"] - 1
     assert res["loss_last"] < 0.05 * res["loss_first"]
-    assert res["pred_max_rel_err_median"] < 0.5 * res["tanh_max_rel_err_median"]
-    assert res["steady_fields_max_abs_diff_median"] < 0.05
+    assert res["err_rms_median"]["learned"] < 0.5 * res["err_rms_median"]["tanh"]
+    assert runs["learned"]["steps_mean"] < 0.9 * runs["tanh"]["steps_mean"]
+    assert runs["steady_fields_max_abs_diff_median"] < 0.05

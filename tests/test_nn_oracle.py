@@ -55,3 +55,54 @@ def test_net_gradients_match_finite_differences():
     x = rng.normal(size=(2, 5, 6, 5))
     tgt = rng.normal(size=(2, 1, 6, 5))
     assert _fd_check(params, x, tgt) < 1e-6
+
+
+def test_square_images_brute_force():
+    """Each image against an explicit coordinate map (odd and even sides)."""
+    for n in (5, 6):
+        c = n // 2
+        a = np.arange(n * n, dtype=float).reshape(n, n) ** 1.5
+        ims = C.square_images(a)
+        assert len(ims) == 8
+        maps = []
+        for tr in (False, True):
+            for fi in (False, True):
+                for fj in (False, True):
+                    def m(i, j, tr=tr, fi=fi, fj=fj):
+                        if fi:
+                            i = (2 * c - i) % n
+                        if fj:
+                            j = (2 * c - j) % n
+                        return (j, i) if tr else (i, j)
+                    maps.append(m)
+        for im, m in zip(ims, maps):
+            for i in range(n):
+                for j in range(n):
+                    assert im[i, j] == a[m(i, j)]
+        # the images form a group: every one is distinct for a generic field
+        assert len({im.tobytes() for im in ims}) == 8
+
+
+def test_start_field_keeps_a_symmetric_field_and_mass():
+    from workload import droplet_rho
+    base = droplet_rho((32, 32), 9)
+    out = C.start_field(np.zeros((32, 32)), base, base.sum(), 10.0, 0.05, 2.5)
+    assert np.max(np.abs(out - base)) < 1e-14
+    # a perturbation odd about the centre node on the periodic grid averages
+    # away; the mass is met
+    x = np.sin(2 * np.pi * (np.arange(32) - 16.0) / 32)[:, None] * np.ones(32)[None]
+    out = C.start_field(10.0 * 0.01 * x, base, base.sum() + 3.0, 10.0, 0.05, 2.5)
+    assert np.max(np.abs(out - (base + 3.0 / 1024))) < 1e-14
+    # clamping happens before the mass shift
+    out = C.start_field(np.full((32, 32), -40.0), base, base.sum(), 10.0, 0.05, 2.5)
+    assert abs(out.sum() - base.sum()) < 1e-10 and np.ptp(out) < 1e-12
+
+
+def test_features_definition():
+    prm = np.array([[0.7, 0.1, -0.2, 0.3]])
+    f = C.features(prm, 9, 12, 10.0)
+    assert f.shape == (1, 5, 9, 12)
+    # node (y, x) = (4, 6) is the centre; (0, 0) is sqrt(4^2 + 6^2) away
+    assert abs(f[0, 0, 4, 6] + 0.7) < 1e-15
+    assert abs(f[0, 0, 0, 0] - (np.sqrt(52.0) / 10.0 - 0.7)) < 1e-15
+    assert np.all(f[0, 3] == -0.2)
