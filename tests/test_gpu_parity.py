@@ -199,18 +199,30 @@ def test_d3q19_droplet(order, collision):
         sim.close()
 
 
-def test_d3q19_variants_bitwise():
+@pytest.mark.parametrize("order,collision,prec", [(8, "mrt", "fp32"), (4, "srt", "fp64"), (6, "mrt", "fp64")])
+def test_d3q19_variants_agree(order, collision, prec):
+    """Every launch shape (register window, prefetch, re-pull) against the
+    oracle, and against shape 0 to rounding: the shapes do the same
+    arithmetic on the same values, but the compiler may fuse multiply-adds
+    differently per shape.  The z range (35) is not a multiple of the
+    segment lengths, so the last segment of each shape overhangs the grid."""
     rho0 = droplet_rho((40, 21, 35), 8, seed=4)
+    kw = dict(order=order, collision=collision, tau=0.9)
+    orc = O.Oracle(rho0, "D3Q19", **kw).step(6)
     ref = None
     for v in range(B.sc_lbm_num_variants(B.make_params("D3Q19", (8, 8, 8)))):
-        sim = Sim(rho0, "D3Q19", order=8, collision="mrt", variant=v)
+        say("d3q19 variant", v, order, collision, prec)
+        sim = Sim(rho0, "D3Q19", precision=prec, variant=v, **kw)
         sim.step(6)
-        st = sim.state()
+        st = sim.state().astype(np.float64)
+        _compare(sim, orc, prec, "D3Q19 E%d %s %s variant %s" % (order, collision, prec, sim.variant))
         sim.close()
         if ref is None:
             ref = st
         else:
-            assert np.array_equal(st, ref), v
+            d = float(np.max(np.abs(st - ref)))
+            say("  max |state - state of shape 0| = %.3e" % d)
+            assert d <= (2e-6 if prec == "fp32" else 1e-14) * float(np.max(np.abs(ref))), (v, d)
 
 
 def test_d3q19_mrt_equals_srt_when_rates_equal():
