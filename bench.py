@@ -70,6 +70,10 @@ Q_OF = {"D2Q9": 9, "D3Q19": 19, "D2Q13": 13, "D2Q25": 25}
 # summary under profiles/).  Keyed by workload and launch shape; a shape
 # without an entry reports traffic null.  Re-measure after a kernel change.
 TRAFFIC_RATIO = {
+    ("d2q13_e6_pr_edm_8192", "wide128x16r2"): (1.407, 1.000),
+    ("d2q13_e6_pr_edm_8192", "wide256x8r2"): (1.380, 1.000),
+    ("d2q25_e8_pr_edm_8192", "wide128x16r2"): (1.450, 1.000),
+    ("d2q25_e8_pr_edm_8192", "wide256x8r2"): (1.375, 1.000),
     ("d2q13_e6_pr_edm_8192", "wide64x16r2"): (1.823, 1.000),
     ("d2q13_e6_pr_edm_8192", "wide64x16r4"): (1.867, 1.000),
     ("d2q25_e8_pr_edm_8192", "wide64x16r2"): (1.798, 1.000),

@@ -103,7 +103,8 @@ static int family_variants(Family f)
 }
 
 namespace sclbm {
-static const char* const kShapesWide[] = {"wide64x8r2", "wide32x8r1", "wide64x16r4", "wide64x16r2"};
+static const char* const kShapesWide[] = {"wide64x8r2", "wide32x8r1", "wide64x16r4", "wide64x16r2", "wide128x16r2",
+                                          "wide256x8r2"};
 int num_variants_wide() { return (int)(sizeof(kShapesWide) / sizeof(kShapesWide[0])); }
 const char* variant_name_wide(int v) { return (v >= 0 && v < num_variants_wide()) ? kShapesWide[v] : "?"; }
 
@@ -351,7 +352,7 @@ static int auto_variant(const sc_lbm_params& p, int64_t n)
     switch (family_of(p)) {
     case kFamD2Q9: return n < (int64_t)1 << 20 ? 2 : 0;   // tile32x8r1 / tile64x16r4
     case kFamD3Q19: return 7;                              // march64x8r1h16pf1
-    default: return n < (int64_t)1 << 20 ? 1 : 0;          // wide32x8r1 / wide64x8r2
+    default: return n < (int64_t)1 << 20 ? 1 : 4;          // wide32x8r1 / wide128x16r2
     }
 }
 

@@ -285,6 +285,9 @@ static hipError_t launch_wide_shape(const StepArgs<T>& a, int variant, hipStream
     case 1: return launch_wide_tile<T, L, ORDER, EDM, WALLS, 32, 8, 1>(a, s);
     case 2: return launch_wide_tile<T, L, ORDER, EDM, WALLS, 64, 16, 4>(a, s);
     case 3: return launch_wide_tile<T, L, ORDER, EDM, WALLS, 64, 16, 2>(a, s);
+    // wide rows use more of each cache line the pulls touch (reach M in x)
+    case 4: return launch_wide_tile<T, L, ORDER, EDM, WALLS, 128, 16, 2>(a, s);
+    case 5: return launch_wide_tile<T, L, ORDER, EDM, WALLS, 256, 8, 2>(a, s);
     default: return hipErrorInvalidValue;
     }
 }
