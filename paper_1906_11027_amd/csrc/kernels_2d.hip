@@ -235,9 +235,9 @@ k_d2q9_march(StepArgs<T> a, int H, int nbx)
 // grids, where the launch itself costs as much as a step.  A block owns a
 // TX x TY tile and computes, with R the force-stencil radius:
 //   phase 1  psi at t+1 on the tile + (2R+1) halo: pull the 9 values of each
-//            node from the state (L2 / MALL), sum, psi -> LDS psi1;
-//   phase 2  step t -> t+1 on the tile + (R+1) halo: pull again (now cache
-//            hits), force from psi1, collide -> LDS s1 (post-collision);
+//            node from the state (kept in registers), sum, psi -> LDS psi1;
+//   phase 2  step t -> t+1 on the tile + (R+1) halo, a sub-region of the
+//            first: force from psi1, collide the registers -> LDS s1;
 //   phase 3  psi at t+2 on the tile + R halo, pulling from s1 -> LDS psi2;
 //   phase 4  step t+1 -> t+2 on the tile: pull from s1, force from psi2,
 //            collide, store.
@@ -295,10 +295,11 @@ k_d2q9_tile2(StepArgs<T> a, int nbx, int nby, int sw)
 
     // phase 1: psi at t+1 on the tile + (2R+1) halo.  The per-thread node
     // loop has a compile-time bound and is unrolled, so the pulls of all its
-    // nodes are in flight together.
+    // nodes are in flight together.  The pulled values stay in registers for
+    // phase 2, whose (R+1)-halo region lies inside this one.
     constexpr int K1 = (P1N + NT - 1) / NT;
+    T g[K1][9];
     {
-        T g[K1][9];
 #pragma unroll
         for (int q = 0; q < K1; ++q) {
             const int i = tid + q * NT;
@@ -314,28 +315,21 @@ k_d2q9_tile2(StepArgs<T> a, int nbx, int nby, int sw)
         }
     }
     __syncthreads();
-    // phase 2: step t -> t+1 on the tile + (R+1) halo (pulls again: cache hits)
-    constexpr int K2 = (C1N + NT - 1) / NT;
-    {
-        T g[K2][9];
+    // phase 2: step t -> t+1 on the tile + (R+1) halo, from the phase-1
+    // registers of the nodes in that region (offset R inside the psi1 region)
 #pragma unroll
-        for (int q = 0; q < K2; ++q) {
-            const int i = tid + q * NT;
-            if (i < C1N) {
-                const int ly = i / C1W, lx = i - ly * C1W;
-                pull_global(x0 - HC + lx, y0 - HC + ly, g[q]);
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < K2; ++q) {
-            const int i = tid + q * NT;
-            if (i < C1N) {
-                const int ly = i / C1W, lx = i - ly * C1W;
+    for (int q = 0; q < K1; ++q) {
+        const int i = tid + q * NT;
+        if (i < P1N) {
+            const int ly = i / P1W, lx = i - ly * P1W;
+            const int cx = lx - R, cy = ly - R;
+            if (cx >= 0 && cx < C1W && cy >= 0 && cy < C1H) {
                 T Fx, Fy;
-                force_at(psi1 + (ly + R) * P1W + lx + R, P1W, Fx, Fy);
+                force_at(psi1 + ly * P1W + lx, P1W, Fx, Fy);
                 collide_d2q9_srt(g[q], sum9(g[q]), Fx, Fy, a);
+                const int ci = cy * C1W + cx;
 #pragma unroll
-                for (int b = 0; b < 9; ++b) s1[b * C1N + i] = g[q][b];
+                for (int b = 0; b < 9; ++b) s1[b * C1N + ci] = g[q][b];
             }
         }
     }
