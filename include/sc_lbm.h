@@ -220,8 +220,10 @@ void* sc_lbm_state_ptr(sc_lbm* h);
 void* sc_lbm_stream(sc_lbm* h);
 
 /* Time every launch shape of the fused step on *p's lattice, order,
- * precision, collision and grid for `steps` steps (state rho = 1), and
- * remember the fastest: later sc_lbm_create calls with variant = -1 and the
+ * precision, collision, forcing and grid (state rho = 1) the way
+ * sc_lbm_step runs it: one warm-up graph of 32 steps, then the best of three
+ * runs of `steps` steps rounded up to whole graphs (at least one).  The
+ * fastest is remembered: later sc_lbm_create calls with variant = -1 and the
  * same problem shape use it.  With SC_LBM_TUNE_CACHE set to a file path the
  * choices persist across processes.  Outputs are nullable. */
 int sc_lbm_autotune(const sc_lbm_params* p, int32_t steps, int32_t* best_variant, double* best_ms_per_step);
