@@ -70,14 +70,14 @@ Q_OF = {"D2Q9": 9, "D3Q19": 19, "D2Q13": 13, "D2Q25": 25}
 # summary under profiles/).  Keyed by workload and launch shape; a shape
 # without an entry reports traffic null.  Re-measure after a kernel change.
 TRAFFIC_RATIO = {
-    ("d2q13_e6_pr_edm_8192", "wide128x16r2"): (1.407, 1.000),
-    ("d2q13_e6_pr_edm_8192", "wide256x8r2"): (1.380, 1.000),
-    ("d2q25_e8_pr_edm_8192", "wide128x16r2"): (1.450, 1.000),
-    ("d2q25_e8_pr_edm_8192", "wide256x8r2"): (1.375, 1.000),
-    ("d2q13_e6_pr_edm_8192", "wide64x16r2"): (1.823, 1.000),
+    ("d2q13_e6_pr_edm_8192", "wide128x16r2"): (1.394, 1.000),
+    ("d2q13_e6_pr_edm_8192", "wide256x8r2"): (1.387, 1.000),
+    ("d2q25_e8_pr_edm_8192", "wide128x16r2"): (1.443, 1.000),
+    ("d2q25_e8_pr_edm_8192", "wide256x8r2"): (1.404, 1.000),
+    ("d2q13_e6_pr_edm_8192", "wide64x16r2"): (1.824, 1.000),
     ("d2q13_e6_pr_edm_8192", "wide64x16r4"): (1.867, 1.000),
-    ("d2q25_e8_pr_edm_8192", "wide64x16r2"): (1.798, 1.000),
-    ("d2q25_e8_pr_edm_8192", "wide64x16r4"): (2.094, 1.000),
+    ("d2q25_e8_pr_edm_8192", "wide64x16r2"): (1.792, 1.000),
+    ("d2q25_e8_pr_edm_8192", "wide64x16r4"): (2.093, 1.000),
     ("d2q9_e8_256", "tile2x16x16"): (0.909, 0.500),
     ("d2q9_e8_256", "tile2x32x16"): (0.692, 0.500),
     ("d2q9_e8_256", "tile2x32x32"): (0.689, 0.500),
@@ -86,15 +86,15 @@ TRAFFIC_RATIO = {
     ("d2q9_e8_256", "tile2x64x8"): (0.697, 0.500),
     ("d2q9_e8_256", "tile32x8r1"): (1.161, 1.000),
     ("d2q9_e8_256", "tile64x4r1"): (1.166, 1.000),
-    ("d2q9_e8_8192", "tile2x16x16"): (1.355, 0.529),
-    ("d2q9_e8_8192", "tile2x32x16"): (0.638, 0.500),
-    ("d2q9_e8_8192", "tile2x32x32"): (0.636, 0.500),
-    ("d2q9_e8_8192", "tile2x32x8"): (0.629, 0.500),
+    ("d2q9_e8_8192", "tile2x16x16"): (1.359, 0.529),
+    ("d2q9_e8_8192", "tile2x32x16"): (0.642, 0.500),
+    ("d2q9_e8_8192", "tile2x32x32"): (0.635, 0.500),
+    ("d2q9_e8_8192", "tile2x32x8"): (0.628, 0.500),
     ("d2q9_e8_8192", "tile2x64x16"): (0.563, 0.500),
     ("d2q9_e8_8192", "tile2x64x8"): (0.563, 0.500),
-    ("d2q9_e8_8192", "tile64x16r4"): (1.526, 1.000),
+    ("d2q9_e8_8192", "tile64x16r4"): (1.525, 1.000),
     ("d3q19_mrt_e8_320", "march64x8r1h32pf1"): (1.335, 1.000),
-    ("d3q19_mrt_e8_320", "march64x8r1h64pf1"): (1.244, 1.000),
+    ("d3q19_mrt_e8_320", "march64x8r1h64pf1"): (1.245, 1.000),
 }
 
 
