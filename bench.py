@@ -232,7 +232,7 @@ def steady_droplet():
     ob = sim.observe(fields=False)["obs"]
     sim.close()
     return {"workload": "D2Q9 SRT 64x64 E4 droplet R=16, FP32, to max|u| change < 1e-10 "
-                        "(or the FP32 round-off floor for 10 checks)",
+                        "(FP32: on 3 consecutive checks, or max|u| of 100 checks within the state's resolution)",
             "steps": done, "wall_s": wall, "max_u": ob["max_u"], "dp": ob["dp"], "rc": rc}
 
 

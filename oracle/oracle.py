@@ -242,8 +242,10 @@ def _observables(fl, cs2, G, c0, solid=None):
     rho, psi, u = fl["rho"], fl["psi"], fl["u"]
     dim = rho.ndim
     umag = np.sqrt((u ** 2).sum(axis=0))
+    rho_fluid = rho
     if solid is not None:
         umag = umag[~solid]
+        rho_fluid = rho[~solid]
     p = cs2 * rho + 0.5 * G * c0 * psi ** 2
     centre = tuple(s // 2 for s in rho.shape)
     corner = (0,) * dim
@@ -261,4 +263,5 @@ def _observables(fl, cs2, G, c0, solid=None):
         "rho_in": rin, "rho_out": rout,
         "p_in": p[centre], "p_out": p[corner], "dp": p[centre] - p[corner],
         "radius": radius,
+        "rho_min": rho_fluid.min(), "rho_max": rho_fluid.max(),
     }

@@ -337,7 +337,7 @@ hipError_t launch_init_rest(int lattice, void* f, int precision, const double* r
                             int ny, int nz, double rho_ref, hipStream_t s);
 
 // Observables: macroscopic fields of the current state and FP64 reductions.
-constexpr int kObsSlots = 9;   // reduction slots per block (observe.hip)
+constexpr int kObsSlots = 11;  // reduction slots per block (observe.hip)
 struct ObsBuffers {
     double* rho;      // [N]
     void* psi;        // [N] in the state precision

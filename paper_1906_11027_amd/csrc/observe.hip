@@ -212,10 +212,14 @@ __global__ void k_psi_convert(const double* __restrict__ src, T* __restrict__ ds
 // ------------------------------------------------------------- reduce ----
 // partial[blk] = {sum rho, sum rho u_x, sum rho u_y, sum rho u_z,
 //                 max |u|, sum |u|, sum |u|^2, count of non-finite nodes,
-//                 count of finite fluid nodes}
-// Wall nodes add their rho (populations in transit) to the mass only.
+//                 count of finite fluid nodes, max rho, max -rho}
+// (the maxima over finite fluid nodes).  Wall nodes add their rho
+// (populations in transit) to the mass only.
 constexpr int kNR = kObsSlots;
 constexpr int kRedThreads = 256;
+
+__host__ __device__ constexpr bool is_max_slot(int k) { return k == 4 || k == 9 || k == 10; }
+__host__ __device__ constexpr double slot_start(int k) { return (k == 9 || k == 10) ? -1e300 : 0.0; }
 
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -235,7 +239,7 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[kNR], double* o
     __shared__ double red[kRedThreads / 64][kNR];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-    for (int k = 0; k < kNR; ++k) acc[k] = (k == 4) ? wave_max(acc[k]) : wave_sum(acc[k]);
+    for (int k = 0; k < kNR; ++k) acc[k] = is_max_slot(k) ? wave_max(acc[k]) : wave_sum(acc[k]);
     if (lane == 0)
 #pragma unroll
         for (int k = 0; k < kNR; ++k) red[wv][k] = acc[k];
@@ -243,7 +247,7 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[kNR], double* o
     if (threadIdx.x < kNR) {
         const int k = threadIdx.x;
         double v = red[0][k];
-        for (int w = 1; w < kRedThreads / 64; ++w) v = (k == 4) ? fmax(v, red[w][k]) : v + red[w][k];
+        for (int w = 1; w < kRedThreads / 64; ++w) v = is_max_slot(k) ? fmax(v, red[w][k]) : v + red[w][k];
         out[k] = v;
     }
 }
@@ -252,7 +256,9 @@ __global__ void __launch_bounds__(kRedThreads)
 k_reduce_partials(const double* __restrict__ rho, const double* __restrict__ u, const uint8_t* __restrict__ solid,
                   int dim, int64_t n, double* __restrict__ partials)
 {
-    double acc[kNR] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double acc[kNR];
+#pragma unroll
+    for (int k = 0; k < kNR; ++k) acc[k] = slot_start(k);
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const double r = rho[i];
@@ -279,6 +285,8 @@ k_reduce_partials(const double* __restrict__ rho, const double* __restrict__ u, 
         acc[5] += um;
         acc[6] += uu;
         acc[8] += 1.0;
+        acc[9] = fmax(acc[9], r);
+        acc[10] = fmax(acc[10], -r);
     }
     block_reduce_store(acc, partials + (int64_t)blockIdx.x * kNR);
 }
@@ -286,11 +294,13 @@ k_reduce_partials(const double* __restrict__ rho, const double* __restrict__ u, 
 __global__ void __launch_bounds__(kRedThreads)
 k_reduce_final(const double* __restrict__ partials, int nblk, double* __restrict__ out)
 {
-    double acc[kNR] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double acc[kNR];
+#pragma unroll
+    for (int k = 0; k < kNR; ++k) acc[k] = slot_start(k);
     for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
         const double* p = partials + (int64_t)b * kNR;
 #pragma unroll
-        for (int k = 0; k < kNR; ++k) acc[k] = (k == 4) ? fmax(acc[k], p[k]) : acc[k] + p[k];
+        for (int k = 0; k < kNR; ++k) acc[k] = is_max_slot(k) ? fmax(acc[k], p[k]) : acc[k] + p[k];
     }
     block_reduce_store(acc, out);
 }

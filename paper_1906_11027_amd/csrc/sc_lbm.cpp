@@ -23,6 +23,7 @@ using namespace sclbm;
 namespace {
 
 constexpr int kGraphSteps = 32;   // steps per captured graph (even)
+constexpr int kFloorWindow = 100; // checks the FP32 resolution rule looks back over
 
 struct ObsState {
     bool ready = false;
@@ -49,7 +50,10 @@ struct sc_lbm {
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     bool graph_failed = false;
     double last_max_u = -1.0;
-    int fp32_hits = 0;
+    double umax_hist[kFloorWindow] = {};   // max|u| of the last checks (FP32 resolution rule)
+    int64_t umax_n = 0;          // checks recorded since the last reset
+    bool at_floor = false;       // the last check found the run at its resolution
+    int tol_hits = 0;            // consecutive checks with a change below tol
     uint8_t* solid = nullptr;   // device wall mask [N] (null: no walls)
 };
 
@@ -659,6 +663,8 @@ static int observe_core(sc_lbm* h, sc_lbm_obs* o)
     o->mom[2] = res[3];
     o->max_u = res[4];
     const double nfin = res[8];   // finite fluid nodes
+    o->rho_max = nfin > 0 ? res[9] : std::nan("");
+    o->rho_min = nfin > 0 ? -res[10] : std::nan("");
     o->mean_u = nfin > 0 ? res[5] / nfin : 0.0;
     o->l2_u = nfin > 0 ? std::sqrt(res[6] / nfin) : 0.0;
     o->nonfinite = (int64_t)res[7];
@@ -673,6 +679,72 @@ static int observe_core(sc_lbm* h, sc_lbm_obs* o)
     o->d_max_u = h->last_max_u >= 0 ? std::fabs(o->max_u - h->last_max_u) : -1.0;
     o->status = o->nonfinite ? SC_E_NONFINITE : SC_OK;
     return SC_OK;
+}
+
+// sum_b |c_b| w_b of each lattice
+static double lattice_cw(int lattice)
+{
+    switch (lattice) {
+    case SC_D2Q9: return 4.0 / 9.0 + 4.0 * std::sqrt(2.0) / 36.0;
+    case SC_D3Q19: return 6.0 / 18.0 + 12.0 * std::sqrt(2.0) / 36.0;
+    case SC_D2Q13: return 4.0 * (8.0 / 75.0) + 4.0 * std::sqrt(2.0) / 25.0 + 4.0 * 2.0 / 300.0;
+    case SC_D2Q25:
+        return 4.0 * (16.0 / 147.0) + 4.0 * std::sqrt(2.0) * (16.0 / 315.0) + 4.0 * 2.0 / 105.0 +
+               8.0 * std::sqrt(5.0) * (8.0 / 2205.0) + 4.0 * std::sqrt(8.0) / 8820.0;
+    default: return 1.0;
+    }
+}
+
+// Smallest change of max|u| an FP32 state resolves: each stored
+// g_b = f_b - w_b rho_ref is rounded to 2^-24 of its size, at most
+// w_b max(1, |rho - rho_ref|); u = (sum_b g_b c_b + F/2) / rho sums them with
+// weights |c_b| and divides by rho.  Taken with a factor 4 for the sums, and
+// never below 4 ulp of max|u| itself.
+static double fp32_u_floor(const sc_lbm_params& p, const sc_lbm_obs& o)
+{
+    const double ulp4 = 4.0 * o.max_u * 1.1920928955078125e-7;
+    if (!(o.rho_min > 0.0)) return ulp4;
+    const double big = std::max(1.0, std::max(std::fabs(o.rho_max - p.rho_ref), std::fabs(o.rho_min - p.rho_ref)));
+    return std::max(ulp4, 4.0 * 5.9604644775390625e-8 * lattice_cw(p.lattice) * big / o.rho_min);
+}
+
+// Records this check's max|u|.  An FP32 run is at its resolution when the
+// max|u| of its last 100 checks lie within one band of fp32_u_floor: a drift
+// of d per check widens that band by 99 d, round-off noise of the state does
+// not, so a run still converging slowly keeps going (droplets have modes
+// that drift by ~1e-8 per check for 10^5 steps).
+static bool fp32_at_resolution(sc_lbm* h, const sc_lbm_obs& o)
+{
+    h->umax_hist[h->umax_n % kFloorWindow] = o.max_u;
+    ++h->umax_n;
+    h->at_floor = false;
+    if (h->p.precision != SC_FP32_SHIFTED || h->umax_n < kFloorWindow) return false;
+    double lo = h->umax_hist[0], hi = lo;
+    for (int k = 1; k < kFloorWindow; ++k) {
+        lo = std::min(lo, h->umax_hist[k]);
+        hi = std::max(hi, h->umax_hist[k]);
+    }
+    h->at_floor = hi - lo <= fp32_u_floor(h->p, o);
+    return h->at_floor;
+}
+
+static void reset_convergence(sc_lbm* h)
+{
+    h->last_max_u = -1.0;
+    h->umax_n = 0;
+    h->at_floor = false;
+    h->tol_hits = 0;
+}
+
+// The tolerance rule: |max_u - previous max_u| < tol.  An FP32 state's
+// round-off moves max_u by ~1e-7 per check near a steady state, so a single
+// check (or a turning point of max_u) can fall below a small tol by chance;
+// FP32 runs need it on 3 consecutive checks.
+static bool tol_rule(sc_lbm* h, const sc_lbm_obs& o, double tol)
+{
+    const bool below = o.d_max_u >= 0 && o.d_max_u < tol;
+    h->tol_hits = below ? h->tol_hits + 1 : 0;
+    return h->p.precision == SC_FP64 ? below : h->tol_hits >= 3;
 }
 
 extern "C" int sc_lbm_step(sc_lbm* h, int64_t max_steps, double tol, int64_t* steps_done)
@@ -702,15 +774,8 @@ extern "C" int sc_lbm_step(sc_lbm* h, int64_t max_steps, double tol, int64_t* st
             rc = SC_E_NONFINITE;
             break;
         }
-        bool done = false;
-        if (o.d_max_u >= 0 && o.d_max_u < tol) {
-            done = true;
-        } else if (h->p.precision == SC_FP32_SHIFTED && o.d_max_u >= 0 &&
-                   o.d_max_u <= 4.0 * o.max_u * 1.1920928955078125e-7) {
-            if (++h->fp32_hits >= 10) done = true;
-        } else {
-            h->fp32_hits = 0;
-        }
+        const bool floor = fp32_at_resolution(h, o);
+        const bool done = tol_rule(h, o, tol) || floor;
         h->last_max_u = o.max_u;
         if (done) break;
     }
@@ -724,7 +789,7 @@ extern "C" int sc_lbm_observe(sc_lbm* h, sc_lbm_obs* obs, double* rho_out, doubl
     sc_lbm_obs o;
     int rc = observe_core(h, &o);
     if (rc != SC_OK) return rc;
-    if (o.d_max_u >= 0 && h->p.precision == SC_FP32_SHIFTED && h->fp32_hits >= 10) o.converged_by = 2;
+    if (h->at_floor) o.converged_by = 2;
     ObsBuffers& b = h->obs.b;
     hipError_t e = hipSuccess;
     if (rho_out) e = hipMemcpyAsync(rho_out, b.rho, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->stream);
@@ -767,8 +832,7 @@ extern "C" int sc_lbm_set_state(sc_lbm* h, const void* f_in, int64_t step)
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_err(e);
     h->step = step;
-    h->last_max_u = -1.0;
-    h->fp32_hits = 0;
+    reset_convergence(h);
     return SC_OK;
 }
 
@@ -826,10 +890,9 @@ extern "C" int sc_lbm_set_walls(sc_lbm* h, const uint8_t* solid, double rho_w)
         if (now == family_of(h->p))
             h->variant = h->p.variant >= 0 ? h->p.variant : auto_variant(h->p, h->n);
         else
-            h->variant = h->n < ((int64_t)1 << 20) ? 1 : 0;
+            h->variant = h->n < ((int64_t)1 << 20) ? 1 : 4;   // wide32x8r1 / wide128x16r2
     }
-    h->last_max_u = -1.0;
-    h->fp32_hits = 0;
+    reset_convergence(h);
     return SC_OK;
 }
 
@@ -1062,16 +1125,11 @@ extern "C" int sc_lbm_batch_step(sc_lbm_batch* b, int64_t max_steps, double tol,
             rc = observe_core(h, &o);
             if (rc != SC_OK) break;
             int by = 0;
-            if (o.nonfinite) {
-                by = -1;
-            } else if (o.d_max_u >= 0 && o.d_max_u < tol) {
-                by = 1;
-            } else if (h->p.precision == SC_FP32_SHIFTED && o.d_max_u >= 0 &&
-                       o.d_max_u <= 4.0 * o.max_u * 1.1920928955078125e-7) {
-                if (++h->fp32_hits >= 10) by = 2;
-            } else {
-                h->fp32_hits = 0;
-            }
+            const bool floor = fp32_at_resolution(h, o);
+            const bool tol_ok = tol_rule(h, o, tol);
+            if (o.nonfinite) by = -1;
+            else if (tol_ok) by = 1;
+            else if (floor) by = 2;
             h->last_max_u = o.max_u;
             if (by != 0) {
                 b->active[i] = 0;

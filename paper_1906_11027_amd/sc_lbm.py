@@ -50,7 +50,8 @@ class sc_lbm_obs(ctypes.Structure):
         ("max_u", ctypes.c_double), ("mean_u", ctypes.c_double), ("l2_u", ctypes.c_double),
         ("rho_in", ctypes.c_double), ("rho_out", ctypes.c_double),
         ("p_in", ctypes.c_double), ("p_out", ctypes.c_double), ("dp", ctypes.c_double),
-        ("radius", ctypes.c_double), ("d_max_u", ctypes.c_double),
+        ("radius", ctypes.c_double), ("rho_min", ctypes.c_double), ("rho_max", ctypes.c_double),
+        ("d_max_u", ctypes.c_double),
         ("nonfinite", ctypes.c_int64), ("converged_by", ctypes.c_int32), ("status", ctypes.c_int32),
     ]
 

@@ -265,24 +265,25 @@ def make_dataset(n_train, n_test, side, tol, max_steps, obs_every, chunk, seed, 
             "jitter": jitter}
 
 
-def _runs(starts, items, init, tol, max_steps, obs_every):
-    """Batched FP32 runs of `items` from the densities `starts`."""
-    run = [{"rho0": r, "order": it["order"], "G": it["G"], "tau": it["tau"], "init": init}
+def _runs(starts, items, init, tol, max_steps, obs_every, precision="fp32"):
+    """Batched runs of `items` from the densities `starts`."""
+    run = [{"rho0": r, "order": it["order"], "G": it["G"], "tau": it["tau"], "init": init, "precision": precision}
            for r, it in zip(starts, items)]
     return steady_states(run, tol=tol, max_steps=max_steps, obs_every=obs_every)
 
 
-def evaluate(ds, epochs=100, batch=16, lr=1e-3, fp64_baseline=8, seed=2026, tols=(None,), log=print):
+def evaluate(ds, epochs=100, batch=16, lr=1e-3, fp64_baseline=8, seed=2026, tols=(1e-10,), log=print):
     """Train on the dataset's training items, then compare steps and wall
-    time to steady state on its held-out items.  Starts (batched FP32 runs
-    unless noted):
+    time to steady state on its held-out items.  Starts (batched runs):
       tanh            the tanh start, f = feq(rho, 0) (the method without the net)
       tanh_rest       the tanh start at rest in the forced sense
       learned         the learned start at rest (inference included in its time)
       learned_eq      the learned start with f = feq(rho, 0)
-      tanh_jitter     the tanh start with the sweep's +-1e-3 per-node jitter
-      fp64            plain per-droplet FP64 runs from the tanh start (first items)
-    for each tolerance in `tols` (None = the dataset's)."""
+    all with the FP64 state, where the steady-state rule is the literal
+    max|u| change < tol; then tanh_fp32 and learned_fp32 with the FP32 state
+    and its rules (sc_lbm_step), and plain per-droplet FP64 runs from the
+    tanh start (first items), for each tolerance in `tols` (None = the
+    dataset's)."""
     from workload import droplet_rho
     torch = __import__("torch")
     items, fields, conv = ds["items"], ds["fields"], ds["conv"]
@@ -308,7 +309,6 @@ def evaluate(ds, epochs=100, batch=16, lr=1e-3, fp64_baseline=8, seed=2026, tols
     torch.cuda.synchronize()
     t_inf = time.perf_counter() - t0
     raw = [b + r / TARGET_SCALE for b, r in zip(bases, predict(net, [inputs[k] for k in test_idx]))]
-    jit = [droplet_rho((side, side), it["R"], seed=it["seed"]) for it in test_items]
     nt = max(1, len(test_idx))
 
     def rel(a, k):
@@ -333,19 +333,23 @@ def evaluate(ds, epochs=100, batch=16, lr=1e-3, fp64_baseline=8, seed=2026, tols
         tol = ds["tol"] if tol is None else tol
         key = "%.0e" % tol
         out = {}
-        for name, st, init in (("tanh", bases, "equilibrium"), ("tanh_rest", bases, "rest"),
-                               ("learned", starts, "rest"), ("learned_eq", starts, "equilibrium"),
-                               ("tanh_jitter", jit, "equilibrium")):
-            f, steps, by, wall = _runs(st, test_items, init, tol, max_steps, obs_every)
+        for name, st, init, prec in (("tanh", bases, "equilibrium", "fp64"), ("tanh_rest", bases, "rest", "fp64"),
+                                     ("learned", starts, "rest", "fp64"),
+                                     ("learned_eq", starts, "equilibrium", "fp64"),
+                                     ("tanh_fp32", bases, "equilibrium", "fp32"),
+                                     ("learned_fp32", starts, "rest", "fp32")):
+            f, steps, by, wall = _runs(st, test_items, init, tol, max_steps, obs_every, prec)
             extra = t_inf if name.startswith("learned") else 0.0
             out[name] = {"steps_mean": float(np.mean(steps)), "steps_median": float(np.median(steps)),
                          "wall_s_per_item": (wall + extra) / nt, "converged": int(sum(1 for v in by if v > 0)),
                          "fields": f, "steps": steps}
             log("%s tol %s: mean steps %.0f, %.4f s per droplet" % (name, key, out[name]["steps_mean"],
                                                                   out[name]["wall_s_per_item"]))
-        t_st = np.maximum(np.array(out["tanh"]["steps"]), 1)
         for name in list(out):
-            out[name]["steps_ratio_median_vs_tanh"] = float(np.median(np.array(out[name]["steps"]) / t_st))
+            ref = out["tanh_fp32" if name.endswith("fp32") else "tanh"]["steps"]
+            out[name]["steps_ratio_median_vs_tanh"] = float(np.median(np.array(out[name]["steps"]) /
+                                                                      np.maximum(np.array(ref), 1)))
+            out[name]["faster_than_tanh"] = int(np.sum(np.array(out[name]["steps"]) < np.array(ref)))
         agree = [float(np.max(np.abs(a - b))) for a, b in zip(out["learned"]["fields"], out["tanh"]["fields"])]
         out["steady_fields_max_abs_diff_median"] = float(np.median(agree)) if agree else None
         t0 = time.perf_counter()
@@ -360,10 +364,8 @@ def evaluate(ds, epochs=100, batch=16, lr=1e-3, fp64_baseline=8, seed=2026, tols
         nb = max(1, min(fp64_baseline, len(test_idx)))
         out["fp64"] = {"steps_mean": float(np.mean(fp64_steps)) if fp64_steps else None,
                        "wall_s_per_item": (time.perf_counter() - t0) / nb, "items": nb}
-        t_by = np.array(out["tanh"]["steps"])
         for name in out:
             if isinstance(out[name], dict) and "steps" in out[name]:
-                out[name]["faster_than_tanh"] = int(np.sum(np.array(out[name]["steps"]) < t_by))
                 out[name].pop("fields", None)
                 out[name]["steps"] = [int(v) for v in out[name]["steps"]]
         res["runs"][key] = out
@@ -372,7 +374,7 @@ def evaluate(ds, epochs=100, batch=16, lr=1e-3, fp64_baseline=8, seed=2026, tols
 
 def run_experiment(n_train=2000, n_test=64, side=256, tol=1e-8, epochs=100, batch=16, lr=1e-3,
                    max_steps=150000, obs_every=200, chunk=64, fp64_baseline=8, seed=2026, jitter=False,
-                   tols=(None,), log=print):
+                   tols=(1e-10,), log=print):
     """The 256^2 warm-start experiment: dataset from batched sweeps, then evaluate()."""
     ds = make_dataset(n_train, n_test, side, tol, max_steps, obs_every, chunk, seed, jitter=jitter, log=log)
     return evaluate(ds, epochs=epochs, batch=batch, lr=lr, fp64_baseline=fp64_baseline, seed=seed, tols=tols,
@@ -391,7 +393,7 @@ if __name__ == "__main__":
     ap.add_argument("--n-test", type=int, default=64)
     ap.add_argument("--side", type=int, default=256)
     ap.add_argument("--tol", type=float, default=1e-8, help="steady-state rule of the dataset runs")
-    ap.add_argument("--eval-tols", default="1e-8", help="rules the starts are compared at")
+    ap.add_argument("--eval-tols", default="1e-10", help="rules the starts are compared at")
     ap.add_argument("--epochs", type=int, default=100)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--jitter", action="store_true", help="dataset runs from the jittered tanh start")

@@ -208,12 +208,12 @@ def test_warm_start_gain_small():
     """Scaled-down warm-start experiment on 64^2 droplets.  What the trained
     net gains over the tanh start: an initial density field several times
     closer to the steady state and, started at rest in the forced sense,
-    fewer steps to the steady-state rule; both starts reach the same steady
-    field."""
+    fewer steps to the steady-state rule (max|u| change < 1e-10, batched FP64
+    runs); both starts reach the same steady field."""
     res = WS.run_experiment(n_train=128, n_test=12, side=64, tol=1e-8, epochs=400, batch=16, lr=1e-3,
-                            max_steps=80000, obs_every=100, chunk=64, fp64_baseline=2, seed=77, tols=(None,),
+                            max_steps=80000, obs_every=100, chunk=64, fp64_baseline=2, seed=77, tols=(1e-10,),
                             log=lambda m: None)
-    runs = res.pop("runs")["1e-08"]
+    runs = res.pop("runs")["1e-10"]
     say("warm start:", res)
     for name, r in runs.items():
         say("  ", name, r)
@@ -222,4 +222,6 @@ def test_warm_start_gain_small():
     assert res["loss_last"] < 0.05 * res["loss_first"]
     assert res["err_rms_median"]["learned"] < 0.5 * res["err_rms_median"]["tanh"]
     assert runs["learned"]["steps_mean"] < 0.9 * runs["tanh"]["steps_mean"]
-    assert runs["steady_fields_max_abs_diff_median"] < 0.05
+    # both starts are symmetric, so they settle on the same droplet (no
+    # translation to align): the FP64 steady fields agree to 1e-5 of rho
+    assert runs["steady_fields_max_abs_diff_median"] < 1e-5 * 2.0

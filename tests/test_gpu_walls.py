@@ -44,6 +44,8 @@ def _compare(sim, orc, prec, label, solid):
     ob, oo = got["obs"], orc.observables()
     for k in ("max_u", "mean_u"):
         assert abs(ob[k] - oo[k]) <= (tu * oo[k] + UFLOOR[prec]), (k, ob[k], oo[k])
+    for k in ("rho_min", "rho_max"):   # over fluid nodes only
+        assert abs(ob[k] - oo[k]) <= tr * oo[k], (k, ob[k], oo[k])
     return got, ref
 
 
