@@ -12,8 +12,8 @@
 // thread keeps its pixel's Cout accumulators in registers.  Backward-data is
 // the same kernel applied to the channel-transposed, spatially flipped
 // weights.  Backward-weight accumulates per-block partial sums over a fixed
-// share of (tile, image) pairs, then a column reduction sums the partials in
-// a fixed order (deterministic).
+// share of (tile, image) pairs (a 32 x 288 x 256 contraction per pair), then a
+// column reduction sums the partials in a fixed order (deterministic).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -50,7 +50,7 @@ k_conv_fwd(const float* __restrict__ in, const uint16_t* __restrict__ w, const f
            float* __restrict__ out, int cin, int cout, int h, int wd)
 {
     __shared__ float tile[CCH][TS + 2][TS + 3];
-    __shared__ float ws[COUT][CCH][9];
+    __shared__ float ws[CCH][9][COUT];   // output channels contiguous: vector LDS reads
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TS + tx;
     const int tiles_x = (wd + TS - 1) / TS;
     const int x0 = (blockIdx.x % tiles_x) * TS, y0 = (blockIdx.x / tiles_x) * TS;
@@ -75,7 +75,7 @@ k_conv_fwd(const float* __restrict__ in, const uint16_t* __restrict__ w, const f
         }
         for (int i = tid; i < COUT * CCH * 9; i += TS * TS) {
             const int co = i / (CCH * 9), r = i % (CCH * 9), c = r / 9, k = r % 9;
-            ws[co][c][k] = (co < cout && c < nc) ? bf16_to_f(w[((int64_t)co * cin + c0 + c) * 9 + k]) : 0.f;
+            ws[c][k][co] = (co < cout && c < nc) ? bf16_to_f(w[((int64_t)co * cin + c0 + c) * 9 + k]) : 0.f;
         }
         __syncthreads();
         for (int c = 0; c < nc; ++c) {
@@ -83,7 +83,7 @@ k_conv_fwd(const float* __restrict__ in, const uint16_t* __restrict__ w, const f
             for (int k = 0; k < 9; ++k) {
                 const float v = tile[c][ty + k / 3][tx + k % 3];
 #pragma unroll
-                for (int co = 0; co < COUT; ++co) acc[co] += ws[co][c][k] * v;
+                for (int co = 0; co < COUT; ++co) acc[co] += ws[c][k][co] * v;
             }
         }
         __syncthreads();
@@ -106,89 +106,112 @@ __global__ void k_transpose_flip(const uint16_t* __restrict__ w, uint16_t* __res
     wt[((int64_t)ci * cout + co) * 9 + (8 - k)] = w[i];
 }
 
-// partial[blk][(ci*cout + co)*9 + k] (entries enumerated ci-major so the
-// lanes of a wave share one input-channel chunk) and partial[blk][E + co] (bias)
-template <int EPT>
+// partial[blk][(ci*cout + co)*9 + k] and partial[blk][E + co] (bias): the
+// block's share of (tile, image) pairs.  Per pair the gradient is a small
+// contraction over the tile's pixels p, gw[co][ci][k] += g[co][p] in[ci][p+k];
+// thread (cog, ci) = (tid / 32, tid % 32) owns 4 output channels x 9 taps of
+// one input channel, so each pixel costs 4 + 9 LDS reads for 36 FMAs.  The
+// input tile holds every channel, one plane of 18 x 19 + 1 floats each (an
+// odd stride: the 32 channels a half-wave reads sit in 32 different banks).
+constexpr int TPL = (TS + 2) * (TS + 3) + 1;   // floats per input-channel plane in LDS
+
 __global__ void __launch_bounds__(TS* TS)
 k_conv_bwd_w(const float* __restrict__ in, const float* __restrict__ gout, float* __restrict__ partial, int batch,
              int cin, int cout, int h, int wd)
 {
-    __shared__ float tile[CCH][TS + 2][TS + 3];
+    __shared__ float tile[MAXC * TPL];
     __shared__ float gs[MAXC][TS * TS];
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TS + tx;
+    const int tid = threadIdx.y * TS + threadIdx.x;
+    const int ci = tid % MAXC, cog = tid / MAXC;   // 8 groups of 4 output channels
     const int tiles_x = (wd + TS - 1) / TS, tiles_y = (h + TS - 1) / TS;
     const int nwork = tiles_x * tiles_y * batch;
     const int64_t plane = (int64_t)h * wd;
     const int E = cout * cin * 9;
-    float acc[EPT];
+    float acc[4][9];
     float bacc = 0.f;
 #pragma unroll
-    for (int j = 0; j < EPT; ++j) acc[j] = 0.f;
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc[j][k] = 0.f;
     for (int wi = blockIdx.x; wi < nwork; wi += gridDim.x) {
         const int b = wi / (tiles_x * tiles_y), t = wi % (tiles_x * tiles_y);
         const int x0 = (t % tiles_x) * TS, y0 = (t / tiles_x) * TS;
-        // output-gradient tile for all channels (zero outside the image)
-        for (int i = tid; i < cout * TS * TS; i += TS * TS) {
+        // output-gradient tile, every channel (zero outside the image and
+        // for channels beyond cout)
+        for (int i = tid; i < MAXC * TS * TS; i += TS * TS) {
             const int co = i / (TS * TS), p = i % (TS * TS);
             const int x = x0 + p % TS, y = y0 + p / TS;
-            gs[co][p] = (x < wd && y < h) ? gout[((int64_t)b * cout + co) * plane + (int64_t)y * wd + x] : 0.f;
+            gs[co][p] = (co < cout && x < wd && y < h) ? gout[((int64_t)b * cout + co) * plane + (int64_t)y * wd + x]
+                                                       : 0.f;
+        }
+        // input tile with a wrapped halo of one, every channel
+        for (int i = tid; i < cin * (TS + 2) * (TS + 2); i += TS * TS) {
+            const int c = i / ((TS + 2) * (TS + 2));
+            const int r = i % ((TS + 2) * (TS + 2));
+            const int ly = r / (TS + 2), lx = r % (TS + 2);
+            const int gy = wrapc(y0 + ly - 1, h), gx = wrapc(x0 + lx - 1, wd);
+            tile[c * TPL + ly * (TS + 3) + lx] = in[((int64_t)b * cin + c) * plane + (int64_t)gy * wd + gx];
         }
         __syncthreads();
         if (tid < cout) {
-            float s = 0.f;
-            for (int p = 0; p < TS * TS; ++p) s += gs[tid][p];
-            bacc += s;
+            float sb = 0.f;
+            for (int p = 0; p < TS * TS; ++p) sb += gs[tid][p];
+            bacc += sb;
         }
-        for (int c0 = 0; c0 < cin; c0 += CCH) {
-            const int nc = cin - c0 < CCH ? cin - c0 : CCH;
-            for (int i = tid; i < CCH * (TS + 2) * (TS + 2); i += TS * TS) {
-                const int c = i / ((TS + 2) * (TS + 2));
-                const int r = i % ((TS + 2) * (TS + 2));
-                const int ly = r / (TS + 2), lx = r % (TS + 2);
-                float v = 0.f;
-                if (c < nc) {
-                    const int gy = wrapc(y0 + ly - 1, h), gx = wrapc(x0 + lx - 1, wd);
-                    v = in[((int64_t)b * cin + c0 + c) * plane + (int64_t)gy * wd + gx];
-                }
-                tile[c][ly][lx] = v;
-            }
-            __syncthreads();
+        if (ci < cin && cog * 4 < cout) {
+            const float* tc = tile + ci * TPL;
+            for (int py = 0; py < TS; ++py) {
+#pragma unroll 4
+                for (int px = 0; px < TS; ++px) {
+                    const int p = py * TS + px;
+                    float g[4], v[9];
 #pragma unroll
-            for (int j = 0; j < EPT; ++j) {
-                const int e = tid + j * TS * TS;
-                if (e < E) {
-                    const int ci = e / (cout * 9), r = e % (cout * 9), co = r / 9, k = r % 9;
-                    if (ci >= c0 && ci < c0 + nc) {
-                        const int c = ci - c0, ky = k / 3, kx = k % 3;
-                        float s = 0.f;
-                        for (int p = 0; p < TS * TS; ++p) s += gs[co][p] * tile[c][p / TS + ky][p % TS + kx];
-                        acc[j] += s;
-                    }
+                    for (int j = 0; j < 4; ++j) g[j] = gs[cog * 4 + j][p];
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) v[k] = tc[(py + k / 3) * (TS + 3) + px + k % 3];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+#pragma unroll
+                        for (int k = 0; k < 9; ++k) acc[j][k] += g[j] * v[k];
                 }
             }
-            __syncthreads();
         }
+        __syncthreads();
     }
     float* pb = partial + (int64_t)blockIdx.x * (E + cout);
+    if (ci < cin) {
 #pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-        const int e = tid + j * TS * TS;
-        if (e < E) pb[e] = acc[j];
+        for (int j = 0; j < 4; ++j) {
+            const int co = cog * 4 + j;
+            if (co < cout)
+#pragma unroll
+                for (int k = 0; k < 9; ++k) pb[(ci * cout + co) * 9 + k] = acc[j][k];
+        }
     }
     if (tid < cout) pb[E + tid] = bacc;
 }
 
 // Sum the per-block partials in a fixed order: gw[co][ci][k] from the
-// ci-major partial entries, gbias[co] from the trailing bias columns.
-__global__ void k_sum_partials(const float* __restrict__ m, int nrow, int cin, int cout, float* __restrict__ gw,
-                               float* __restrict__ gbias)
+// ci-major partial entries, gbias[co] from the trailing bias columns.  A block
+// covers 64 columns with 4 row groups (rows r = g mod 4), combined in group
+// order through LDS.
+constexpr int kSumCols = 64, kSumGroups = 4;
+__global__ void __launch_bounds__(kSumCols* kSumGroups)
+k_sum_partials(const float* __restrict__ m, int nrow, int cin, int cout, float* __restrict__ gw,
+               float* __restrict__ gbias)
 {
+    __shared__ float part[kSumGroups][kSumCols];
     const int E = cin * cout * 9;
     const int ncol = E + cout;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= ncol) return;
+    const int lc = threadIdx.x % kSumCols, g = threadIdx.x / kSumCols;
+    const int j = blockIdx.x * kSumCols + lc;
     float s = 0.f;
-    for (int r = 0; r < nrow; ++r) s += m[(int64_t)r * ncol + j];
+    if (j < ncol)
+        for (int r = g; r < nrow; r += kSumGroups) s += m[(int64_t)r * ncol + j];
+    part[g][lc] = s;
+    __syncthreads();
+    if (g != 0 || j >= ncol) return;
+    s = ((part[0][lc] + part[1][lc]) + part[2][lc]) + part[3][lc];
     if (j < E) {
         const int ci = j / (cout * 9), rr = j % (cout * 9), co = rr / 9, k = rr % 9;
         gw[((int64_t)co * cin + ci) * 9 + k] = s;
@@ -377,21 +400,12 @@ extern "C" int sc_nn_conv3x3_bwd_weight(const float* in, const float* gout, floa
     if (!in || !gout || !partial_scratch || !gw || !gbias || nblk < 1 || !conv_shape_ok(batch, cin, cout, h, wd))
         return SC_E_INVAL;
     const int E = cin * cout * 9;
-    const int ept = (E + TS * TS - 1) / (TS * TS);
-    dim3 block(TS, TS);
     hipStream_t s = (hipStream_t)stream;
-    if (ept <= 2)
-        hipLaunchKernelGGL(k_conv_bwd_w<2>, nblk, block, 0, s, in, gout, partial_scratch, batch, cin, cout, h, wd);
-    else if (ept <= 8)
-        hipLaunchKernelGGL(k_conv_bwd_w<8>, nblk, block, 0, s, in, gout, partial_scratch, batch, cin, cout, h, wd);
-    else if (ept <= 36)
-        hipLaunchKernelGGL(k_conv_bwd_w<36>, nblk, block, 0, s, in, gout, partial_scratch, batch, cin, cout, h, wd);
-    else
-        return SC_E_INVAL;
+    hipLaunchKernelGGL(k_conv_bwd_w, nblk, dim3(TS, TS), 0, s, in, gout, partial_scratch, batch, cin, cout, h, wd);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return nn_status(e);
-    hipLaunchKernelGGL(k_sum_partials, (E + cout + 255) / 256, 256, 0, s, partial_scratch, nblk, cin, cout, gw,
-                       gbias);
+    hipLaunchKernelGGL(k_sum_partials, (E + cout + kSumCols - 1) / kSumCols, kSumCols * kSumGroups, 0, s,
+                       partial_scratch, nblk, cin, cout, gw, gbias);
     return nn_status(hipGetLastError());
 }
 

@@ -81,7 +81,7 @@ class WarmStartNet:
         self.acts = [torch.empty((batch, c, h, w), dtype=torch.float32, device=self.dev) for c in CHANNELS]
         self.gact = [torch.empty((batch, c, h, w), dtype=torch.float32, device=self.dev) for c in CHANNELS]
         self.prm = torch.empty((batch, 4), dtype=torch.float32, device=self.dev)
-        self.nblk_w = 128
+        self.nblk_w = 512
         nsc = max(B.lib().sc_nn_bwd_weight_scratch_floats(CHANNELS[i], CHANNELS[i + 1], self.nblk_w)
                   for i in range(5))
         self.wscratch = torch.empty(nsc, dtype=torch.float32, device=self.dev)
@@ -272,7 +272,7 @@ def _runs(starts, items, init, tol, max_steps, obs_every, precision="fp32"):
     return steady_states(run, tol=tol, max_steps=max_steps, obs_every=obs_every)
 
 
-def evaluate(ds, epochs=100, batch=16, lr=1e-3, fp64_baseline=8, seed=2026, tols=(1e-10,), log=print):
+def evaluate(ds, epochs=300, batch=16, lr=1e-3, fp64_baseline=8, seed=2026, tols=(1e-10,), log=print):
     """Train on the dataset's training items, then compare steps and wall
     time to steady state on its held-out items.  Starts (batched runs):
       tanh            the tanh start, f = feq(rho, 0) (the method without the net)
@@ -372,7 +372,7 @@ def evaluate(ds, epochs=100, batch=16, lr=1e-3, fp64_baseline=8, seed=2026, tols
     return res
 
 
-def run_experiment(n_train=2000, n_test=64, side=256, tol=1e-8, epochs=100, batch=16, lr=1e-3,
+def run_experiment(n_train=2000, n_test=64, side=256, tol=1e-8, epochs=300, batch=16, lr=1e-3,
                    max_steps=150000, obs_every=200, chunk=64, fp64_baseline=8, seed=2026, jitter=False,
                    tols=(1e-10,), log=print):
     """The 256^2 warm-start experiment: dataset from batched sweeps, then evaluate()."""
@@ -394,7 +394,7 @@ if __name__ == "__main__":
     ap.add_argument("--side", type=int, default=256)
     ap.add_argument("--tol", type=float, default=1e-8, help="steady-state rule of the dataset runs")
     ap.add_argument("--eval-tols", default="1e-10", help="rules the starts are compared at")
-    ap.add_argument("--epochs", type=int, default=100)
+    ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--jitter", action="store_true", help="dataset runs from the jittered tanh start")
     ap.add_argument("--out", default=None)
