@@ -136,7 +136,8 @@ typedef struct sc_lbm_obs {
     double rho_min, rho_max; /* extremes of rho over finite fluid nodes           */
     double d_max_u;       /* |max_u - max_u at the previous check|, or -1         */
     int64_t nonfinite;    /* nodes with a non-finite rho or u                     */
-    int32_t converged_by; /* 0 no; 1 d_max_u < tol; 2 FP32 resolution floor       */
+    int32_t converged_by; /* rule that stopped the last sc_lbm_step: 0 none (or no
+                             tol given); 1 d_max_u < tol; 2 FP32 resolution rule */
     int32_t status;       /* SC_OK or SC_E_NONFINITE                              */
 } sc_lbm_obs;
 

@@ -52,7 +52,7 @@ struct sc_lbm {
     double last_max_u = -1.0;
     double umax_hist[kFloorWindow] = {};   // max|u| of the last checks (FP32 resolution rule)
     int64_t umax_n = 0;          // checks recorded since the last reset
-    bool at_floor = false;       // the last check found the run at its resolution
+    int conv_by = 0;             // rule that stopped the last sc_lbm_step: 1 tol, 2 FP32 floor
     int tol_hits = 0;            // consecutive checks with a change below tol
     uint8_t* solid = nullptr;   // device wall mask [N] (null: no walls)
 };
@@ -717,22 +717,20 @@ static bool fp32_at_resolution(sc_lbm* h, const sc_lbm_obs& o)
 {
     h->umax_hist[h->umax_n % kFloorWindow] = o.max_u;
     ++h->umax_n;
-    h->at_floor = false;
     if (h->p.precision != SC_FP32_SHIFTED || h->umax_n < kFloorWindow) return false;
     double lo = h->umax_hist[0], hi = lo;
     for (int k = 1; k < kFloorWindow; ++k) {
         lo = std::min(lo, h->umax_hist[k]);
         hi = std::max(hi, h->umax_hist[k]);
     }
-    h->at_floor = hi - lo <= fp32_u_floor(h->p, o);
-    return h->at_floor;
+    return hi - lo <= fp32_u_floor(h->p, o);
 }
 
 static void reset_convergence(sc_lbm* h)
 {
     h->last_max_u = -1.0;
     h->umax_n = 0;
-    h->at_floor = false;
+    h->conv_by = 0;
     h->tol_hits = 0;
 }
 
@@ -751,6 +749,7 @@ extern "C" int sc_lbm_step(sc_lbm* h, int64_t max_steps, double tol, int64_t* st
 {
     if (!h || max_steps < 0 || !(tol >= 0.0)) return SC_E_INVAL;
     const int64_t start = h->step;
+    h->conv_by = 0;
     if (tol == 0.0) {
         hipError_t e = run_steps(h, max_steps);
         if (steps_done) *steps_done = h->step - start;
@@ -775,7 +774,9 @@ extern "C" int sc_lbm_step(sc_lbm* h, int64_t max_steps, double tol, int64_t* st
             break;
         }
         const bool floor = fp32_at_resolution(h, o);
-        const bool done = tol_rule(h, o, tol) || floor;
+        const bool tol_ok = tol_rule(h, o, tol);
+        h->conv_by = tol_ok ? 1 : (floor ? 2 : 0);
+        const bool done = tol_ok || floor;
         h->last_max_u = o.max_u;
         if (done) break;
     }
@@ -789,7 +790,7 @@ extern "C" int sc_lbm_observe(sc_lbm* h, sc_lbm_obs* obs, double* rho_out, doubl
     sc_lbm_obs o;
     int rc = observe_core(h, &o);
     if (rc != SC_OK) return rc;
-    if (h->at_floor) o.converged_by = 2;
+    o.converged_by = h->conv_by;
     ObsBuffers& b = h->obs.b;
     hipError_t e = hipSuccess;
     if (rho_out) e = hipMemcpyAsync(rho_out, b.rho, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->stream);

@@ -210,7 +210,7 @@ def test_fp32_run_stops_at_its_resolution(item):
     say("fp32 stops after %d steps (by %d), fp64 after %d; max_u %.6e / %.6e, dp %.6e / %.6e" % (
         n32, o32["converged_by"], n64, o32["max_u"], o64["max_u"], o32["dp"], o64["dp"]))
     assert rc == 0 and rc64 == 0 and n32 < 150000 and n64 < 250000
-    assert o32["converged_by"] == 2
+    assert o32["converged_by"] == 2 and o64["converged_by"] == 1
     assert abs(o32["max_u"] - o64["max_u"]) < 1e-3 * o64["max_u"]
     assert abs(o32["dp"] - o64["dp"]) < 1e-4 * abs(o64["dp"]) + 1e-7
     for k in ("rho_min", "rho_max"):
