@@ -78,7 +78,11 @@ TRAFFIC_RATIO = {
     ("d2q13_e6_pr_edm_8192", "wide64x16r4"): (1.867, 1.000),
     ("d2q25_e8_pr_edm_8192", "wide64x16r2"): (1.792, 1.000),
     ("d2q25_e8_pr_edm_8192", "wide64x16r4"): (2.093, 1.000),
-    ("d2q9_e8_256", "tile2x16x16"): (0.909, 0.500),
+    ("d2q9_e8_256", "tile2x32x8t1024"): (0.677, 0.500),
+    ("d2q9_e8_256", "tile2x32x8t512"): (0.688, 0.500),
+    ("d2q9_e8_8192", "tile2x32x8t1024"): (0.626, 0.500),
+    ("d2q9_e8_8192", "tile2x32x8t512"): (0.626, 0.500),
+    ("d2q9_e8_256", "tile2x16x16"): (0.905, 0.500),
     ("d2q9_e8_256", "tile2x32x16"): (0.692, 0.500),
     ("d2q9_e8_256", "tile2x32x32"): (0.689, 0.500),
     ("d2q9_e8_256", "tile2x32x8"): (0.697, 0.500),

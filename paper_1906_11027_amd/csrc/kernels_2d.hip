@@ -245,13 +245,12 @@ k_d2q9_march(StepArgs<T> a, int H, int nbx)
 // node updates at 16 x 16), so this shape pays off only where launches
 // dominate.  Every region is walked by a bounded loop over its node count;
 // nodes outside the grid are computed on wrapped coordinates and not stored.
-template <typename T, int ORDER, int TX, int TY>
-__global__ void __launch_bounds__(TX* TY)
+template <typename T, int ORDER, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT)
 k_d2q9_tile2(StepArgs<T> a, int nbx, int nby, int sw)
 {
     using ST = Stencil<2, ORDER>;
     constexpr int R = ST::R;
-    constexpr int NT = TX * TY;
     constexpr int H1 = 2 * R + 1, P1W = TX + 2 * H1, P1H = TY + 2 * H1, P1N = P1W * P1H;   // psi1
     constexpr int HC = R + 1, C1W = TX + 2 * HC, C1H = TY + 2 * HC, C1N = C1W * C1H;       // s1
     constexpr int P2W = TX + 2 * R, P2H = TY + 2 * R, P2N = P2W * P2H;                     // psi2
@@ -262,7 +261,7 @@ k_d2q9_tile2(StepArgs<T> a, int nbx, int nby, int sw)
     const int nx = a.nx, ny = a.ny;
     const int64_t n = a.n;
     const uint32_t TS = sizeof(T), rowb = (uint32_t)nx * TS;
-    const int tid = threadIdx.y * TX + threadIdx.x;
+    const int tid = threadIdx.x;
     int bx, by;
     strip_tile(xcd_swizzle(blockIdx.x, gridDim.x), nbx, nby, sw, bx, by);
     const int x0 = bx * TX, y0 = by * TY;
@@ -353,8 +352,12 @@ k_d2q9_tile2(StepArgs<T> a, int nbx, int nby, int sw)
     }
     __syncthreads();
     // phase 4: step t+1 -> t+2 on the tile, store
-    {
-        const int lx = threadIdx.x, ly = threadIdx.y;
+    constexpr int K4 = (TX * TY + NT - 1) / NT;
+#pragma unroll
+    for (int q = 0; q < K4; ++q) {
+        const int i = tid + q * NT;
+        if (i >= TX * TY) break;
+        const int lx = i % TX, ly = i / TX;
         T g[9];
         pull_s1(lx + HC, ly + HC, g);
         T Fx, Fy;
@@ -377,11 +380,12 @@ static const Shape2D kShapes2D[] = {
     {"tile64x16r4"}, {"tile64x8r2"}, {"tile32x8r1"}, {"tile64x4r1"},
     {"march256h128"}, {"march256h128pf2"}, {"march512h128"}, {"march256h128pf3"}, {"march512h128pf2"},
     {"tile2x16x16"}, {"tile2x32x8"}, {"tile2x32x16"}, {"tile2x64x8"}, {"tile2x64x16"}, {"tile2x32x32"},
+    {"tile2x32x8t512"}, {"tile2x32x8t1024"},
 };
 constexpr int kNumShapes2D = sizeof(kShapes2D) / sizeof(kShapes2D[0]);
 
 int num_variants_d2q9() { return kNumShapes2D; }
-int variant_steps_d2q9(int v) { return (v >= 9 && v <= 14) ? 2 : 1; }
+int variant_steps_d2q9(int v) { return (v >= 9 && v <= 16) ? 2 : 1; }
 const char* variant_name_d2q9(int v) { return (v >= 0 && v < kNumShapes2D) ? kShapes2D[v].name : "?"; }
 
 template <typename T, int ORDER, int TX, int TY, int RPT>
@@ -394,11 +398,11 @@ static hipError_t launch_tile(const StepArgs<T>& a, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename T, int ORDER, int TX, int TY>
+template <typename T, int ORDER, int TX, int TY, int NT = TX * TY>
 static hipError_t launch_tile2(const StepArgs<T>& a, hipStream_t s)
 {
     const int nbx = (a.nx + TX - 1) / TX, nby = (a.ny + TY - 1) / TY;
-    hipLaunchKernelGGL((k_d2q9_tile2<T, ORDER, TX, TY>), dim3(nbx * nby), dim3(TX, TY), 0, s, a, nbx, nby,
+    hipLaunchKernelGGL((k_d2q9_tile2<T, ORDER, TX, TY, NT>), dim3(nbx * nby), dim3(NT), 0, s, a, nbx, nby,
                        kStripTiles);
     return hipGetLastError();
 }
@@ -433,6 +437,10 @@ static hipError_t launch_order(const StepArgs<T>& a, int variant, hipStream_t s)
     case 12: return launch_tile2<T, ORDER, 64, 8>(a, s);
     case 13: return launch_tile2<T, ORDER, 64, 16>(a, s);
     case 14: return launch_tile2<T, ORDER, 32, 32>(a, s);
+    // more threads than tile nodes: more waves per CU and fewer halo nodes per
+    // thread (the 256^2 grid has one 32 x 8 tile per CU)
+    case 15: return launch_tile2<T, ORDER, 32, 8, 512>(a, s);
+    case 16: return launch_tile2<T, ORDER, 32, 8, 1024>(a, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -65,7 +65,7 @@ def test_d2q9_droplet_64(order, prec):
     sim.close()
 
 
-@pytest.mark.parametrize("variant", [9, 10, 11, 12, 13, 14])
+@pytest.mark.parametrize("variant", list(range(9, 17)))
 @pytest.mark.parametrize("shape,order", [((37, 29), 10), ((3, 5), 4), ((1, 16), 6), ((64, 64), 8)])
 def test_d2q9_two_step_shapes(shape, order, variant):
     """Shapes that fuse two steps per launch, on ragged and tiny grids, with
