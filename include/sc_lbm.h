@@ -83,6 +83,8 @@ extern "C" {
 #define SC_FP32_SHIFTED 0      /* float state stored as f - w rho_ref       */
 #define SC_FP64 1              /* double state (same shift)                 */
 
+#define SC_RHO_REF_AUTO (-1.0)  /* rho_ref < 0: the library picks the shift  */
+
 #define SC_INIT_EQUILIBRIUM 0  /* f = feq(rho_init, 0)                      */
 #define SC_INIT_REST 1         /* f = feq(rho_init, -F / (2 rho_init)): the
                                   forced velocity (sum f c + F/2) / rho is
@@ -104,7 +106,10 @@ typedef struct sc_lbm_params {
     int32_t precision;    /* SC_FP32_SHIFTED or SC_FP64                           */
     double s_bulk;        /* MRT rate of the c^2 (bulk) moment                    */
     double s_ghost;       /* MRT rate of all non-hydrodynamic moments             */
-    double rho_ref;       /* storage shift (normally 1)                           */
+    double rho_ref;       /* storage shift, >= 0; or SC_RHO_REF_AUTO (any value
+                             < 0): the median of rho_init over at most 2^20
+                             evenly strided nodes, so that most nodes store
+                             values near zero; sc_lbm_rho_ref() returns it     */
     int32_t obs_every;    /* K: steps between convergence checks (default 100)    */
     int32_t variant;      /* launch shape of the fused kernel; -1 = automatic     */
     int32_t forcing;      /* SC_GUO or SC_EDM                                     */
@@ -116,7 +121,7 @@ typedef struct sc_lbm_params {
 
 /* Fills *p with the defaults: D2Q9 64x64, E4, G = -5, c0 = 1/3, exp psi with
  * psi0 = rho_psi = 1, tau = 1, SRT, Guo forcing, FP32 shifted, MRT rates 1.2,
- * rho_ref = 1, K = 100, automatic variant, EOS fields zero,
+ * rho_ref = SC_RHO_REF_AUTO, K = 100, automatic variant, EOS fields zero,
  * SC_INIT_EQUILIBRIUM. */
 void sc_lbm_default_params(sc_lbm_params* p);
 
@@ -197,7 +202,8 @@ int sc_lbm_force(sc_lbm* h, const double* psi_in, double* F_out);
 /* FP64 reductions of the current state (see sc_lbm_obs) and optional host
  * copies of its fields, each nullable: rho_out [N], u_out [D][N] doubles,
  * f_out the raw state buffer (sc_lbm_state_bytes bytes: post-collision,
- * shifted by w_b rho_ref, [Q][N] in the library's velocity order).
+ * shifted by w_b sc_lbm_rho_ref(h), [Q][N] in the library's velocity
+ * order).
  * Synchronous. */
 int sc_lbm_observe(sc_lbm* h, sc_lbm_obs* obs, double* rho_out, double* u_out, void* f_out);
 
@@ -230,6 +236,10 @@ void* sc_lbm_state_ptr(sc_lbm* h);
 /* The hipStream_t the handle enqueues on (the caller's, or its own). */
 void* sc_lbm_stream(sc_lbm* h);
 
+/* The storage shift rho_ref the handle uses (the one given, or the one
+ * SC_RHO_REF_AUTO picked at creation); NaN on a NULL handle. */
+double sc_lbm_rho_ref(const sc_lbm* h);
+
 /* Time every launch shape of the fused step on *p's lattice, order,
  * precision, collision, forcing and grid (state rho = 1) the way
  * sc_lbm_step runs it: one warm-up graph of 32 steps, then the best of three
@@ -259,7 +269,8 @@ const char* sc_lbm_strerror(int code);
 /* Many independent D2Q9 SRT droplets (the droplet test of Sec. 3 repeated
  * over a parameter sweep) advanced by ONE kernel launch per step over a
  * (item, tile) work list.  Items may differ in nx, ny, stencil order, G, c0
- * and tau; they must share precision, psi parameters and rho_ref.  Each
+ * and tau; they must share precision, psi parameters and rho_ref (with
+ * SC_RHO_REF_AUTO, one median over all items' initial densities).  Each
  * item keeps its own state (two buffers carved from one allocation).
  * Converged or diverged items leave the work list; the others continue. */
 typedef struct sc_lbm_batch sc_lbm_batch;
@@ -291,6 +302,9 @@ int sc_lbm_batch_status(sc_lbm_batch* b, int32_t item, int64_t* steps, int32_t* 
 
 /* Number of items still in the work list. */
 int32_t sc_lbm_batch_active(sc_lbm_batch* b);
+
+/* The storage shift rho_ref every item uses; NaN on a NULL batch. */
+double sc_lbm_batch_rho_ref(const sc_lbm_batch* b);
 
 void sc_lbm_batch_destroy(sc_lbm_batch* b);
 

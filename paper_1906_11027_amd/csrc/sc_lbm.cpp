@@ -152,7 +152,7 @@ extern "C" void sc_lbm_default_params(sc_lbm_params* p)
     p->precision = SC_FP32_SHIFTED;
     p->s_bulk = 1.2;
     p->s_ghost = 1.2;
-    p->rho_ref = 1.0;
+    p->rho_ref = SC_RHO_REF_AUTO;
     p->obs_every = 100;
     p->variant = -1;
 }
@@ -356,7 +356,10 @@ static int auto_variant(const sc_lbm_params& p, int64_t n)
     if (tuned >= 0) return tuned;
     switch (family_of(p)) {
     case kFamD2Q9: return n < (int64_t)1 << 20 ? 2 : 0;   // tile32x8r1 / tile64x16r4
-    case kFamD3Q19: return 7;                              // march64x8r1h16pf1
+    // march64x8r1h16pf1; in FP64 its 512-thread blocks leave 256 registers
+    // a lane and the E6/E8 MRT step spills, so FP64 takes the 256-thread
+    // march32x16h16, which keeps its window in registers
+    case kFamD3Q19: return p.precision == SC_FP64 ? 0 : 7;
     default: return n < (int64_t)1 << 20 ? 1 : 4;          // wide32x8r1 / wide128x16r2
     }
 }
@@ -388,6 +391,32 @@ static void release(sc_lbm* h)
 static int ensure_obs(sc_lbm* h);
 static const void* args_ptr(sc_lbm* h);
 
+// Appends about `budget` evenly strided finite densities of one initial
+// field (all of them when it is smaller; rho = 1 everywhere for a NULL field).
+static void sample_density(const double* rho, int64_t n, int64_t budget, std::vector<double>& out)
+{
+    const int64_t stride = std::max<int64_t>(1, n / std::max<int64_t>(1, budget));
+    for (int64_t i = 0; i < n; i += stride) {
+        const double r = rho ? rho[i] : 1.0;
+        if (std::isfinite(r)) out.push_back(r);  // sc_lbm_create rejects the field
+    }
+}
+
+// The shift SC_RHO_REF_AUTO picks: the median of the sampled densities.  A
+// state stored as f - w rho_ref is rounded relative to |rho - rho_ref|, so
+// centring it on the density most nodes hold (the surrounding phase of a
+// droplet or a bubble) keeps their rounding, and the velocity noise it feeds,
+// smallest.
+static double median_density(std::vector<double>& v)
+{
+    if (v.empty()) return 1.0;
+    const size_t mid = v.size() / 2;
+    std::nth_element(v.begin(), v.begin() + mid, v.end());
+    return std::max(0.0, v[mid]);
+}
+
+constexpr int64_t kShiftSamples = (int64_t)1 << 20;
+
 extern "C" int sc_lbm_create(const sc_lbm_params* p, const double* rho_init, void* dev_a, void* dev_b,
                              void* hip_stream, sc_lbm** out)
 {
@@ -410,6 +439,11 @@ extern "C" int sc_lbm_create(const sc_lbm_params* p, const double* rho_init, voi
                 delete h;
                 return SC_E_INVAL;
             }
+    }
+    if (h->p.rho_ref < 0.0) {
+        std::vector<double> smp;
+        sample_density(rho_init, h->n, kShiftSamples, smp);
+        h->p.rho_ref = median_density(smp);
     }
     int ndev = 0;
     hipError_t de = hipGetDeviceCount(&ndev);
@@ -463,7 +497,7 @@ extern "C" int sc_lbm_create(const sc_lbm_params* p, const double* rho_init, voi
     e = hipMemcpyAsync(rho_d, src, sizeof(double) * h->n, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) {
         where = "init kernel";
-        e = launch_init(p->lattice, h->f[0], p->precision, rho_d, p->nx, p->ny, p->nz, p->rho_ref, h->stream);
+        e = launch_init(p->lattice, h->f[0], p->precision, rho_d, p->nx, p->ny, p->nz, h->p.rho_ref, h->stream);
     }
     if (e == hipSuccess && p->init == SC_INIT_REST) {
         // F of psi(rho_init) from the equilibrium state just written, then
@@ -479,8 +513,8 @@ extern "C" int sc_lbm_create(const sc_lbm_params* p, const double* rho_init, voi
         e = launch_macro(p->lattice, p->precision, h->f[0], args_ptr(h), b, h->stream);
         if (e == hipSuccess) e = launch_force(h->dim, p->precision, p->order, args_ptr(h), b, false, h->stream);
         if (e == hipSuccess)
-            e = launch_init_rest(p->lattice, h->f[0], p->precision, rho_d, b.F, p->nx, p->ny, p->nz, p->rho_ref,
-                                 h->stream);
+            e = launch_init_rest(p->lattice, h->f[0], p->precision, rho_d, b.F, p->nx, p->ny, p->nz,
+                                 h->p.rho_ref, h->stream);
     }
     if (e == hipSuccess) {
         where = "hipStreamSynchronize(create)";
@@ -506,6 +540,8 @@ extern "C" void sc_lbm_destroy(sc_lbm* h)
 extern "C" void* sc_lbm_state_ptr(sc_lbm* h) { return h ? h->f[h->cur] : nullptr; }
 
 extern "C" void* sc_lbm_stream(sc_lbm* h) { return h ? (void*)h->stream : nullptr; }
+
+extern "C" double sc_lbm_rho_ref(const sc_lbm* h) { return h ? h->p.rho_ref : std::nan(""); }
 
 
 // single-step D2Q9 shape used for the odd step of a two-step shape
@@ -1033,6 +1069,15 @@ extern "C" int sc_lbm_batch_create(const sc_lbm_params* items, int32_t n, const 
             items[i].rho_ref != items[0].rho_ref)
             return SC_E_INVAL;
     }
+    std::vector<sc_lbm_params> its(items, items + n);
+    if (items[0].rho_ref < 0.0) {
+        std::vector<double> smp;
+        for (int i = 0; i < n; ++i)
+            sample_density(rho_init ? rho_init[i] : nullptr, (int64_t)items[i].nx * items[i].ny,
+                           std::max<int64_t>(1, kShiftSamples / n), smp);
+        const double shift = median_density(smp);
+        for (auto& it : its) it.rho_ref = shift;
+    }
     sc_lbm_batch* b = new (std::nothrow) sc_lbm_batch();
     if (!b) return SC_E_NOMEM;
     b->n = n;
@@ -1076,7 +1121,7 @@ extern "C" int sc_lbm_batch_create(const sc_lbm_params* items, int32_t n, const 
         char* base = (char*)b->pool + off[i];
         const size_t half = (sc_lbm_state_bytes(&items[i]) + 255) / 256 * 256;
         sc_lbm* h = nullptr;
-        int rc = sc_lbm_create(&items[i], rho_init ? rho_init[i] : nullptr, base, base + half, b->stream, &h);
+        int rc = sc_lbm_create(&its[i], rho_init ? rho_init[i] : nullptr, base, base + half, b->stream, &h);
         if (rc != SC_OK) {
             batch_release(b);
             return rc;
@@ -1174,6 +1219,11 @@ extern "C" int32_t sc_lbm_batch_active(sc_lbm_batch* b)
     int32_t k = 0;
     for (int v : b->active) k += v;
     return k;
+}
+
+extern "C" double sc_lbm_batch_rho_ref(const sc_lbm_batch* b)
+{
+    return (b && !b->items.empty()) ? b->items[0]->p.rho_ref : std::nan("");
 }
 
 extern "C" void sc_lbm_batch_destroy(sc_lbm_batch* b)

@@ -24,6 +24,7 @@ SC_GUO, SC_EDM = 0, 1
 SC_SRT, SC_MRT = 0, 1
 SC_FP32_SHIFTED, SC_FP64 = 0, 1
 SC_INIT_EQUILIBRIUM, SC_INIT_REST = 0, 1
+SC_RHO_REF_AUTO = -1.0
 
 LATTICE = {"D2Q9": SC_D2Q9, "D3Q19": SC_D3Q19, "D2Q13": SC_D2Q13, "D2Q25": SC_D2Q25}
 Q = {SC_D2Q9: 9, SC_D3Q19: 19, SC_D2Q13: 13, SC_D2Q25: 25}
@@ -67,9 +68,9 @@ EXPORTS = [
     "sc_lbm_force", "sc_lbm_observe", "sc_lbm_set_state", "sc_lbm_state_ptr",
     "sc_lbm_variant_name", "sc_lbm_num_variants", "sc_lbm_destroy", "sc_lbm_strerror", "sc_lbm_set_walls",
     "sc_lbm_steps_per_launch",
-    "sc_lbm_last_error_detail", "sc_lbm_stream",
+    "sc_lbm_last_error_detail", "sc_lbm_stream", "sc_lbm_rho_ref",
     "sc_lbm_batch_create", "sc_lbm_batch_step", "sc_lbm_batch_observe", "sc_lbm_batch_status",
-    "sc_lbm_batch_active", "sc_lbm_batch_destroy", "sc_lbm_autotune",
+    "sc_lbm_batch_active", "sc_lbm_batch_rho_ref", "sc_lbm_batch_destroy", "sc_lbm_autotune",
     "sc_nn_conv3x3_fwd", "sc_nn_conv3x3_bwd_data", "sc_nn_bwd_weight_scratch_floats",
     "sc_nn_conv3x3_bwd_weight", "sc_nn_tanh_fwd", "sc_nn_tanh_bwd", "sc_nn_mse", "sc_nn_adam",
     "sc_nn_to_bf16", "sc_nn_features", "sc_nn_start_field",
@@ -169,6 +170,10 @@ def lib():
         getattr(L, name).restype = ctypes.c_int
     L.sc_lbm_stream.argtypes = [vp]
     L.sc_lbm_stream.restype = vp
+    L.sc_lbm_rho_ref.argtypes = [vp]
+    L.sc_lbm_rho_ref.restype = ctypes.c_double
+    L.sc_lbm_batch_rho_ref.argtypes = [vp]
+    L.sc_lbm_batch_rho_ref.restype = ctypes.c_double
     L.sc_lbm_last_error_detail.argtypes = []
     L.sc_lbm_last_error_detail.restype = ctypes.c_char_p
     _lib = L
@@ -287,11 +292,12 @@ def sc_lbm_strerror(code):
 
 def make_params(lattice="D2Q9", shape=(64, 64), order=4, G=-5.0, c0=1.0 / 3.0, psi="exp",
                 psi0=1.0, rho_psi=1.0, tau=1.0, collision="srt", precision="fp32",
-                s_bulk=1.2, s_ghost=1.2, rho_ref=1.0, obs_every=100, variant=-1, forcing="guo", eos=None,
+                s_bulk=1.2, s_ghost=1.2, rho_ref="auto", obs_every=100, variant=-1, forcing="guo", eos=None,
                 init="equilibrium"):
     """eos: for psi == "pr", a dict with a, b, R, T (absolute) and alpha.
     init: "equilibrium" (f = feq(rho0, 0)) or "rest" (f = feq(rho0, -F/(2 rho0)):
-    the forced velocity is zero at t = 0)."""
+    the forced velocity is zero at t = 0).
+    rho_ref: the storage shift, or "auto" (the median initial density)."""
     p = sc_lbm_default_params()
     p.lattice = LATTICE[lattice]
     shape = tuple(int(s) for s in shape)
@@ -305,7 +311,8 @@ def make_params(lattice="D2Q9", shape=(64, 64), order=4, G=-5.0, c0=1.0 / 3.0, p
     p.G, p.c0, p.psi0, p.rho_psi, p.tau = G, c0, psi0, rho_psi, tau
     p.collision = {"srt": SC_SRT, "mrt": SC_MRT}[collision]
     p.precision = {"fp32": SC_FP32_SHIFTED, "fp64": SC_FP64}[precision]
-    p.s_bulk, p.s_ghost, p.rho_ref = s_bulk, s_ghost, rho_ref
+    p.s_bulk, p.s_ghost = s_bulk, s_ghost
+    p.rho_ref = SC_RHO_REF_AUTO if isinstance(rho_ref, str) and rho_ref == "auto" else float(rho_ref)
     p.obs_every, p.variant = obs_every, variant
     p.init = {"equilibrium": SC_INIT_EQUILIBRIUM, "rest": SC_INIT_REST}[init]
     return p
@@ -404,6 +411,11 @@ class Sim:
     def stream(self):
         """hipStream_t the library enqueues on (as an int)."""
         return lib().sc_lbm_stream(self.h)
+
+    @property
+    def rho_ref(self):
+        """The storage shift the state uses (state = f - w rho_ref)."""
+        return lib().sc_lbm_rho_ref(self.h)
 
     @property
     def variant(self):
@@ -521,3 +533,8 @@ class Batch:
     @property
     def active(self):
         return sc_lbm_batch_active(self.h)
+
+    @property
+    def rho_ref(self):
+        """The storage shift every item's state uses."""
+        return lib().sc_lbm_batch_rho_ref(self.h)

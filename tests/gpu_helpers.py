@@ -36,7 +36,7 @@ def pre_collision_from_state(sim, oracle_c):
     for b in range(len(c)):
         fb = flat[b * sim.n:(b + 1) * sim.n].reshape(shape[::-1]).transpose()
         fb = np.roll(fb, tuple(int(v) for v in c[b][:sim.dim]), axis=tuple(range(sim.dim)))
-        out[b] = fb + w[b] * sim.p.rho_ref
+        out[b] = fb + w[b] * sim.rho_ref
     order = []
     for co in oracle_c:
         key = tuple(int(v) for v in co[:sim.dim])

@@ -8,10 +8,10 @@ FP32 state density <= 1e-5 relative, velocity <= 1e-3 of max |u| plus the
 FP32 momentum resolution (1e-7 max rho).  At t = 0, where the oracle's
 velocity is zero, the GPU's is bounded by the resolution of the first
 moment of the stored state divided by the density: the shifted values
-g_b = f_b - w_b are at most w_b max(1, |rho - 1|) in size and each is
-rounded to u_r = 2^-24 (2^-53 for the FP64 state) of it, so
-|u| <= u_r sum_b |c_b| w_b max(1, |rho - 1|) / min rho, taken with a
-factor 4 for the sums (about 1e-6 here in FP32)."""
+g_b = f_b - w_b rho_ref are at most w_b max(1, |rho - rho_ref|) in size
+and each is rounded to u_r = 2^-24 (2^-53 for the FP64 state) of it, so
+|u| <= u_r sum_b |c_b| w_b max(1, |rho - rho_ref|) / min rho, taken with
+a factor 4 for the sums (about 1e-6 here in FP32)."""
 import warnings
 
 import numpy as np
@@ -69,7 +69,7 @@ def test_rest_start_parity(lattice, shape, kw, prec):
     u0 = float(np.max(np.abs(got["u"])))
     _, c, w, _ = O.lattice_table(lattice)
     cw = float((np.sqrt((c * c).sum(axis=1)) * w).sum())
-    big = max(1.0, float(np.max(np.abs(rho0 - 1.0))))
+    big = max(1.0, float(np.max(np.abs(rho0 - sim.rho_ref))))
     unit = 2.0 ** -24 if prec == "fp32" else 2.0 ** -53
     floor = 4 * unit * cw * big / float(np.min(rho0))
     say("%s %s t=0: rho rel err %.3e, max|u| %.3e (bound %.3e)" % (lattice, prec, er, u0, floor))

@@ -392,7 +392,8 @@ def test_batch_matches_oracle_and_single(prec):
         say("batch item %d %s: rho %.2e u %.2e" % (k, it["rho0"].shape, er, eu))
         tr, tu = TOL[prec]
         assert er <= tr and eu <= tu, (k, er, eu)
-        single = Sim(it["rho0"], "D2Q9", order=it["order"], G=it["G"], tau=it["tau"], precision=prec)
+        single = Sim(it["rho0"], "D2Q9", order=it["order"], G=it["G"], tau=it["tau"], precision=prec,
+                     rho_ref=bt.rho_ref)
         single.step(60)
         sg = single.observe()
         assert np.max(np.abs(sg["rho"] - got["rho"])) <= (1e-6 if prec == "fp32" else 1e-13)
@@ -414,7 +415,8 @@ def test_batch_convergence_and_quarantine():
     assert st[0][1] in (1, 2) and st[1][1] in (1, 2)
     assert st[2][1] == -1
     # retired items keep their state: a converged item matches a single run
-    single = Sim(items[0]["rho0"], "D2Q9", order=4)
+    # with the batch's storage shift
+    single = Sim(items[0]["rho0"], "D2Q9", order=4, rho_ref=bt.rho_ref)
     single.step(st[0][0])
     a = single.observe()["rho"]
     b = bt.observe(0)["rho"]
