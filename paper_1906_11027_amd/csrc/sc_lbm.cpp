@@ -360,7 +360,11 @@ static int auto_variant(const sc_lbm_params& p, int64_t n)
     // a lane and the E6/E8 MRT step spills, so FP64 takes the 256-thread
     // march32x16h16, which keeps its window in registers
     case kFamD3Q19: return p.precision == SC_FP64 ? 0 : 7;
-    default: return n < (int64_t)1 << 20 ? 1 : 4;          // wide32x8r1 / wide128x16r2
+    default:
+        if (n < (int64_t)1 << 20) return 1;                    // wide32x8r1
+        // wide128x16r2; its 1024-thread blocks spill the FP64 D2Q25 step, which
+        // takes wide64x8r2 (512 threads)
+        return (p.precision == SC_FP64 && p.lattice == SC_D2Q25) ? 0 : 4;
     }
 }
 
