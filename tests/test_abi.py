@@ -2,6 +2,7 @@
 include/sc_lbm.h declares, and rejects invalid parameter sets before any
 device call.  No kernel is launched here."""
 import ctypes
+import math
 import os
 import re
 import subprocess
@@ -58,6 +59,7 @@ def test_defaults():
     assert p.G == -5.0 and abs(p.c0 - 1 / 3) < 1e-16 and p.tau == 1.0
     assert p.variant == -1 and p.obs_every == 100
     assert p.init == B.SC_INIT_EQUILIBRIUM and p.forcing == B.SC_GUO
+    assert p.rho_ref == B.SC_RHO_REF_AUTO
     assert B.sc_lbm_state_bytes(p) == 9 * 64 * 64 * 4
     p.precision = B.SC_FP64
     assert B.sc_lbm_state_bytes(p) == 9 * 64 * 64 * 8
@@ -76,6 +78,8 @@ def test_defaults():
     ("variant", 99, B.SC_E_INVAL),
     ("G", float("inf"), B.SC_E_INVAL),
     ("init", 2, B.SC_E_INVAL),
+    ("rho_ref", float("inf"), B.SC_E_INVAL),
+    ("rho_ref", float("nan"), B.SC_E_INVAL),
 ])
 def test_invalid_parameters_rejected(field, value, code):
     p = B.sc_lbm_default_params()
@@ -84,6 +88,19 @@ def test_invalid_parameters_rejected(field, value, code):
     h = ctypes.c_void_p()
     assert B.lib().sc_lbm_create(ctypes.byref(p), None, None, None, None, ctypes.byref(h)) == code
     assert h.value is None
+
+
+def test_shift_accessors_on_null_handles():
+    L = B.lib()
+    assert math.isnan(L.sc_lbm_rho_ref(None)) and math.isnan(L.sc_lbm_batch_rho_ref(None))
+
+
+def test_make_params_shift():
+    assert B.make_params().rho_ref == B.SC_RHO_REF_AUTO
+    assert B.make_params(rho_ref=0.25).rho_ref == 0.25
+    # any negative shift asks for the automatic one and is a valid problem
+    p = B.make_params(rho_ref=-3.0)
+    assert B.sc_lbm_state_bytes(p) == 9 * 64 * 64 * 4
 
 
 def test_3d_order_10_unsupported():
