@@ -288,6 +288,19 @@ def cpu_baseline(name, target_s=15.0):
             "sample": "%d steps of the %s workload (FP64 oracle, OpenMP over rows)" % (k, name)}
 
 
+def cpu_one_core(name, target_s=8.0):
+    """The same oracle timing with one OpenMP thread, in a child process (the
+    thread count is fixed when the oracle library loads)."""
+    import subprocess
+    code = "import json, bench; print(json.dumps(bench.cpu_baseline(%r, %r)))" % (name, target_s)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], cwd=os.path.dirname(os.path.abspath(__file__)), env=env,
+                       capture_output=True, text=True, timeout=300)
+    if r.returncode != 0:
+        return {"error": r.stderr.strip().splitlines()[-1] if r.stderr.strip() else "rc %d" % r.returncode}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -304,6 +317,12 @@ def main():
               "(a domain would shard into slabs along its slowest axis with a halo exchange per step; "
               "not built)", file=sys.stderr)
         sys.exit(2)
+
+    # before the GPU is touched: the one-core oracle timing runs in a child
+    one_core = None
+    if not args.no_cpu:
+        one_core = cpu_one_core(args.workload)
+        log("cpu one core:", json.dumps(one_core))
 
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -369,7 +388,7 @@ def main():
                      "kernel_ms_mean": main_r["launch_ms"],
                      "bytes_per_launch": main_r["bytes_per_launch"]},
         "cpu_baseline": cpu,
-        "extra": extra,
+        "extra": dict(extra, cpu_oracle_one_core=one_core) if one_core else extra,
     }
     print(json.dumps(line), flush=True)
 

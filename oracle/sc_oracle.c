@@ -305,7 +305,8 @@ static void force_from_psi(const orc_sim *s, const double *psi, double *F)
 {
     const long n = s->n;
     const int nx = s->p.nx, ny = s->p.ny, nz = s->p.nz;
-#pragma omp parallel for schedule(static)
+    /* threads take whole rows (z, y); every node's sum is the same either way */
+#pragma omp parallel for collapse(2) schedule(static)
     for (long z = 0; z < nz; ++z)
         for (long y = 0; y < ny; ++y)
             for (long x = 0; x < nx; ++x) {
@@ -510,7 +511,7 @@ void orc_step(orc_sim *s, long nsteps)
     const int nx = s->p.nx, ny = s->p.ny, nz = s->p.nz;
     for (long t = 0; t < nsteps; ++t) {
         macro(s);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for collapse(2) schedule(static)
         for (long z = 0; z < nz; ++z)
             for (long y = 0; y < ny; ++y)
                 for (long x = 0; x < nx; ++x) {
