@@ -7,10 +7,10 @@ velocity along the row and the column through the droplet centre.  Orders
 already in the file are kept, so the orders can be run at different
 lengths.
 
-Only the oracle computes these values.  The stored file came from (about
-50 min on 8 cores):
-    python tests/golden/make_droplet_256_orders.py --orders 8 --steps 50000
-    python tests/golden/make_droplet_256_orders.py --orders 4,6,10 --steps 10000
+Only the oracle computes these values.  The stored file came from
+    python tests/golden/make_droplet_256_orders.py --orders 8
+    python tests/golden/make_droplet_256_orders.py --orders 4,6,10
+(50,000 steps each; about 4-8 min per order on 8 cores).
 """
 import argparse
 import json
