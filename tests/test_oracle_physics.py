@@ -103,3 +103,23 @@ def test_laplace_law():
     assert r2 > 0.999
     assert coef[0] > 0
     assert abs(coef[1]) < 0.1 * dps.min()
+
+
+def test_spurious_currents_fall_modestly_with_force_isotropy():
+    """Sec. 2: raising the isotropy order of the force stencil alone (Shan's
+    remedy) lowers the spurious currents, but only partly, because the
+    velocity set's own tensors stay at their order.  The oracle's 256^2
+    droplet (tests/golden/droplet_256_orders_oracle.json, 50,000 steps) shows
+    both: max|u| falls with every order E4 -> E6 -> E8 -> E10, yet E10 keeps
+    more than a tenth of the E4 value; the Laplace jump stays within a
+    factor 2 across the orders (the bulk state changes little)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "droplet_256_orders_oracle.json")
+    with open(path) as fh:
+        g = json.load(fh)["orders"]
+    umax = [g[o]["traj"][-1]["max_u"] for o in ("4", "6", "8", "10")]
+    dp = [g[o]["traj"][-1]["dp"] for o in ("4", "6", "8", "10")]
+    assert all(a > b for a, b in zip(umax, umax[1:])), umax
+    assert umax[-1] > 0.1 * umax[0], umax
+    assert max(dp) < 2.0 * min(dp), dp
