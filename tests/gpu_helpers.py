@@ -51,3 +51,24 @@ def rel_err(a, b):
 def say(*args):
     print(*args, flush=True)
     sys.stdout.flush()
+
+
+def pre_collision_patch(state, sim, lo, size, oracle_c):
+    """pre_collision_from_state restricted to the box [lo, lo + size) of the
+    (periodic) grid, from a state array already copied to the host: f_b(x, t)
+    = state_b(x - c_b) + w_b rho_ref in float64, oracle velocity order,
+    indexed [q][x, y(, z)] over the box."""
+    c = lib_velocities(sim)
+    w = lib_weights(sim.lattice)
+    shape, dim = sim.shape, sim.dim
+    planes = state.reshape((len(c),) + tuple(shape[::-1]))    # [q][(z,) y, x]
+    out = np.zeros((len(c),) + tuple(size))
+    for b in range(len(c)):
+        src = [(np.arange(lo[d], lo[d] + size[d]) - int(c[b][d])) % shape[d] for d in range(dim)]
+        blk = planes[b][np.ix_(*src[::-1])]                    # [(z,) y, x] of the box
+        out[b] = blk.transpose().astype(np.float64) + w[b] * sim.rho_ref
+    order = []
+    for co in oracle_c:
+        key = tuple(int(v) for v in co[:dim])
+        order.append([tuple(int(v) for v in cc[:dim]) for cc in c].index(key))
+    return out[order]
