@@ -103,6 +103,21 @@ def test_make_params_shift():
     assert B.sc_lbm_state_bytes(p) == 9 * 64 * 64 * 4
 
 
+def test_largest_velocity_plane():
+    # one velocity plane must stay below 4 GiB (32-bit byte offsets)
+    p = B.sc_lbm_default_params()
+    p.nx, p.ny = 65536, 16383
+    assert B.sc_lbm_state_bytes(p) == 9 * 65536 * 16383 * 4
+    p.ny = 16384
+    assert B.sc_lbm_state_bytes(p) == 0
+    h = ctypes.c_void_p()
+    assert B.lib().sc_lbm_create(ctypes.byref(p), None, None, None, None, ctypes.byref(h)) == B.SC_E_UNSUPPORTED
+    p.precision, p.ny = B.SC_FP64, 8191
+    assert B.sc_lbm_state_bytes(p) == 9 * 65536 * 8191 * 8
+    p.ny = 8192
+    assert B.sc_lbm_state_bytes(p) == 0
+
+
 def test_3d_order_10_unsupported():
     p = B.sc_lbm_default_params()
     p.lattice, p.nz, p.order = B.SC_D3Q19, 8, 10
