@@ -40,6 +40,8 @@ def droplet(shape=(256, 256), R=40, seed=2):
 
 def run_one(rho0, order, precision, steps, every, G=-5.0, tau=1.0, rho_ref="auto", lattice="D2Q9", **kw):
     import torch
+    if every < 1 or steps % every:
+        raise ValueError("steps (%d) must be a multiple of every (%d)" % (steps, every))
     sim = Sim(rho0, lattice, order=order, G=G, tau=tau, precision=precision, obs_every=every, rho_ref=rho_ref,
               **kw)
     shift = sim.rho_ref
