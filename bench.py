@@ -60,6 +60,12 @@ WORKLOADS = {
                                  pr=0.85, forcing="edm", tau=19.0 / 24.0,
                                  desc="D2Q25 SRT 8192^2, E8, P-R psi T/Tc=0.85, EDM, tau=19/24, droplet "
                                       "R=1600, FP32"),
+    # the FP64 state at the HBM-bound sizes (same droplets)
+    "d2q9_e8_8192_fp64": dict(lattice="D2Q9", shape=(8192, 8192), order=8, R=1600, seed=7, collision="srt",
+                              precision="fp64", desc="D2Q9 SRT 8192^2, E8, droplet R=1600, FP64 state"),
+    "d3q19_mrt_e8_320_fp64": dict(lattice="D3Q19", shape=(320, 320, 320), order=8, R=64, seed=8,
+                                  collision="mrt", precision="fp64",
+                                  desc="D3Q19 MRT 320^3, E8, droplet R=64, FP64 state"),
 }
 Q_OF = {"D2Q9": 9, "D3Q19": 19, "D2Q13": 13, "D2Q25": 25}
 
@@ -107,8 +113,9 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def bytes_per_node(lattice):
-    return 2 * Q_OF[lattice] * 4   # read Q + write Q FP32 values (algorithmic traffic)
+def bytes_per_node(lattice, precision="fp32"):
+    # read Q + write Q values of the state (algorithmic traffic)
+    return 2 * Q_OF[lattice] * (8 if precision == "fp64" else 4)
 
 
 def sim_kwargs(w):
@@ -141,10 +148,12 @@ def measure(name, steps, warmup, kernel_launches=50):
     nodes = 1
     for d in w["shape"]:
         nodes *= int(d)
-    tuned = B.sc_lbm_autotune(B.make_params(w["lattice"], w["shape"], **kw), steps=256 if nodes < 1 << 20 else 32)
+    prec = w.get("precision", "fp32")
+    tuned = B.sc_lbm_autotune(B.make_params(w["lattice"], w["shape"], precision=prec, **kw),
+                              steps=256 if nodes < 1 << 20 else 32)
     log("autotune %s: variant %d, %.4f ms/step" % (name, tuned[0], tuned[1]))
     stream = torch.cuda.Stream()
-    sim = Sim(rho0, w["lattice"], precision="fp32", stream=stream, **kw)
+    sim = Sim(rho0, w["lattice"], precision=prec, stream=stream, **kw)
     assert sim.stream == stream.cuda_stream, "library is not on the timed stream"
     n = rho0.size
     del rho0
@@ -180,7 +189,7 @@ def measure(name, steps, warmup, kernel_launches=50):
     sim.close()
     ok = ob["nonfinite"] == 0 and ob["mass"] > 0
     mlups = n * steps / (ms * 1e-3) / 1e6
-    bpn = bytes_per_node(w["lattice"])
+    bpn = bytes_per_node(w["lattice"], prec)
     # one fused launch per step: its average duration is the graph-timed
     # per-step time (an upper bound: it includes the gap between launches)
     achieved = bpn * n / (ms / steps * 1e-3) / 1e9
@@ -288,6 +297,18 @@ def cpu_baseline(name, target_s=15.0):
             "sample": "%d steps of the %s workload (FP64 oracle, OpenMP over rows)" % (k, name)}
 
 
+def kernel_label(w, r):
+    """The fused step kernel a workload's tuned shape runs."""
+    t = "double" if w.get("precision") == "fp64" else "float"
+    if w["lattice"] == "D2Q9":
+        k = "k_d2q9_tile2" if r["steps_per_launch"] == 2 else "k_d2q9_tile"
+        return "%s<%s, %d, ...> (%s)" % (k, t, w["order"], r["variant"])
+    if w["lattice"] == "D3Q19":
+        return "k_d3q19_march<%s, %d, %s, ...> (%s)" % (t, w["order"], str(w["collision"] == "mrt").lower(),
+                                                        r["variant"])
+    return "k_wide_tile<%s, %s, %d, ...> (%s)" % (t, w["lattice"], w["order"], r["variant"])
+
+
 def cpu_one_core(name, target_s=8.0):
     """The same oracle timing with one OpenMP thread, in a child process (the
     thread count is fixed when the oracle library loads)."""
@@ -340,7 +361,8 @@ def main():
     extra = {}
     if not args.no_extra:
         for name, st in (("d3q19_mrt_e8_128", 200), ("d2q9_e8_8192", 100), ("d3q19_mrt_e8_320", 40),
-                         ("d2q13_e6_pr_edm_8192", 40), ("d2q25_e8_pr_edm_8192", 30)):
+                         ("d2q13_e6_pr_edm_8192", 40), ("d2q25_e8_pr_edm_8192", 30),
+                         ("d2q9_e8_8192_fp64", 40), ("d3q19_mrt_e8_320_fp64", 20)):
             if name == args.workload:
                 continue
             r = measure(name, st, 10, kernel_launches=10)
@@ -374,7 +396,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp32",
+        "dtype": w.get("precision", "fp32"),
         "data": "synthetic",
         "config": {"workload": w["desc"], "nodes": main_r["nodes"], "lattice": w["lattice"],
                    "grid": list(w["shape"]), "stencil_order": w["order"], "variant": main_r["variant"]},
@@ -382,8 +404,7 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(main_r["frac"], 4),
                      "traffic": main_r["traffic_bytes"],
                      "traffic_ratio": main_r["traffic_ratio"],
-                     "kernel": "%s<float, %d, ...> (%s)" % ("k_d2q9_tile2" if main_r["steps_per_launch"] == 2
-                                                             else "k_d2q9_tile", w["order"], main_r["variant"]),
+                     "kernel": kernel_label(w, main_r),
                      "steps_per_launch": main_r["steps_per_launch"],
                      "kernel_ms_mean": main_r["launch_ms"],
                      "bytes_per_launch": main_r["bytes_per_launch"]},
