@@ -445,9 +445,14 @@ extern "C" int sc_lbm_create(const sc_lbm_params* p, const double* rho_init, voi
             }
     }
     if (h->p.rho_ref < 0.0) {
-        std::vector<double> smp;
-        sample_density(rho_init, h->n, kShiftSamples, smp);
-        h->p.rho_ref = median_density(smp);
+        try {
+            std::vector<double> smp;
+            sample_density(rho_init, h->n, kShiftSamples, smp);
+            h->p.rho_ref = median_density(smp);
+        } catch (const std::bad_alloc&) {
+            delete h;
+            return SC_E_NOMEM;
+        }
     }
     int ndev = 0;
     hipError_t de = hipGetDeviceCount(&ndev);
@@ -494,7 +499,13 @@ extern "C" int sc_lbm_create(const sc_lbm_params* p, const double* rho_init, voi
     std::vector<double> ones;
     const double* src = rho_init;
     if (!src) {
-        ones.assign(h->n, 1.0);
+        try {
+            ones.assign(h->n, 1.0);
+        } catch (const std::bad_alloc&) {
+            hipFree(rho_d);
+            release(h);
+            return SC_E_NOMEM;
+        }
         src = ones.data();
     }
     const char* where = "hipMemcpyAsync(rho_init)";
@@ -1073,14 +1084,19 @@ extern "C" int sc_lbm_batch_create(const sc_lbm_params* items, int32_t n, const 
             items[i].rho_ref != items[0].rho_ref)
             return SC_E_INVAL;
     }
-    std::vector<sc_lbm_params> its(items, items + n);
-    if (items[0].rho_ref < 0.0) {
-        std::vector<double> smp;
-        for (int i = 0; i < n; ++i)
-            sample_density(rho_init ? rho_init[i] : nullptr, (int64_t)items[i].nx * items[i].ny,
-                           std::max<int64_t>(1, kShiftSamples / n), smp);
-        const double shift = median_density(smp);
-        for (auto& it : its) it.rho_ref = shift;
+    std::vector<sc_lbm_params> its;
+    try {
+        its.assign(items, items + n);
+        if (items[0].rho_ref < 0.0) {
+            std::vector<double> smp;
+            for (int i = 0; i < n; ++i)
+                sample_density(rho_init ? rho_init[i] : nullptr, (int64_t)items[i].nx * items[i].ny,
+                               std::max<int64_t>(1, kShiftSamples / n), smp);
+            const double shift = median_density(smp);
+            for (auto& it : its) it.rho_ref = shift;
+        }
+    } catch (const std::bad_alloc&) {
+        return SC_E_NOMEM;
     }
     sc_lbm_batch* b = new (std::nothrow) sc_lbm_batch();
     if (!b) return SC_E_NOMEM;
