@@ -227,26 +227,30 @@ def copy_ceiling(nbytes=1 << 30, reps=8):
     return {"bytes": 2 * nbytes, "ms": best, "gbs": 2 * nbytes / (best * 1e-3) / 1e9}
 
 
-def steady_droplet():
-    """The 64^2 E4 droplet (R = 16) run to steady state on the GPU."""
+def steady_droplet(shape=(64, 64), R=16, seed=1, order=4, precision="fp32", max_steps=400000):
+    """A droplet run to steady state on the GPU (default: the 64^2 E4 droplet,
+    R = 16)."""
     import torch
 
     from paper_1906_11027_amd import Sim
     from workload import droplet_rho
 
-    rho0 = droplet_rho((64, 64), 16, seed=1)
+    rho0 = droplet_rho(shape, R, seed=seed)
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim = Sim(rho0, "D2Q9", order=4, stream=stream, obs_every=100)
-    rc, done = sim.step(400000, tol=1e-10)
+    sim = Sim(rho0, "D2Q9", order=order, stream=stream, obs_every=100, precision=precision)
+    rc, done = sim.step(max_steps, tol=1e-10)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ob = sim.observe(fields=False)["obs"]
     sim.close()
-    return {"workload": "D2Q9 SRT 64x64 E4 droplet R=16, FP32, to max|u| change < 1e-10 "
-                        "(FP32: on 3 consecutive checks, or max|u| of 100 checks within the state's resolution)",
-            "steps": done, "wall_s": wall, "max_u": ob["max_u"], "dp": ob["dp"], "rc": rc}
+    rule = ("FP32: on 3 consecutive checks, or max|u| of 100 checks within the state's resolution"
+            if precision == "fp32" else "FP64: the literal rule")
+    return {"workload": "D2Q9 SRT %dx%d E%d droplet R=%d, %s, to max|u| change < 1e-10 per 100 steps (%s)"
+                        % (shape[0], shape[1], order, R, precision.upper(), rule),
+            "steps": done, "wall_s": wall, "max_u": ob["max_u"], "dp": ob["dp"], "rc": rc,
+            "converged_by": ob["converged_by"]}
 
 
 def batched_sweep(steps=200):
@@ -376,6 +380,11 @@ def main():
         sd = steady_droplet()
         log("steady:", json.dumps(sd))
         extra["steady_droplet"] = sd
+        # the headline droplet (256^2, E8, R = 40) to steady state, both states
+        for prec in ("fp32", "fp64"):
+            sd = steady_droplet((256, 256), 40, 2, 8, prec)
+            log("steady 256 %s:" % prec, json.dumps(sd))
+            extra["steady_droplet_256_e8_" + prec] = sd
         bs = batched_sweep()
         log("batch:", json.dumps(bs))
         extra["batched_sweep_64"] = bs
