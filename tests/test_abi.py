@@ -95,6 +95,15 @@ def test_shift_accessors_on_null_handles():
     assert math.isnan(L.sc_lbm_rho_ref(None)) and math.isnan(L.sc_lbm_batch_rho_ref(None))
 
 
+def test_batch_items_must_share_the_shift():
+    # checked before any device call
+    a = B.make_params("D2Q9", (16, 16))
+    b = B.make_params("D2Q9", (16, 16), rho_ref=1.0)
+    with pytest.raises(B.ScError) as ei:
+        B.sc_lbm_batch_create([a, b])
+    assert ei.value.code == B.SC_E_INVAL
+
+
 def test_make_params_shift():
     assert B.make_params().rho_ref == B.SC_RHO_REF_AUTO
     assert B.make_params(rho_ref=0.25).rho_ref == 0.25
