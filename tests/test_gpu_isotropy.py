@@ -87,7 +87,12 @@ def test_fp64_matches_oracle_run(order):
 def test_fp32_matches_oracle_run(order):
     g = GOLD["orders"][order]
     say("case droplet 256 E%s fp32, %d steps" % (order, g["steps"]))
-    sim = Sim(_rho0(), "D2Q9", order=int(order), G=GOLD["G"], tau=GOLD["tau"], obs_every=g["every"])
+    # one fixed launch shape (tile32x8r1, the small-grid default): an FP32 run's
+    # rounding, and so its far-field noise, depends on the shape, and an
+    # autotuning call earlier in the process may change the default; every
+    # shape's agreement with this one is checked in test_gpu_parity
+    sim = Sim(_rho0(), "D2Q9", order=int(order), G=GOLD["G"], tau=GOLD["tau"], obs_every=g["every"], variant=2)
+    assert sim.variant == "tile32x8r1"
     sim.step(g["steps"])
     out = sim.observe()
     ob, ref = out["obs"], g["traj"][-1]
