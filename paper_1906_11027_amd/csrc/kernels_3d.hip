@@ -188,6 +188,8 @@ static const Shape3D kShapes3D[] = {
     {64, 8, 1, 32, "march64x8r1h32pf1"},
     {64, 8, 2, 32, "march64x16h32"},
     {64, 8, 1, 64, "march64x8r1h64pf1"},
+    {32, 8, 1, 32, "march32x8r1h32pf1"},
+    {32, 8, 1, 64, "march32x8r1h64pf1"},
 };
 constexpr int kNumShapes3D = sizeof(kShapes3D) / sizeof(kShapes3D[0]);
 
@@ -221,6 +223,9 @@ static hipError_t launch_v(const StepArgs<T>& a, int variant, hipStream_t s)
     case 8: return launch_march<T, ORDER, MRT, 64, 8, 1, 1>(a, 32, s);
     case 9: return launch_march<T, ORDER, MRT, 64, 8, 2, 0>(a, 32, s);
     case 10: return launch_march<T, ORDER, MRT, 64, 8, 1, 1>(a, 64, s);
+    // 256 threads with the prefetch window: room for the FP64 window without spills
+    case 11: return launch_march<T, ORDER, MRT, 32, 8, 1, 1>(a, 32, s);
+    case 12: return launch_march<T, ORDER, MRT, 32, 8, 1, 1>(a, 64, s);
     default: return hipErrorInvalidValue;
     }
 }
