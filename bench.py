@@ -76,6 +76,18 @@ Q_OF = {"D2Q9": 9, "D3Q19": 19, "D2Q13": 13, "D2Q25": 25}
 # summary under profiles/).  Keyed by workload and launch shape; a shape
 # without an entry reports traffic null.  Re-measure after a kernel change.
 TRAFFIC_RATIO = {
+    ("d2q9_e8_8192_fp64", "tile2x16x16"): (0.626, 0.500),
+    ("d2q9_e8_8192_fp64", "tile2x32x8"): (0.564, 0.500),
+    ("d2q9_e8_8192_fp64", "tile2x32x8t512"): (0.564, 0.500),
+    ("d2q9_e8_8192_fp64", "tile2x32x8t1024"): (0.564, 0.500),
+    ("d2q9_e8_8192_fp64", "tile2x32x16"): (0.564, 0.500),
+    ("d2q9_e8_8192_fp64", "tile2x32x32"): (0.564, 0.500),
+    ("d2q9_e8_8192_fp64", "tile2x64x8"): (0.532, 0.500),
+    ("d2q9_e8_8192_fp64", "tile2x64x16"): (0.534, 0.500),
+    ("d3q19_mrt_e8_320_fp64", "march32x16h16"): (1.620, 1.000),
+    ("d3q19_mrt_e8_320_fp64", "march32x16h32"): (1.460, 1.000),
+    ("d3q19_mrt_e8_320_fp64", "march32x8r1h32pf1"): (1.566, 1.000),
+    ("d3q19_mrt_e8_320_fp64", "march32x8r1h64pf1"): (1.502, 1.000),
     ("d2q13_e6_pr_edm_8192", "wide128x16r2"): (1.394, 1.000),
     ("d2q13_e6_pr_edm_8192", "wide256x8r2"): (1.387, 1.000),
     ("d2q25_e8_pr_edm_8192", "wide128x16r2"): (1.443, 1.000),
