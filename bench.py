@@ -76,6 +76,10 @@ Q_OF = {"D2Q9": 9, "D3Q19": 19, "D2Q13": 13, "D2Q25": 25}
 # summary under profiles/).  Keyed by workload and launch shape; a shape
 # without an entry reports traffic null.  Re-measure after a kernel change.
 TRAFFIC_RATIO = {
+    ("d3q19_mrt_e8_128", "march64x8r1h16pf1"): (1.253, 1.000),
+    ("d3q19_mrt_e8_128", "march64x8r1h32pf1"): (1.198, 1.000),
+    ("d3q19_mrt_e8_128", "march64x8r1h64pf1"): (1.198, 1.000),
+    ("d3q19_mrt_e8_128", "march64x8r1h16"): (1.253, 1.000),
     ("d2q9_e8_8192_fp64", "tile2x16x16"): (0.626, 0.500),
     ("d2q9_e8_8192_fp64", "tile2x32x8"): (0.564, 0.500),
     ("d2q9_e8_8192_fp64", "tile2x32x8t512"): (0.564, 0.500),
