@@ -211,17 +211,36 @@ __device__ __forceinline__ T sum19(const T (&g)[19])
 // The conserved moments drop out because m.(n + phihat/2) = 0 for rho and j.
 // This equals M^-1 S M with the rates grouped as conserved / bulk / shear /
 // ghost; with all rates 1/tau it is exactly the BGK step.
+// velocities b and b + 1 (b odd) are opposite: the collision below pairs them
+constexpr bool d3q19_opposite_pairs()
+{
+    for (int b = 1; b < 19; b += 2)
+        if (D3Q19::cx[b + 1] != -D3Q19::cx[b] || D3Q19::cy[b + 1] != -D3Q19::cy[b] ||
+            D3Q19::cz[b + 1] != -D3Q19::cz[b] || D3Q19::w[b + 1] != D3Q19::w[b])
+            return false;
+    return true;
+}
+static_assert(d3q19_opposite_pairs(), "D3Q19 velocity order must list opposite pairs");
+
 template <typename T, bool MRT>
 __device__ __forceinline__ void collide_d3q19(T (&g)[19], T drho, T Fx, T Fy, T Fz, const StepArgs<T>& a)
 {
+    // The moving velocities come in pairs (b, b + 1), b odd, with
+    // c_{b+1} = -c_b.  Over a pair, feq and phihat split into a part even in
+    // c (the same for both) and a part odd in c (opposite signs):
+    //   feq   = w [drho + rho (4.5 (c.u)^2 - 1.5 u^2)]  +-  3 w rho (c.u)
+    //   phihat = w [9 (c.u)(c.F) - 3 u.F]                +-  3 w (c.F)
+    // and every moment vector above is even in c, so the moments need only
+    // the pair sums.  Each pair's c.u and c.F are formed once.
     using L = D3Q19;
     const T rho = a.rho_ref + drho;
     T jx = T(0), jy = T(0), jz = T(0);
 #pragma unroll
-    for (int b = 1; b < 19; ++b) {
-        if (L::cx[b] > 0) jx += g[b]; else if (L::cx[b] < 0) jx -= g[b];
-        if (L::cy[b] > 0) jy += g[b]; else if (L::cy[b] < 0) jy -= g[b];
-        if (L::cz[b] > 0) jz += g[b]; else if (L::cz[b] < 0) jz -= g[b];
+    for (int b = 1; b < 19; b += 2) {
+        const T d = g[b] - g[b + 1];
+        if (L::cx[b] > 0) jx += d; else if (L::cx[b] < 0) jx -= d;
+        if (L::cy[b] > 0) jy += d; else if (L::cy[b] < 0) jy -= d;
+        if (L::cz[b] > 0) jz += d; else if (L::cz[b] < 0) jz -= d;
     }
     const T inv = fast_rcp(rho);
     const T ux = (jx + T(0.5) * Fx) * inv;
@@ -235,52 +254,63 @@ __device__ __forceinline__ void collide_d3q19(T (&g)[19], T drho, T Fx, T Fy, T 
     if (!MRT) {
         const T om = a.omega, gu = a.guo;
 #pragma unroll
-        for (int b = 1; b < 19; ++b) {
+        for (int b = 1; b < 19; b += 2) {
             const T cu = T(L::cx[b]) * ux + T(L::cy[b]) * uy + T(L::cz[b]) * uz;
             const T cF = T(L::cx[b]) * Fx + T(L::cy[b]) * Fy + T(L::cz[b]) * Fz;
             const T w = T(L::w[b]);
-            const T geq = w * (drho + rho * (T(3) * cu + T(4.5) * cu * cu - usq));
-            const T phi = gu * w * (T(3) * (cF - uF) + T(9) * cu * cF);
-            const T gn = g[b] - om * (g[b] - geq) + phi;
-            dm += g[b] - gn;
-            g[b] = gn;
+            const T es = w * (drho + rho * (T(4.5) * cu * cu - usq));
+            const T ea = w * rho * (T(3) * cu);
+            const T ps = gu * w * (T(9) * cu * cF - T(3) * uF);
+            const T pa = gu * w * (T(3) * cF);
+            const T gp = g[b], gm = g[b + 1];
+            const T np = gp - om * (gp - (es + ea)) + (ps + pa);
+            const T nm = gm - om * (gm - (es - ea)) + (ps - pa);
+            dm += (gp - np) + (gm - nm);
+            g[b] = np;
+            g[b + 1] = nm;
         }
         g[0] += dm;
     } else {
         const T sg = a.s_ghost;
         const T gh = T(1) - T(0.5) * sg;
-        T v[19];
-        T mb = T(0), m1 = T(0), m2 = T(0), m3 = T(0), m4 = T(0), m5 = T(0);
+        // the rest population enters only the bulk moment (19 c^2 - 30 = -30)
+        const T w0 = T(L::w[0]);
+        const T v0 = (g[0] - w0 * (drho - rho * usq)) + T(0.5) * (w0 * (T(-3) * uF));
+        T mb = T(-30) * v0, m1 = T(0), m2 = T(0), m3 = T(0), m4 = T(0), m5 = T(0);
 #pragma unroll
-        for (int b = 0; b < 19; ++b) {
+        for (int b = 1; b < 19; b += 2) {
             const int cx = L::cx[b], cy = L::cy[b], cz = L::cz[b];
             const T cu = T(cx) * ux + T(cy) * uy + T(cz) * uz;
             const T cF = T(cx) * Fx + T(cy) * Fy + T(cz) * Fz;
             const T w = T(L::w[b]);
-            const T geq = w * (drho + rho * (T(3) * cu + T(4.5) * cu * cu - usq));
-            const T ph = w * (T(3) * (cF - uF) + T(9) * cu * cF);   // phihat
-            const T ne = g[b] - geq;
-            v[b] = ne + T(0.5) * ph;
-            if (b) {   // the rest population is closed below
-                const T gn = g[b] - sg * ne + gh * ph;
-                dm += g[b] - gn;
-                g[b] = gn;
-            }
+            const T es = w * (drho + rho * (T(4.5) * cu * cu - usq));
+            const T ea = w * rho * (T(3) * cu);
+            const T ps = w * (T(9) * cu * cF - T(3) * uF);
+            const T pa = w * (T(3) * cF);
+            const T gp = g[b], gm = g[b + 1];
+            const T nep = gp - (es + ea), nem = gm - (es - ea);
+            const T php = ps + pa, phm = ps - pa;
+            const T vs = (nep + T(0.5) * php) + (nem + T(0.5) * phm);   // v_b + v_{b+1}
+            const T gnp = gp - sg * nep + gh * php;
+            const T gnm = gm - sg * nem + gh * phm;
+            dm += (gp - gnp) + (gm - gnm);
+            g[b] = gnp;
+            g[b + 1] = gnm;
             const int c2 = cx * cx + cy * cy + cz * cz;
-            mb += T(19 * c2 - 30) * v[b];
+            mb += T(19 * c2 - 30) * vs;
             const int p1 = 2 * cx * cx - cy * cy - cz * cz, p2 = cy * cy - cz * cz;
-            if (p1) m1 += T(p1) * v[b];
-            if (p2) m2 += T(p2) * v[b];
-            if (cx * cy) m3 += T(cx * cy) * v[b];
-            if (cy * cz) m4 += T(cy * cz) * v[b];
-            if (cx * cz) m5 += T(cx * cz) * v[b];
+            if (p1) m1 += T(p1) * vs;
+            if (p2) m2 += T(p2) * vs;
+            if (cx * cy) m3 += T(cx * cy) * vs;
+            if (cy * cz) m4 += T(cy * cz) * vs;
+            if (cx * cz) m5 += T(cx * cz) * vs;
         }
         const T kb = (sg - a.s_bulk) * mb * T(1.0 / 2394.0);
         const T ks = sg - a.omega;
         const T k1 = ks * m1 * T(1.0 / 36.0), k2 = ks * m2 * T(1.0 / 12.0);
         const T k3 = ks * m3 * T(0.25), k4 = ks * m4 * T(0.25), k5 = ks * m5 * T(0.25);
 #pragma unroll
-        for (int b = 1; b < 19; ++b) {
+        for (int b = 1; b < 19; b += 2) {   // the correction is even in c: one per pair
             const int cx = L::cx[b], cy = L::cy[b], cz = L::cz[b];
             const int c2 = cx * cx + cy * cy + cz * cz;
             T d = kb * T(19 * c2 - 30);
@@ -290,9 +320,10 @@ __device__ __forceinline__ void collide_d3q19(T (&g)[19], T drho, T Fx, T Fy, T 
             if (cx * cy) d += k3 * T(cx * cy);
             if (cy * cz) d += k4 * T(cy * cz);
             if (cx * cz) d += k5 * T(cx * cz);
-            const T gf = g[b] + d;
-            dm += g[b] - gf;
-            g[b] = gf;
+            const T fp = g[b] + d, fm = g[b + 1] + d;
+            dm += (g[b] - fp) + (g[b + 1] - fm);
+            g[b] = fp;
+            g[b + 1] = fm;
         }
         g[0] += dm;
     }
