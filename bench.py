@@ -119,8 +119,8 @@ TRAFFIC_RATIO = {
     ("d2q9_e8_8192", "tile2x64x16"): (0.563, 0.500),
     ("d2q9_e8_8192", "tile2x64x8"): (0.563, 0.500),
     ("d2q9_e8_8192", "tile64x16r4"): (1.525, 1.000),
-    ("d3q19_mrt_e8_320", "march64x8r1h32pf1"): (1.335, 1.000),
-    ("d3q19_mrt_e8_320", "march64x8r1h64pf1"): (1.245, 1.000),
+    ("d3q19_mrt_e8_320", "march64x8r1h32pf1"): (1.515, 1.000),
+    ("d3q19_mrt_e8_320", "march64x8r1h64pf1"): (1.382, 1.000),
 }
 
 
