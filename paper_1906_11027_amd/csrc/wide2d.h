@@ -100,6 +100,25 @@ struct TreeSum<LO, 1> {
 // the node's mass is that of the stored g0*, where summing the populations
 // before and after would add the rounding of two Q-term sums of O(rho)
 // values, repeated identically every step near a steady state.
+// Index of the velocity opposite to b (-1 if the list has none).
+template <typename L>
+constexpr int opposite_of(int b)
+{
+    for (int k = 0; k < L::Q; ++k)
+        if (L::cx[k] == -L::cx[b] && L::cy[k] == -L::cy[b]) return k;
+    return -1;
+}
+
+template <typename L>
+constexpr bool has_opposite_pairs()
+{
+    for (int b = 1; b < L::Q; ++b) {
+        const int m = opposite_of<L>(b);
+        if (m < 1 || m == b || L::w[m] != L::w[b]) return false;
+    }
+    return true;
+}
+
 template <typename T, typename L, bool EDM>
 __device__ __forceinline__ void collide_lat(T (&g)[L::Q], T drho, T Fx, T Fy, const StepArgs<T>& a)
 {
@@ -122,36 +141,55 @@ __device__ __forceinline__ void collide_lat(T (&g)[L::Q], T drho, T Fx, T Fy, co
         const T usq = T(0.5 * ics) * (ux * ux + uy * uy);
         const T uF = ux * Fx + uy * Fy;
         const T gu = a.guo;
+        // over each pair (b, -b) feq and the Guo source split into a part
+        // even in c and a part odd in c; c.u and c.F are formed once per pair
 #pragma unroll
         for (int b = 1; b < Q; ++b) {
+            const int m = opposite_of<L>(b);
+            if (m < b) continue;   // the pair was done from its first member
             const T cu = T(L::cx[b]) * ux + T(L::cy[b]) * uy;
             const T cF = T(L::cx[b]) * Fx + T(L::cy[b]) * Fy;
             const T w = T(L::w[b]);
-            const T geq = w * (drho + rho * (T(ics) * cu + T(ics2h) * cu * cu - usq));
-            const T phi = gu * w * (T(ics) * (cF - uF) + T(2.0 * ics2h) * cu * cF);
-            const T gn = g[b] - om * (g[b] - geq) + phi;
-            dm += g[b] - gn;
-            g[b] = gn;
+            const T es = w * (drho + rho * (T(ics2h) * cu * cu - usq));
+            const T ea = w * rho * (T(ics) * cu);
+            const T ps = gu * w * (T(2.0 * ics2h) * cu * cF - T(ics) * uF);
+            const T pa = gu * w * (T(ics) * cF);
+            const T gp = g[b], gm = g[m];
+            const T np = gp - om * (gp - (es + ea)) + (ps + pa);
+            const T nm = gm - om * (gm - (es - ea)) + (ps - pa);
+            dm += (gp - np) + (gm - nm);
+            g[b] = np;
+            g[m] = nm;
         }
     } else {
         const T vx = jx * inv, vy = jy * inv;
         const T dx = Fx * inv, dy = Fy * inv;
         const T vsq = T(0.5 * ics) * (vx * vx + vy * vy);
         const T dsq = T(0.5 * ics) * (dx * (T(2) * vx + dx) + dy * (T(2) * vy + dy));
+        // the same even/odd split for feq(v) and feq(v + F/rho) - feq(v)
 #pragma unroll
         for (int b = 1; b < Q; ++b) {
+            const int m = opposite_of<L>(b);
+            if (m < b) continue;
             const T cv = T(L::cx[b]) * vx + T(L::cy[b]) * vy;
             const T cd = T(L::cx[b]) * dx + T(L::cy[b]) * dy;
             const T w = T(L::w[b]);
-            const T geq = w * (drho + rho * (T(ics) * cv + T(ics2h) * cv * cv - vsq));
-            const T dfe = w * rho * (T(ics) * cd + T(ics2h) * cd * (T(2) * cv + cd) - dsq);
-            const T gn = g[b] - om * (g[b] - geq) + dfe;
-            dm += g[b] - gn;
-            g[b] = gn;
+            const T es = w * (drho + rho * (T(ics2h) * cv * cv - vsq));
+            const T ea = w * rho * (T(ics) * cv);
+            const T ds = w * rho * (T(ics2h) * cd * (T(2) * cv + cd) - dsq);
+            const T da = w * rho * (T(ics) * cd);
+            const T gp = g[b], gm = g[m];
+            const T np = gp - om * (gp - (es + ea)) + (ds + da);
+            const T nm = gm - om * (gm - (es - ea)) + (ds - da);
+            dm += (gp - np) + (gm - nm);
+            g[b] = np;
+            g[m] = nm;
         }
     }
     g[0] += dm;
 }
+static_assert(has_opposite_pairs<D2Q9>() && has_opposite_pairs<D2Q13>() && has_opposite_pairs<D2Q25>(),
+              "every moving velocity needs an opposite of equal weight");
 
 template <typename T, typename L, int ORDER, bool EDM, bool WALLS, int TX, int TY, int RPT>
 __global__ void __launch_bounds__(TX*(TY / RPT))
