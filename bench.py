@@ -92,14 +92,14 @@ TRAFFIC_RATIO = {
     ("d3q19_mrt_e8_320_fp64", "march32x16h32"): (1.460, 1.000),
     ("d3q19_mrt_e8_320_fp64", "march32x8r1h32pf1"): (1.566, 1.000),
     ("d3q19_mrt_e8_320_fp64", "march32x8r1h64pf1"): (1.502, 1.000),
-    ("d2q13_e6_pr_edm_8192", "wide128x16r2"): (1.394, 1.000),
-    ("d2q13_e6_pr_edm_8192", "wide256x8r2"): (1.387, 1.000),
-    ("d2q25_e8_pr_edm_8192", "wide128x16r2"): (1.443, 1.000),
-    ("d2q25_e8_pr_edm_8192", "wide256x8r2"): (1.404, 1.000),
-    ("d2q13_e6_pr_edm_8192", "wide64x16r2"): (1.824, 1.000),
-    ("d2q13_e6_pr_edm_8192", "wide64x16r4"): (1.867, 1.000),
-    ("d2q25_e8_pr_edm_8192", "wide64x16r2"): (1.792, 1.000),
-    ("d2q25_e8_pr_edm_8192", "wide64x16r4"): (2.093, 1.000),
+    ("d2q13_e6_pr_edm_8192", "wide128x16r2"): (1.365, 1.000),
+    ("d2q13_e6_pr_edm_8192", "wide256x8r2"): (1.374, 1.000),
+    ("d2q25_e8_pr_edm_8192", "wide128x16r2"): (1.439, 1.000),
+    ("d2q25_e8_pr_edm_8192", "wide256x8r2"): (1.401, 1.000),
+    ("d2q13_e6_pr_edm_8192", "wide64x16r2"): (1.799, 1.000),
+    ("d2q13_e6_pr_edm_8192", "wide64x16r4"): (1.864, 1.000),
+    ("d2q25_e8_pr_edm_8192", "wide64x16r2"): (1.795, 1.000),
+    ("d2q25_e8_pr_edm_8192", "wide64x16r4"): (2.114, 1.000),
     ("d2q9_e8_256", "tile2x32x8t1024"): (0.677, 0.500),
     ("d2q9_e8_256", "tile2x32x8t512"): (0.688, 0.500),
     ("d2q9_e8_8192", "tile2x32x8t1024"): (0.626, 0.500),
