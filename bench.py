@@ -261,7 +261,8 @@ def steady_droplet(shape=(64, 64), R=16, seed=1, order=4, precision="fp32", max_
     wall = time.perf_counter() - t0
     ob = sim.observe(fields=False)["obs"]
     sim.close()
-    rule = ("FP32: on 3 consecutive checks, or max|u| of 100 checks within the state's resolution"
+    rule = ("FP32: on 3 consecutive checks, or max|u| of 50 checks on a line within the state's resolution "
+            "that stays in it for 300 more checks"
             if precision == "fp32" else "FP64: the literal rule")
     return {"workload": "D2Q9 SRT %dx%d E%d droplet R=%d, %s, to max|u| change < 1e-10 per 100 steps (%s)"
                         % (shape[0], shape[1], order, R, precision.upper(), rule),

@@ -173,7 +173,7 @@ int sc_lbm_create(const sc_lbm_params* p, const double* rho_init, void* dev_a, v
 
 /* Advance the state (Sec. 2, Eq. (1), (3), (4): psi, force, collision and
  * pull streaming fused in one kernel per step, or per two steps for the
- * D2Q9 launch shapes that block two steps in time; see
+ * launch shapes that block two steps in time; see
  * sc_lbm_steps_per_launch).
  *   max_steps  steps to run (>= 0);
  *   tol        0: run exactly max_steps, asynchronously (nothing is read
@@ -181,14 +181,18 @@ int sc_lbm_create(const sc_lbm_params* p, const double* rho_init, void* dev_a, v
  *              once |max_u - previous max_u| < tol (an FP32 state on 3
  *              consecutive checks: its round-off moves max_u by ~1e-7 per
  *              check, so one check can fall below tol by chance), or (FP32)
- *              once max_u of the last 100 checks lies within one band as
- *              wide as the velocity the FP32 state resolves: the stored
- *              g_b = f_b - w_b rho_ref are rounded to 2^-24 of at most
- *              w_b max(1, |rho - rho_ref|), so u is resolved to
+ *              once max_u of the last 50 checks scatters around its
+ *              least-squares line by less than the velocity the FP32 state
+ *              resolves, and that line moves by less than the same band over
+ *              the next 300 checks: the stored g_b = f_b - w_b rho_ref are
+ *              rounded to 2^-24 of at most w_b max(1, |rho - rho_ref|), so u
+ *              is resolved to
  *              4 * 2^-24 * sum_b |c_b| w_b * max(1, |rho - rho_ref|) / rho_min
  *              (about 1e-6 for a droplet with rho in 0.15..2; at least 4 ulp
- *              of max_u).  A slow drift of max_u widens the band and keeps
- *              the run going; round-off noise of the state does not;
+ *              of max_u).  A slow drift of max_u shows as a slope and keeps
+ *              the run going; round-off noise of the state does not.  Each
+ *              check is one fused pass over the state (see sc_lbm_check),
+ *              captured with the K steps in one graph;
  *   steps_done  may be NULL; receives the steps actually taken.
  * Returns SC_E_NONFINITE as soon as a check sees a non-finite node. */
 int sc_lbm_step(sc_lbm* h, int64_t max_steps, double tol, int64_t* steps_done);
@@ -206,6 +210,19 @@ int sc_lbm_force(sc_lbm* h, const double* psi_in, double* F_out);
  * order).
  * Synchronous. */
 int sc_lbm_observe(sc_lbm* h, sc_lbm_obs* obs, double* rho_out, double* u_out, void* f_out);
+
+/* The observables of sc_lbm_observe (no fields) from one fused pass over
+ * the current state: psi of each tile and its stencil halo in LDS, then per
+ * node rho, u = (sum_b f_b c_b + F/2) / rho with F of Eq. (1), and the FP64
+ * reduction slots (per-block partials summed in a fixed order); max_u equals
+ * sc_lbm_observe's, the sums agree to rounding.  This is the check
+ * sc_lbm_step runs every K steps, where it is captured in the same graph as
+ * the K steps.  The partials and the result block live in device buffers of
+ * the handle (about 90 KB, allocated on first use) and the result is copied
+ * to pinned host memory.  Synchronous; obs->converged_by reports the last
+ * sc_lbm_step's rule.  Errors: SC_E_INVAL (NULL argument), SC_E_NOMEM,
+ * SC_E_DEVICE; SC_E_NONFINITE when a node is not finite (obs is filled). */
+int sc_lbm_check(sc_lbm* h, sc_lbm_obs* obs);
 
 /* Restore a state written by sc_lbm_observe(f_out) (checkpoint / resume):
  * f_in host buffer of sc_lbm_state_bytes bytes; step sets the step counter. */
@@ -258,8 +275,9 @@ const char* sc_lbm_variant_name(const sc_lbm* h);
 int sc_lbm_num_variants(const sc_lbm_params* p);
 
 /* Time steps one kernel launch of the handle's launch shape advances: 1, or
- * 2 for the D2Q9 shapes that fuse two steps per launch (temporal blocking;
- * sc_lbm_step still advances exactly the steps asked for).  0 on NULL. */
+ * 2 for the D2Q9 and any-lattice 2D shapes that fuse two steps per launch
+ * (temporal blocking; sc_lbm_step still advances exactly the steps asked
+ * for, and with walls every launch takes one step).  0 on NULL. */
 int sc_lbm_steps_per_launch(const sc_lbm* h);
 
 void sc_lbm_destroy(sc_lbm* h);
@@ -276,7 +294,12 @@ const char* sc_lbm_strerror(int code);
 typedef struct sc_lbm_batch sc_lbm_batch;
 
 /*   items      n parameter sets (lattice SC_D2Q9, collision SC_SRT, Guo
- *              forcing, psi SC_PSI_EXP or SC_PSI_IDENTITY);
+ *              forcing, psi SC_PSI_EXP or SC_PSI_IDENTITY); items[0].variant
+ *              picks the batched launch shape (see sc_lbm_batch_variant_name):
+ *              0 one step per launch on 32 x 8 tiles, 1 / 2 / 3 two steps per
+ *              launch (temporal blocking, one-step launches for an odd
+ *              remainder) on 32 x 8, 64 x 16 and 32 x 16 tiles; any other
+ *              value the automatic shape (2 for FP32, 1 for FP64);
  *   rho_init   n host pointers to [nx*ny] initial densities (each nullable),
  *              or NULL for rho = 1 everywhere;
  *   hip_stream as for sc_lbm_create.
@@ -305,6 +328,21 @@ int32_t sc_lbm_batch_active(sc_lbm_batch* b);
 
 /* The storage shift rho_ref every item uses; NaN on a NULL batch. */
 double sc_lbm_batch_rho_ref(const sc_lbm_batch* b);
+
+/* Continue an FP32 batch in FP64 from its current states: a sweep run in
+ * FP32 to its steady-state rule is then finished to the literal rule (the
+ * max |u| change below tol) with the FP64 state, whose resolution the rule
+ * needs.  Each item's state is widened exactly into new FP64 buffers (same
+ * storage shift rho_ref, freshly allocated; the FP32 buffers are freed);
+ * items retired by a convergence rule rejoin the work list with their
+ * convergence history cleared, quarantined items stay out, and every item
+ * keeps its own step count.  The batch then runs the automatic FP64 launch
+ * shape.  Synchronises the stream.  Errors: SC_E_INVAL (NULL or already FP64
+ * batch), SC_E_NOMEM, SC_E_DEVICE. */
+int sc_lbm_batch_promote(sc_lbm_batch* b);
+
+/* Name of the batched launch shape in use ("" on a NULL batch). */
+const char* sc_lbm_batch_variant_name(const sc_lbm_batch* b);
 
 void sc_lbm_batch_destroy(sc_lbm_batch* b);
 

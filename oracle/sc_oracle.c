@@ -40,6 +40,11 @@
 #include <omp.h>
 #endif
 
+/* Grids below this many nodes run their node loops on one thread: the
+ * fork/join of a parallel region costs more than their work (no result
+ * depends on the thread count). */
+#define ORC_OMP_MIN_NODES 16384
+
 #define ORC_D2Q9 0
 #define ORC_D3Q19 1
 #define ORC_D2Q13 2
@@ -306,7 +311,7 @@ static void force_from_psi(const orc_sim *s, const double *psi, double *F)
     const long n = s->n;
     const int nx = s->p.nx, ny = s->p.ny, nz = s->p.nz;
     /* threads take whole rows (z, y); every node's sum is the same either way */
-#pragma omp parallel for collapse(2) schedule(static)
+#pragma omp parallel for collapse(2) schedule(static) if (n >= ORC_OMP_MIN_NODES)
     for (long z = 0; z < nz; ++z)
         for (long y = 0; y < ny; ++y)
             for (long x = 0; x < nx; ++x) {
@@ -324,7 +329,7 @@ static void force_from_psi(const orc_sim *s, const double *psi, double *F)
 static void macro(orc_sim *s)
 {
     const long n = s->n;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= ORC_OMP_MIN_NODES)
     for (long i = 0; i < n; ++i) {
         double r = 0.0;
         for (int b = 0; b < s->q; ++b) r += s->f[b * n + i];
@@ -511,7 +516,7 @@ void orc_step(orc_sim *s, long nsteps)
     const int nx = s->p.nx, ny = s->p.ny, nz = s->p.nz;
     for (long t = 0; t < nsteps; ++t) {
         macro(s);
-#pragma omp parallel for collapse(2) schedule(static)
+#pragma omp parallel for collapse(2) schedule(static) if (n >= ORC_OMP_MIN_NODES)
         for (long z = 0; z < nz; ++z)
             for (long y = 0; y < ny; ++y)
                 for (long x = 0; x < nx; ++x) {

@@ -370,6 +370,7 @@ hipError_t launch_step_wide(int lattice, const StepArgs<float>& a, int order, bo
 hipError_t launch_step_wide(int lattice, const StepArgs<double>& a, int order, bool edm, int variant,
                             hipStream_t s);
 int num_variants_wide();
+int variant_steps_wide(int v);   // 1, or 2 for the shapes that block two steps in time
 const char* variant_name_wide(int v);
 // per-lattice instantiations (kernels_wide_q*.hip)
 hipError_t launch_wide_q9(const StepArgs<float>& a, int order, bool edm, int variant, hipStream_t s);
@@ -405,14 +406,42 @@ hipError_t launch_force(int dim, int precision, int order, const void* args, Obs
                         bool with_velocity, hipStream_t s);
 hipError_t launch_psi_from_host(int precision, const double* psi_dev_d, void* psi, int64_t n, hipStream_t s);
 hipError_t launch_reduce(int dim, ObsBuffers& ob, const uint8_t* solid, int64_t n, hipStream_t s);
+// dst[i] = (double)src[i], i < n
+hipError_t launch_widen(const float* src, double* dst, int64_t n, hipStream_t s);
+
+// Steady-state check straight from the state, in one pass: each block takes
+// tiles of the grid, fills an LDS tile of psi (tile plus the force stencil's
+// halo, every node pulled from the state), then for its own nodes forms rho,
+// j, F (Eq. (1)) and u = (j + F/2) / rho and accumulates the kObsSlots FP64
+// reduction slots; a single-block pass sums the per-block partials in a
+// fixed order.  result holds kCheckSlots doubles: the reduction slots, then
+// rho and psi at the centre node and at node 0 (the Laplace pressure pair).
+// partials: check_blocks(...) rows of kObsSlots doubles.
+constexpr int kCheckSlots = kObsSlots + 4;
+int check_blocks(int lattice, int64_t nx, int64_t ny, int64_t nz);
+hipError_t launch_check(int lattice, int precision, int order, const void* f, const void* args, double* partials,
+                        double* result, hipStream_t s);
 
 // Batched D2Q9 step over a (item, tile) work list (kernels_batch.hip).
-int batch_tile_w();
-int batch_tile_h();
+// Launch shapes of the batched step: 0 one step per launch on 32 x 8 tiles;
+// 1-3 two steps per launch (temporal blocking) on 32 x 8, 64 x 16 and
+// 32 x 16 tiles.  Work entries are (item, tile) pairs of the shape's tile.
+int batch_num_shapes();
+int batch_shape_steps(int v);
+void batch_shape_tile(int v, int* tw, int* th);
+const char* batch_shape_name(int v);
 size_t batch_item_bytes(int precision);
 void batch_fill_item(void* dst, int precision, const void* a, void* b, int nx, int ny, int order, double gc0,
                      double tau);
-hipError_t launch_batch_d2q9(const void* items, const int2* work, int nwork, int parity, int precision,
+hipError_t launch_batch_d2q9(int shape, const void* items, const int2* work, int nwork, int parity, int precision,
                              const void* common, hipStream_t s);
+// Steady-state check of every active item (the single-grid check above per
+// item): cwork lists (item, 16 x 16 tile) entries, one block each, whose
+// partial rows are cwork's indices; citems lists (item, first entry, entry
+// count) per active item; results holds kCheckSlots doubles per item.
+int batch_check_tile();
+hipError_t launch_batch_check(const void* items, const int2* cwork, int ncwork, const int4* citems, int nactive,
+                              int parity, int precision, const void* common, double* partials, double* results,
+                              hipStream_t s);
 
 }  // namespace sclbm

@@ -190,6 +190,11 @@ static const Shape3D kShapes3D[] = {
     {64, 8, 1, 64, "march64x8r1h64pf1"},
     {32, 8, 1, 32, "march32x8r1h32pf1"},
     {32, 8, 1, 64, "march32x8r1h64pf1"},
+    // 768 threads: three waves per SIMD at up to 168 VGPRs (the MRT E8
+    // window needs ~153), and a halo ring of 0.42 nodes per tile node
+    {64, 12, 1, 64, "march64x12r1h64pf1"},
+    {64, 12, 1, 32, "march64x12r1h32pf1"},
+    {64, 12, 1, 16, "march64x12r1h16pf1"},
 };
 constexpr int kNumShapes3D = sizeof(kShapes3D) / sizeof(kShapes3D[0]);
 
@@ -226,6 +231,9 @@ static hipError_t launch_v(const StepArgs<T>& a, int variant, hipStream_t s)
     // 256 threads with the prefetch window: room for the FP64 window without spills
     case 11: return launch_march<T, ORDER, MRT, 32, 8, 1, 1>(a, 32, s);
     case 12: return launch_march<T, ORDER, MRT, 32, 8, 1, 1>(a, 64, s);
+    case 13: return launch_march<T, ORDER, MRT, 64, 12, 1, 1>(a, 64, s);
+    case 14: return launch_march<T, ORDER, MRT, 64, 12, 1, 1>(a, 32, s);
+    case 15: return launch_march<T, ORDER, MRT, 64, 12, 1, 1>(a, 16, s);
     default: return hipErrorInvalidValue;
     }
 }

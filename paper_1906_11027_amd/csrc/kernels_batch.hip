@@ -8,7 +8,8 @@
 // over the four compiled orders) and an LDS tile sized for the largest
 // radius (3), so items of every order share one launch.  Items drop out of
 // the work list when they converge; the host rebuilds the list.
-#include "kernels.h"
+#include "reduce.h"
+#include "tile2.h"
 
 namespace sclbm {
 
@@ -17,7 +18,6 @@ struct BatchItem {
     const T* a;          // state buffer 0
     T* b;                // state buffer 1
     int nx, ny;
-    int tiles_x;         // tiles per row of this item
     int order;           // 4, 6, 8, 10
     T gc0, omega, guo;
 };
@@ -74,7 +74,8 @@ k_d2q9_batch(const BatchItem<T>* __restrict__ items, const int2* __restrict__ wo
     const uint32_t TS = sizeof(T), rowb = (uint32_t)nx * TS;
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = ty * TX + tx;
-    const int x0 = (wk.y % it.tiles_x) * TX, y0 = (wk.y / it.tiles_x) * TY;
+    const int tiles_x = (it.nx + TX - 1) / TX;
+    const int x0 = (wk.y % tiles_x) * TX, y0 = (wk.y / tiles_x) * TY;
 
     const int xr = x0 + tx, yr = y0 + ty;
     const bool valid = xr < nx && yr < ny;
@@ -130,21 +131,99 @@ k_d2q9_batch(const BatchItem<T>* __restrict__ items, const int2* __restrict__ wo
     }
 }
 
-int batch_tile_w() { return kBTX; }
-int batch_tile_h() { return kBTY; }
+// Two steps per launch: the two-step tile of the single-grid kernel
+// (tile2.h) per work entry, with the item's stencil order (a uniform switch)
+// and LDS sized for the largest radius.  Work entries of one item are listed
+// in strip order; the XCD swizzle gives each XCD a contiguous range of them,
+// so tiles that share halo lines run on the same XCD (same L2).
+template <typename T, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT)
+k_d2q9_batch2(const BatchItem<T>* __restrict__ items, const int2* __restrict__ work, int parity,
+              StepArgs<T> common)
+{
+    using LD = Tile2Lds<kBRMAX, TX, TY>;
+    __shared__ T psi1[LD::P1N];
+    __shared__ T psi2[LD::P2N];
+    __shared__ T s1[9 * LD::C1N];
+    const int2 wk = work[xcd_swizzle(blockIdx.x, gridDim.x)];
+    const BatchItem<T> it = items[wk.x];
+    StepArgs<T> a = common;
+    a.fin = parity ? it.b : it.a;
+    a.fout = parity ? (T*)it.a : it.b;
+    a.nx = it.nx;
+    a.ny = it.ny;
+    a.nz = 1;
+    a.n = (int64_t)it.nx * it.ny;
+    a.gc0 = it.gc0;
+    a.omega = it.omega;
+    a.guo = it.guo;
+    const int tiles_x = (it.nx + TX - 1) / TX;
+    const int x0 = (wk.y % tiles_x) * TX, y0 = (wk.y / tiles_x) * TY;
+    switch (it.order) {   // uniform across the block
+    case 4: d2q9_tile2_body<T, 4, TX, TY, NT>(a, x0, y0, psi1, psi2, s1); break;
+    case 6: d2q9_tile2_body<T, 6, TX, TY, NT>(a, x0, y0, psi1, psi2, s1); break;
+    case 8: d2q9_tile2_body<T, 8, TX, TY, NT>(a, x0, y0, psi1, psi2, s1); break;
+    default: d2q9_tile2_body<T, 10, TX, TY, NT>(a, x0, y0, psi1, psi2, s1); break;
+    }
+}
 
-hipError_t launch_batch_d2q9(const void* items, const int2* work, int nwork, int parity, int precision,
+// ------------------------------------------------------------ shapes ----
+struct BatchShape {
+    int tw, th, steps;
+    const char* name;
+};
+static const BatchShape kBatchShapes[] = {
+    {kBTX, kBTY, 1, "batch32x8"},
+    {32, 8, 2, "batch2x32x8t256"},
+    {64, 16, 2, "batch2x64x16t1024"},
+    {32, 16, 2, "batch2x32x16t512"},
+};
+constexpr int kNumBatchShapes = sizeof(kBatchShapes) / sizeof(kBatchShapes[0]);
+
+int batch_num_shapes() { return kNumBatchShapes; }
+int batch_shape_steps(int v) { return (v >= 0 && v < kNumBatchShapes) ? kBatchShapes[v].steps : 0; }
+void batch_shape_tile(int v, int* tw, int* th)
+{
+    const BatchShape& b = kBatchShapes[(v >= 0 && v < kNumBatchShapes) ? v : 0];
+    *tw = b.tw;
+    *th = b.th;
+}
+const char* batch_shape_name(int v) { return (v >= 0 && v < kNumBatchShapes) ? kBatchShapes[v].name : "?"; }
+
+template <typename T>
+static hipError_t batch_launch_t(int shape, const BatchItem<T>* items, const int2* work, int nwork, int parity,
+                                 const StepArgs<T>& common, hipStream_t s)
+{
+    switch (shape) {
+    case 0:
+        hipLaunchKernelGGL(k_d2q9_batch<T>, dim3(nwork), dim3(kBTX, kBTY), 0, s, items, work, parity, common);
+        break;
+    case 1:
+        hipLaunchKernelGGL((k_d2q9_batch2<T, 32, 8, 256>), dim3(nwork), dim3(256), 0, s, items, work, parity,
+                           common);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_d2q9_batch2<T, 64, 16, 1024>), dim3(nwork), dim3(1024), 0, s, items, work, parity,
+                           common);
+        break;
+    case 3:
+        hipLaunchKernelGGL((k_d2q9_batch2<T, 32, 16, 512>), dim3(nwork), dim3(512), 0, s, items, work, parity,
+                           common);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_d2q9(int shape, const void* items, const int2* work, int nwork, int parity, int precision,
                              const void* common, hipStream_t s)
 {
     if (nwork <= 0) return hipSuccess;
-    dim3 block(kBTX, kBTY);
     if (precision == 0)
-        hipLaunchKernelGGL(k_d2q9_batch<float>, dim3(nwork), block, 0, s, (const BatchItem<float>*)items, work,
-                           parity, *(const StepArgs<float>*)common);
-    else
-        hipLaunchKernelGGL(k_d2q9_batch<double>, dim3(nwork), block, 0, s, (const BatchItem<double>*)items, work,
-                           parity, *(const StepArgs<double>*)common);
-    return hipGetLastError();
+        return batch_launch_t<float>(shape, (const BatchItem<float>*)items, work, nwork, parity,
+                                     *(const StepArgs<float>*)common, s);
+    return batch_launch_t<double>(shape, (const BatchItem<double>*)items, work, nwork, parity,
+                                  *(const StepArgs<double>*)common, s);
 }
 
 size_t batch_item_bytes(int precision)
@@ -155,15 +234,88 @@ size_t batch_item_bytes(int precision)
 void batch_fill_item(void* dst, int precision, const void* a, void* b, int nx, int ny, int order, double gc0,
                      double tau)
 {
-    const int tiles_x = (nx + kBTX - 1) / kBTX;
     if (precision == 0) {
-        BatchItem<float> it{(const float*)a, (float*)b, nx, ny, tiles_x, order, (float)gc0, (float)(1.0 / tau),
+        BatchItem<float> it{(const float*)a, (float*)b, nx, ny, order, (float)gc0, (float)(1.0 / tau),
                             (float)(1.0 - 0.5 / tau)};
         *(BatchItem<float>*)dst = it;
     } else {
-        BatchItem<double> it{(const double*)a, (double*)b, nx, ny, tiles_x, order, gc0, 1.0 / tau, 1.0 - 0.5 / tau};
+        BatchItem<double> it{(const double*)a, (double*)b, nx, ny, order, gc0, 1.0 / tau, 1.0 - 0.5 / tau};
         *(BatchItem<double>*)dst = it;
     }
+}
+
+// ------------------------------------------------------------- check ----
+// Steady-state check of the active items: block k takes check entry k, a
+// (item, 16 x 16 tile) pair, and runs the fused check of that tile on the
+// item's current buffer with the item's stencil order; its partial row is
+// row k.  Then one block per active item sums the rows of its entries in
+// order into the item's result row.
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads)
+k_batch_check(const BatchItem<T>* __restrict__ items, const int2* __restrict__ cwork, int parity,
+              StepArgs<T> common, double* __restrict__ partials, double* __restrict__ results)
+{
+    using CT = CheckTile<2>;
+    __shared__ T psi_s[check_lds_max<2>()];
+    const int2 wk = cwork[blockIdx.x];
+    const BatchItem<T> it = items[wk.x];
+    StepArgs<T> a = common;
+    a.fin = parity ? it.b : it.a;
+    a.nx = it.nx;
+    a.ny = it.ny;
+    a.nz = 1;
+    a.n = (int64_t)it.nx * it.ny;
+    a.gc0 = it.gc0;
+    const int tiles_x = (it.nx + CT::TX - 1) / CT::TX;
+    const int x0 = (wk.y % tiles_x) * CT::TX, y0 = (wk.y / tiles_x) * CT::TY;
+    const int64_t ic = (int64_t)(it.nx / 2) + (int64_t)it.nx * (it.ny / 2);
+    double* extra = results + (int64_t)wk.x * kCheckSlots + kObsSlots;
+    double acc[kNR];
+#pragma unroll
+    for (int k = 0; k < kNR; ++k) acc[k] = slot_start(k);
+    switch (it.order) {   // uniform across the block
+    case 4: check_tile<T, D2Q9, 1, 4>(a, x0, y0, 0, psi_s, acc, ic, extra); break;
+    case 6: check_tile<T, D2Q9, 1, 6>(a, x0, y0, 0, psi_s, acc, ic, extra); break;
+    case 8: check_tile<T, D2Q9, 1, 8>(a, x0, y0, 0, psi_s, acc, ic, extra); break;
+    default: check_tile<T, D2Q9, 1, 10>(a, x0, y0, 0, psi_s, acc, ic, extra); break;
+    }
+    block_reduce_store(acc, partials + (int64_t)blockIdx.x * kNR);
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+k_batch_check_final(const int4* __restrict__ citems, const double* __restrict__ partials, double* __restrict__ results)
+{
+    const int4 ci = citems[blockIdx.x];   // item, first entry, entry count
+    double acc[kNR];
+#pragma unroll
+    for (int k = 0; k < kNR; ++k) acc[k] = slot_start(k);
+    for (int b = threadIdx.x; b < ci.z; b += blockDim.x) {
+        const double* p = partials + (int64_t)(ci.y + b) * kNR;
+#pragma unroll
+        for (int k = 0; k < kNR; ++k) acc[k] = is_max_slot(k) ? fmax(acc[k], p[k]) : acc[k] + p[k];
+    }
+    block_reduce_store(acc, results + (int64_t)ci.x * kCheckSlots);
+}
+
+int batch_check_tile() { return CheckTile<2>::TX; }
+
+hipError_t launch_batch_check(const void* items, const int2* cwork, int ncwork, const int4* citems, int nactive,
+                              int parity, int precision, const void* common, double* partials, double* results,
+                              hipStream_t s)
+{
+    if (ncwork <= 0 || nactive <= 0) return hipSuccess;
+    if (precision == 0)
+        hipLaunchKernelGGL(k_batch_check<float>, dim3(ncwork), dim3(kRedThreads), 0, s,
+                           (const BatchItem<float>*)items, cwork, parity, *(const StepArgs<float>*)common, partials,
+                           results);
+    else
+        hipLaunchKernelGGL(k_batch_check<double>, dim3(ncwork), dim3(kRedThreads), 0, s,
+                           (const BatchItem<double>*)items, cwork, parity, *(const StepArgs<double>*)common,
+                           partials, results);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batch_check_final, dim3(nactive), dim3(kRedThreads), 0, s, citems, partials, results);
+    return hipGetLastError();
 }
 
 }  // namespace sclbm

@@ -39,9 +39,15 @@ __device__ __forceinline__ uint16_t f_to_bf16(float f)
     return (uint16_t)(u >> 16);
 }
 
+// v mod n for the halo coordinates of a tile: one add or subtract when v is
+// within one period of [0, n), a full modulo otherwise (images narrower than
+// the tile plus its halo)
 __device__ __forceinline__ int wrapc(int v, int n)
 {
-    return v < 0 ? v + n : (v >= n ? v - n : v);
+    const int r = v < 0 ? v + n : (v >= n ? v - n : v);
+    if (r >= 0 && r < n) return r;
+    const int m = v % n;
+    return m < 0 ? m + n : m;
 }
 
 template <int COUT>

@@ -6,45 +6,9 @@
 // the state precision, reduce a wavefront with xor-shuffles, combine the
 // waves of a block through LDS, and sum the per-block partials in a second
 // single-block pass in a fixed order (deterministic for a given grid).
-#include "kernels.h"
+#include "reduce.h"
 
 namespace sclbm {
-
-template <typename L>
-__device__ __forceinline__ void neighbours(int64_t i, int nx, int ny, int nz, int64_t (&zo)[3],
-                                           int64_t (&yo)[3], int (&xo)[3])
-{
-    const int64_t nxy = (int64_t)nx * ny;
-    const int z = (int)(i / nxy);
-    const int64_t rem = i - (int64_t)z * nxy;
-    const int y = (int)(rem / nx);
-    const int x = (int)(rem - (int64_t)y * nx);
-    xo[0] = x == 0 ? nx - 1 : x - 1;
-    xo[1] = x;
-    xo[2] = x == nx - 1 ? 0 : x + 1;
-    yo[0] = (int64_t)(y == 0 ? ny - 1 : y - 1) * nx;
-    yo[1] = (int64_t)y * nx;
-    yo[2] = (int64_t)(y == ny - 1 ? 0 : y + 1) * nx;
-    zo[0] = (int64_t)(z == 0 ? nz - 1 : z - 1) * nxy;
-    zo[1] = (int64_t)z * nxy;
-    zo[2] = (int64_t)(z == nz - 1 ? 0 : z + 1) * nxy;
-}
-
-// Flat index of node (x, y, z) + (dx, dy, dz) on the periodic grid (any
-// offset; used by the lattices that stream over distance 2).
-__device__ __forceinline__ int64_t shifted_node(int x, int y, int z, int dx, int dy, int dz, int nx, int ny, int nz)
-{
-    return ((int64_t)wrap_any(z + dz, nz) * ny + wrap_any(y + dy, ny)) * nx + wrap_any(x + dx, nx);
-}
-
-__device__ __forceinline__ void coords(int64_t i, int nx, int ny, int& x, int& y, int& z)
-{
-    const int64_t nxy = (int64_t)nx * ny;
-    z = (int)(i / nxy);
-    const int64_t rem = i - (int64_t)z * nxy;
-    y = (int)(rem / nx);
-    x = (int)(rem - (int64_t)y * nx);
-}
 
 // ---------------------------------------------------------------- init ----
 template <typename T, typename L, int M>
@@ -116,7 +80,7 @@ __global__ void k_init_rest(T* __restrict__ f, const double* __restrict__ rho0, 
 }
 
 // --------------------------------------------------------------- macro ----
-// rho, psi and j = sum_b f_b c_b of the pulled (pre-collision) state.
+// rho, psi and j of the pulled state as fields.
 template <typename T, typename L, int M>
 __global__ void k_macro(const T* __restrict__ f, StepArgs<T> a, double* __restrict__ rho,
                         T* __restrict__ psi, double* __restrict__ j)
@@ -124,31 +88,8 @@ __global__ void k_macro(const T* __restrict__ f, StepArgs<T> a, double* __restri
     const int64_t n = a.n;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        T dr = T(0), jx = T(0), jy = T(0), jz = T(0);
-        if (M == 1) {
-            int64_t zo[3], yo[3];
-            int xo[3];
-            neighbours<L>(i, a.nx, a.ny, a.nz, zo, yo, xo);
-#pragma unroll
-            for (int b = 0; b < L::Q; ++b) {
-                const T v = f[b * n + zo[1 - L::cz[b]] + yo[1 - L::cy[b]] + xo[1 - L::cx[b]]];
-                dr += v;
-                jx += T(L::cx[b]) * v;
-                jy += T(L::cy[b]) * v;
-                jz += T(L::cz[b]) * v;
-            }
-        } else {
-            int x, y, z;
-            coords(i, a.nx, a.ny, x, y, z);
-#pragma unroll
-            for (int b = 0; b < L::Q; ++b) {
-                const T v = f[b * n + shifted_node(x, y, z, -L::cx[b], -L::cy[b], -L::cz[b], a.nx, a.ny, a.nz)];
-                dr += v;
-                jx += T(L::cx[b]) * v;
-                jy += T(L::cy[b]) * v;
-                jz += T(L::cz[b]) * v;
-            }
-        }
+        T dr, jx, jy, jz;
+        pull_moments<T, L, M>(f, a, i, dr, jx, jy, jz);
         const T r = a.rho_ref + dr;
         rho[i] = (double)r;
         psi[i] = (a.solid && a.solid[i]) ? a.psi_w : psi_of(r, a);
@@ -159,46 +100,35 @@ __global__ void k_macro(const T* __restrict__ f, StepArgs<T> a, double* __restri
 }
 
 // --------------------------------------------------------------- force ----
-// Eq. (1) from a psi array, summed over +-e pairs; optionally the velocity
-// u = (j + F/2) / rho of the observed state.
+// The force field, and optionally the velocity u = (j + F/2) / rho of the
+// observed state.
 template <typename T, int D, int ORDER>
 __global__ void k_force(const T* __restrict__ psi, StepArgs<T> a, double* __restrict__ F,
                         const double* __restrict__ rho, const double* __restrict__ j,
                         double* __restrict__ u)
 {
-    using ST = Stencil<D, ORDER>;
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int64_t n = a.n;
-    const int64_t nxy = (int64_t)nx * ny;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const int z = (int)(i / nxy);
-        const int64_t rem = i - (int64_t)z * nxy;
-        const int y = (int)(rem / nx);
-        const int x = (int)(rem - (int64_t)y * nx);
-        T s[3] = {T(0), T(0), T(0)};
-#pragma unroll
-        for (int p = 0; p < ST::NP; ++p) {
-            constexpr PairList P = ST::P;
-            const int ex = P.e[p][0], ey = P.e[p][1], ez = P.e[p][2];
-            const int64_t ip = (int64_t)wrap_any(z + ez, nz) * nxy + (int64_t)wrap_any(y + ey, ny) * nx +
-                               wrap_any(x + ex, nx);
-            const int64_t im = (int64_t)wrap_any(z - ez, nz) * nxy + (int64_t)wrap_any(y - ey, ny) * nx +
-                               wrap_any(x - ex, nx);
-            const T wd = T(P.w[p]) * (psi[ip] - psi[im]);
-            s[0] += T(ex) * wd;
-            s[1] += T(ey) * wd;
-            s[2] += T(ez) * wd;
-        }
+        T s[3];
+        force_sum<T, D, ORDER>(psi, a, i, s);
         const T pref = -a.gc0 * psi[i];
         const bool wall = a.solid && a.solid[i];   // no force or velocity inside a wall
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             const double Fd = wall ? 0.0 : (double)(pref * s[d]);
             F[d * n + i] = Fd;
-            if (u) u[d * n + i] = wall ? 0.0 : (j[d * n + i] + 0.5 * Fd) / rho[i];
+            if (u) u[d * n + i] = wall ? 0.0 : node_u(j[d * n + i], Fd, rho[i]);
         }
     }
+}
+
+// an FP32 state widened exactly to FP64 (same storage shift)
+__global__ void k_widen(const float* __restrict__ src, double* __restrict__ dst, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = (double)src[i];
 }
 
 template <typename T>
@@ -210,48 +140,6 @@ __global__ void k_psi_convert(const double* __restrict__ src, T* __restrict__ ds
 }
 
 // ------------------------------------------------------------- reduce ----
-// partial[blk] = {sum rho, sum rho u_x, sum rho u_y, sum rho u_z,
-//                 max |u|, sum |u|, sum |u|^2, count of non-finite nodes,
-//                 count of finite fluid nodes, max rho, max -rho}
-// (the maxima over finite fluid nodes).  Wall nodes add their rho
-// (populations in transit) to the mass only.
-constexpr int kNR = kObsSlots;
-constexpr int kRedThreads = 256;
-
-__host__ __device__ constexpr bool is_max_slot(int k) { return k == 4 || k == 9 || k == 10; }
-__host__ __device__ constexpr double slot_start(int k) { return (k == 9 || k == 10) ? -1e300 : 0.0; }
-
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-__device__ __forceinline__ double wave_max(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    return v;
-}
-
-__device__ __forceinline__ void block_reduce_store(double (&acc)[kNR], double* out)
-{
-    __shared__ double red[kRedThreads / 64][kNR];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < kNR; ++k) acc[k] = is_max_slot(k) ? wave_max(acc[k]) : wave_sum(acc[k]);
-    if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < kNR; ++k) red[wv][k] = acc[k];
-    __syncthreads();
-    if (threadIdx.x < kNR) {
-        const int k = threadIdx.x;
-        double v = red[0][k];
-        for (int w = 1; w < kRedThreads / 64; ++w) v = is_max_slot(k) ? fmax(v, red[w][k]) : v + red[w][k];
-        out[k] = v;
-    }
-}
-
 __global__ void __launch_bounds__(kRedThreads)
 k_reduce_partials(const double* __restrict__ rho, const double* __restrict__ u, const uint8_t* __restrict__ solid,
                   int dim, int64_t n, double* __restrict__ partials)
@@ -261,32 +149,9 @@ k_reduce_partials(const double* __restrict__ rho, const double* __restrict__ u, 
     for (int k = 0; k < kNR; ++k) acc[k] = slot_start(k);
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const double r = rho[i];
-        if (solid && solid[i]) {
-            if (isfinite(r)) acc[0] += r;
-            else acc[7] += 1.0;
-            continue;
-        }
-        double uu = 0.0;
-        bool fin = isfinite(r);
-        for (int d = 0; d < dim; ++d) {
-            const double ud = u[d * n + i];
-            fin = fin && isfinite(ud);
-            acc[1 + d] += r * ud;
-            uu += ud * ud;
-        }
-        if (!fin) {
-            acc[7] += 1.0;
-            continue;
-        }
-        const double um = sqrt(uu);
-        acc[0] += r;
-        acc[4] = fmax(acc[4], um);
-        acc[5] += um;
-        acc[6] += uu;
-        acc[8] += 1.0;
-        acc[9] = fmax(acc[9], r);
-        acc[10] = fmax(acc[10], -r);
+        double ud[3] = {0.0, 0.0, 0.0};
+        for (int d = 0; d < dim; ++d) ud[d] = u[d * n + i];
+        accumulate_node(acc, rho[i], ud, dim, solid && solid[i]);
     }
     block_reduce_store(acc, partials + (int64_t)blockIdx.x * kNR);
 }
@@ -303,6 +168,30 @@ k_reduce_final(const double* __restrict__ partials, int nblk, double* __restrict
         for (int k = 0; k < kNR; ++k) acc[k] = is_max_slot(k) ? fmax(acc[k], p[k]) : acc[k] + p[k];
     }
     block_reduce_store(acc, out);
+}
+
+
+// ------------------------------------------------------------- check ----
+// Fused steady-state check: blocks take the grid's check tiles in turn
+// (a bounded grid, so the partials stay a few hundred rows).
+constexpr int kCheckMaxBlocks = 1024;
+
+template <typename T, typename L, int M, int ORDER>
+__global__ void __launch_bounds__(kRedThreads)
+k_check(StepArgs<T> a, int ntx, int nty, int ntz, int64_t ic, double* __restrict__ partials,
+        double* __restrict__ extra)
+{
+    using CT = CheckTile<L::D>;
+    __shared__ T psi_s[check_lds_max<L::D>()];
+    double acc[kNR];
+#pragma unroll
+    for (int k = 0; k < kNR; ++k) acc[k] = slot_start(k);
+    const int ntiles = ntx * nty * ntz;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int bx = t % ntx, by = (t / ntx) % nty, bz = t / (ntx * nty);
+        check_tile<T, L, M, ORDER>(a, bx * CT::TX, by * CT::TY, bz * CT::TZ, psi_s, acc, ic, extra);
+    }
+    block_reduce_store(acc, partials + (int64_t)blockIdx.x * kNR);
 }
 
 // ----------------------------------------------------------- launchers ----
@@ -422,6 +311,12 @@ hipError_t launch_psi_from_host(int precision, const double* psi_dev_d, void* ps
     return hipGetLastError();
 }
 
+hipError_t launch_widen(const float* src, double* dst, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_widen, grid_for(n, 256), 256, 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_reduce(int dim, ObsBuffers& ob, const uint8_t* solid, int64_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_reduce_partials, ob.nblk, kRedThreads, 0, s, ob.rho, ob.u, solid, dim, n, ob.partials);
@@ -429,6 +324,76 @@ hipError_t launch_reduce(int dim, ObsBuffers& ob, const uint8_t* solid, int64_t 
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce_final, 1, kRedThreads, 0, s, ob.partials, ob.nblk, ob.result);
     return hipGetLastError();
+}
+
+static void check_tiles(int lattice, int64_t nx, int64_t ny, int64_t nz, int64_t& tx, int64_t& ty, int64_t& tz)
+{
+    const bool d3 = lattice == 1;
+    const int TX = d3 ? CheckTile<3>::TX : CheckTile<2>::TX, TY = d3 ? CheckTile<3>::TY : CheckTile<2>::TY;
+    const int TZ = d3 ? CheckTile<3>::TZ : CheckTile<2>::TZ;
+    tx = (nx + TX - 1) / TX;
+    ty = (ny + TY - 1) / TY;
+    tz = (nz + TZ - 1) / TZ;
+}
+
+int check_blocks(int lattice, int64_t nx, int64_t ny, int64_t nz)
+{
+    int64_t tx, ty, tz;
+    check_tiles(lattice, nx, ny, nz, tx, ty, tz);
+    const int64_t t = tx * ty * tz;
+    return (int)(t < kCheckMaxBlocks ? t : kCheckMaxBlocks);
+}
+
+template <typename T, typename L, int M, int ORDER>
+static hipError_t check_launch(const StepArgs<T>& a, double* partials, double* result, hipStream_t s)
+{
+    int64_t tx, ty, tz;
+    check_tiles(L::D == 3 ? 1 : 0, a.nx, a.ny, a.nz, tx, ty, tz);
+    const int nb = check_blocks(L::D == 3 ? 1 : 0, a.nx, a.ny, a.nz);
+    const int64_t ic = (int64_t)(a.nx / 2) + (int64_t)a.nx * ((int64_t)(a.ny / 2) + (int64_t)a.ny * (a.nz / 2));
+    hipLaunchKernelGGL((k_check<T, L, M, ORDER>), nb, kRedThreads, 0, s, a, (int)tx, (int)ty, (int)tz, ic,
+                       partials, result + kObsSlots);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_final, 1, kRedThreads, 0, s, partials, nb, result);
+    return hipGetLastError();
+}
+
+template <typename T, typename L, int M>
+static hipError_t check_order(int order, const StepArgs<T>& a, double* partials, double* result, hipStream_t s)
+{
+    switch (order) {
+    case 4: return check_launch<T, L, M, 4>(a, partials, result, s);
+    case 6: return check_launch<T, L, M, 6>(a, partials, result, s);
+    case 8: return check_launch<T, L, M, 8>(a, partials, result, s);
+    case 10:
+        if constexpr (L::D == 2) return check_launch<T, L, M, 10>(a, partials, result, s);
+        return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+static hipError_t check_t(int lattice, int order, const T* f, const StepArgs<T>& args, double* partials,
+                          double* result, hipStream_t s)
+{
+    StepArgs<T> a = args;
+    a.fin = f;
+    switch (lattice) {
+    case 0: return check_order<T, D2Q9, 1>(order, a, partials, result, s);
+    case 1: return check_order<T, D3Q19, 1>(order, a, partials, result, s);
+    case 2: return check_order<T, D2Q13, 2>(order, a, partials, result, s);
+    case 3: return check_order<T, D2Q25, 2>(order, a, partials, result, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_check(int lattice, int precision, int order, const void* f, const void* args, double* partials,
+                        double* result, hipStream_t s)
+{
+    if (precision == 0)
+        return check_t<float>(lattice, order, (const float*)f, *(const StepArgs<float>*)args, partials, result, s);
+    return check_t<double>(lattice, order, (const double*)f, *(const StepArgs<double>*)args, partials, result, s);
 }
 
 }  // namespace sclbm

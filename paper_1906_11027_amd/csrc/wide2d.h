@@ -87,6 +87,18 @@ struct TreeSum<LO, 1> {
     }
 };
 
+// every moving velocity has an opposite of the same weight: b and
+// opposite(b) differ, and the rest velocity is its own opposite
+template <typename L>
+constexpr bool has_opposite_pairs()
+{
+    for (int b = 1; b < L::Q; ++b) {
+        const int m = opposite<L>(b);
+        if (m < 1 || m == b || L::w[m] != L::w[b]) return false;
+    }
+    return true;
+}
+
 // Collision on shifted values g = f - w rho_ref, drho = rho - rho_ref.
 //   Guo:  u = (j + F/2)/rho,  g* = g - (g - geq(u))/tau + (1 - 1/(2 tau)) phihat(u, F)
 //   EDM:  v = j/rho, dv = F/rho,  g* = g - (g - geq(v))/tau + feq(v + dv) - feq(v)
@@ -100,25 +112,6 @@ struct TreeSum<LO, 1> {
 // the node's mass is that of the stored g0*, where summing the populations
 // before and after would add the rounding of two Q-term sums of O(rho)
 // values, repeated identically every step near a steady state.
-// Index of the velocity opposite to b (-1 if the list has none).
-template <typename L>
-constexpr int opposite_of(int b)
-{
-    for (int k = 0; k < L::Q; ++k)
-        if (L::cx[k] == -L::cx[b] && L::cy[k] == -L::cy[b]) return k;
-    return -1;
-}
-
-template <typename L>
-constexpr bool has_opposite_pairs()
-{
-    for (int b = 1; b < L::Q; ++b) {
-        const int m = opposite_of<L>(b);
-        if (m < 1 || m == b || L::w[m] != L::w[b]) return false;
-    }
-    return true;
-}
-
 template <typename T, typename L, bool EDM>
 __device__ __forceinline__ void collide_lat(T (&g)[L::Q], T drho, T Fx, T Fy, const StepArgs<T>& a)
 {
@@ -145,7 +138,7 @@ __device__ __forceinline__ void collide_lat(T (&g)[L::Q], T drho, T Fx, T Fy, co
         // even in c and a part odd in c; c.u and c.F are formed once per pair
 #pragma unroll
         for (int b = 1; b < Q; ++b) {
-            const int m = opposite_of<L>(b);
+            const int m = opposite<L>(b);
             if (m < b) continue;   // the pair was done from its first member
             const T cu = T(L::cx[b]) * ux + T(L::cy[b]) * uy;
             const T cF = T(L::cx[b]) * Fx + T(L::cy[b]) * Fy;
@@ -169,7 +162,7 @@ __device__ __forceinline__ void collide_lat(T (&g)[L::Q], T drho, T Fx, T Fy, co
         // the same even/odd split for feq(v) and feq(v + F/rho) - feq(v)
 #pragma unroll
         for (int b = 1; b < Q; ++b) {
-            const int m = opposite_of<L>(b);
+            const int m = opposite<L>(b);
             if (m < b) continue;
             const T cv = T(L::cx[b]) * vx + T(L::cy[b]) * vy;
             const T cd = T(L::cx[b]) * dx + T(L::cy[b]) * dy;
@@ -305,6 +298,178 @@ k_wide_tile(StepArgs<T> a, int nbx, int nby, int sw)
     }
 }
 
+// Two time steps per launch (temporal blocking), any lattice without walls.
+// A block owns a TX x TY tile; with R the force-stencil radius and M the
+// lattice's reach:
+//   phase 1  psi at t+1 on the tile + (2R + M): pull each node's Q values
+//            from the state (kept in registers), sum, psi -> LDS psi1;
+//   phase 2  step t -> t+1 on the tile + (R + M), a sub-region of the first:
+//            force from psi1, collide the registers -> LDS copy s1 of the
+//            post-collision values;
+//   phase 3  psi at t+2 on the tile + R, pulled from s1 -> LDS psi2;
+//   phase 4  step t+1 -> t+2 on the tile: pull from s1, force from psi2,
+//            collide, store.
+// The state is read and written once per two updates; the (R + M) halo of
+// phase 2 is collided again by the neighbouring tiles.
+template <int Q, int R, int M, int TX, int TY>
+struct WideTile2 {
+    static constexpr int H1 = 2 * R + M, P1W = TX + 2 * H1, P1H = TY + 2 * H1, P1N = P1W * P1H;
+    static constexpr int HC = R + M, C1W = TX + 2 * HC, C1H = TY + 2 * HC, C1N = C1W * C1H;
+    static constexpr int P2W = TX + 2 * R, P2H = TY + 2 * R, P2N = P2W * P2H;
+    template <typename T>
+    static constexpr size_t lds_bytes()
+    {
+        return sizeof(T) * ((size_t)P1N + P2N + (size_t)Q * C1N);
+    }
+};
+
+template <typename T, int ORDER>
+__device__ __forceinline__ void wide_force_at(const T* c, int LW, T gc0, T& Fx, T& Fy)
+{
+    using ST = Stencil<2, ORDER>;
+    T sx = T(0), sy = T(0), ax = T(0), ay = T(0);
+#pragma unroll
+    for (int p = 0; p < ST::NP; ++p) {
+        constexpr PairList P = ST::P;
+        const int ex = P.e[p][0], ey = P.e[p][1];
+        const T d = c[ey * LW + ex] - c[-ey * LW - ex];
+        if (ex) ax += T(ex) * d;
+        if (ey) ay += T(ey) * d;
+        if (P.shell_end(p)) {
+            sx += T(P.w[p]) * ax;
+            sy += T(P.w[p]) * ay;
+            ax = ay = T(0);
+        }
+    }
+    const T pref = -gc0 * c[0];
+    Fx = pref * sx;
+    Fy = pref * sy;
+}
+
+template <typename T, typename L, int ORDER, bool EDM, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT)
+k_wide_tile2(StepArgs<T> a, int nbx, int nby, int sw)
+{
+    constexpr int Q = L::Q;
+    constexpr int M = lattice_reach<L>();
+    constexpr int R = Stencil<2, ORDER>::R;
+    using W = WideTile2<Q, R, M, TX, TY>;
+    constexpr int H1 = W::H1, P1W = W::P1W, P1N = W::P1N;
+    constexpr int HC = W::HC, C1W = W::C1W, C1H = W::C1H, C1N = W::C1N;
+    constexpr int P2W = W::P2W, P2N = W::P2N;
+    __shared__ T psi1[P1N];
+    __shared__ T psi2[P2N];
+    __shared__ T s1[Q * C1N];
+
+    const int nx = a.nx, ny = a.ny;
+    const int64_t n = a.n;
+    const uint32_t TS = sizeof(T), rowb = (uint32_t)nx * TS;
+    const int tid = threadIdx.x;
+    int bx, by;
+    strip_tile(xcd_swizzle(blockIdx.x, gridDim.x), nbx, nby, sw, bx, by);
+    const int x0 = bx * TX, y0 = by * TY;
+
+    // phase 1 (the per-thread node loop has a compile-time bound and is
+    // unrolled, so all of a thread's pulls are in flight together)
+    constexpr int K1 = (P1N + NT - 1) / NT;
+    T g[K1][Q];
+#pragma unroll
+    for (int q = 0; q < K1; ++q) {
+        const int i = tid + q * NT;
+        if (i < P1N) {
+            const int ly = i / P1W, lx = i - ly * P1W;
+            uint32_t xo[2 * M + 1], yo[2 * M + 1];
+            offsets_m<M>(wrap_near(x0 - H1 + lx, nx), nx, TS, xo);
+            offsets_m<M>(wrap_near(y0 - H1 + ly, ny), ny, rowb, yo);
+            pull_lat<T, L, M>(a.fin, n, xo, yo, g[q]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < K1; ++q) {
+        const int i = tid + q * NT;
+        if (i < P1N) psi1[i] = psi_of(a.rho_ref + TreeSum<0, Q>::of(g[q]), a);
+    }
+    __syncthreads();
+    // phase 2: the (R + M)-halo region sits R inside the psi1 region
+#pragma unroll
+    for (int q = 0; q < K1; ++q) {
+        const int i = tid + q * NT;
+        if (i < P1N) {
+            const int ly = i / P1W, lx = i - ly * P1W;
+            const int cx = lx - R, cy = ly - R;
+            if (cx >= 0 && cx < C1W && cy >= 0 && cy < C1H) {
+                T Fx, Fy;
+                wide_force_at<T, ORDER>(psi1 + ly * P1W + lx, P1W, a.gc0, Fx, Fy);
+                collide_lat<T, L, EDM>(g[q], TreeSum<0, Q>::of(g[q]), Fx, Fy, a);
+                const int ci = cy * C1W + cx;
+#pragma unroll
+                for (int b = 0; b < Q; ++b) s1[b * C1N + ci] = g[q][b];
+            }
+        }
+    }
+    __syncthreads();
+    // pull at t+2 of the node at s1 coordinates (cx, cy)
+    auto pull_s1 = [&](int cx, int cy, T (&h)[Q]) {
+#pragma unroll
+        for (int b = 0; b < Q; ++b) h[b] = s1[b * C1N + (cy - L::cy[b]) * C1W + cx - L::cx[b]];
+    };
+    // phase 3: psi at t+2 on the tile + R (s1 coordinates offset by M)
+    constexpr int K3 = (P2N + NT - 1) / NT;
+#pragma unroll
+    for (int q = 0; q < K3; ++q) {
+        const int i = tid + q * NT;
+        if (i < P2N) {
+            const int ly = i / P2W, lx = i - ly * P2W;
+            T h[Q];
+            pull_s1(lx + M, ly + M, h);
+            psi2[i] = psi_of(a.rho_ref + TreeSum<0, Q>::of(h), a);
+        }
+    }
+    __syncthreads();
+    // phase 4: step t+1 -> t+2 on the tile, store
+    constexpr int K4 = (TX * TY + NT - 1) / NT;
+#pragma unroll
+    for (int q = 0; q < K4; ++q) {
+        const int i = tid + q * NT;
+        if (i >= TX * TY) break;
+        const int lx = i % TX, ly = i / TX;
+        T h[Q];
+        pull_s1(lx + HC, ly + HC, h);
+        T Fx, Fy;
+        wide_force_at<T, ORDER>(psi2 + (ly + R) * P2W + lx + R, P2W, a.gc0, Fx, Fy);
+        collide_lat<T, L, EDM>(h, TreeSum<0, Q>::of(h), Fx, Fy, a);
+        const int xr = x0 + lx, yr = y0 + ly;
+        if (xr < nx && yr < ny) {
+            const uint32_t off = (uint32_t)yr * rowb + (uint32_t)xr * TS;
+#pragma unroll
+            for (int b = 0; b < Q; ++b) st_off(a.fout + b * n, off, h[b]);
+        }
+    }
+}
+
+// LDS of a block on gfx950
+constexpr size_t kLdsBytes = 160 * 1024;
+
+template <typename T, typename L, int ORDER, bool EDM, int TX, int TY, int NT>
+static hipError_t launch_wide_tile2(const StepArgs<T>& a, hipStream_t s)
+{
+    using W = WideTile2<L::Q, Stencil<2, ORDER>::R, lattice_reach<L>(), TX, TY>;
+    if constexpr (W::template lds_bytes<T>() > kLdsBytes) {
+        // the tile does not fit: a smaller two-step tile takes its place,
+        // 32 x 8, else 32 x 4 (which fits every lattice and order in FP64)
+        static_assert(TX * TY > 128, "the 32 x 4 two-step tile must fit");
+        if constexpr (TX * TY > 256)
+            return launch_wide_tile2<T, L, ORDER, EDM, 32, 8, 256>(a, s);
+        else
+            return launch_wide_tile2<T, L, ORDER, EDM, 32, 4, 256>(a, s);
+    } else {
+        const int nbx = (a.nx + TX - 1) / TX, nby = (a.ny + TY - 1) / TY;
+        hipLaunchKernelGGL((k_wide_tile2<T, L, ORDER, EDM, TX, TY, NT>), dim3(nbx * nby), dim3(NT), 0, s, a, nbx,
+                           nby, kStripTiles);
+        return hipGetLastError();
+    }
+}
+
 // Launch shapes of the any-lattice family (names as variant_name_wide()).
 template <typename T, typename L, int ORDER, bool EDM, bool WALLS, int TX, int TY, int RPT>
 static hipError_t launch_wide_tile(const StepArgs<T>& a, hipStream_t s)
@@ -326,6 +491,19 @@ static hipError_t launch_wide_shape(const StepArgs<T>& a, int variant, hipStream
     // wide rows use more of each cache line the pulls touch (reach M in x)
     case 4: return launch_wide_tile<T, L, ORDER, EDM, WALLS, 128, 16, 2>(a, s);
     case 5: return launch_wide_tile<T, L, ORDER, EDM, WALLS, 256, 8, 2>(a, s);
+    // two steps per launch (no walls: the wall kernels step one at a time)
+    case 6:
+        if constexpr (!WALLS) return launch_wide_tile2<T, L, ORDER, EDM, 32, 8, 256>(a, s);
+        return hipErrorInvalidValue;
+    case 7:
+        if constexpr (!WALLS) return launch_wide_tile2<T, L, ORDER, EDM, 64, 8, 512>(a, s);
+        return hipErrorInvalidValue;
+    case 8:
+        if constexpr (!WALLS) return launch_wide_tile2<T, L, ORDER, EDM, 64, 16, 1024>(a, s);
+        return hipErrorInvalidValue;
+    case 9:
+        if constexpr (!WALLS) return launch_wide_tile2<T, L, ORDER, EDM, 128, 8, 1024>(a, s);
+        return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
 }

@@ -65,12 +65,12 @@ class sc_lbm_obs(ctypes.Structure):
 #: every symbol include/sc_lbm.h declares
 EXPORTS = [
     "sc_lbm_default_params", "sc_lbm_state_bytes", "sc_lbm_create", "sc_lbm_step",
-    "sc_lbm_force", "sc_lbm_observe", "sc_lbm_set_state", "sc_lbm_state_ptr",
+    "sc_lbm_force", "sc_lbm_observe", "sc_lbm_check", "sc_lbm_set_state", "sc_lbm_state_ptr",
     "sc_lbm_variant_name", "sc_lbm_num_variants", "sc_lbm_destroy", "sc_lbm_strerror", "sc_lbm_set_walls",
     "sc_lbm_steps_per_launch",
     "sc_lbm_last_error_detail", "sc_lbm_stream", "sc_lbm_rho_ref",
     "sc_lbm_batch_create", "sc_lbm_batch_step", "sc_lbm_batch_observe", "sc_lbm_batch_status",
-    "sc_lbm_batch_active", "sc_lbm_batch_rho_ref", "sc_lbm_batch_destroy", "sc_lbm_autotune",
+    "sc_lbm_batch_active", "sc_lbm_batch_rho_ref", "sc_lbm_batch_variant_name", "sc_lbm_batch_promote", "sc_lbm_batch_destroy", "sc_lbm_autotune",
     "sc_nn_conv3x3_fwd", "sc_nn_conv3x3_bwd_data", "sc_nn_bwd_weight_scratch_floats",
     "sc_nn_conv3x3_bwd_weight", "sc_nn_tanh_fwd", "sc_nn_tanh_bwd", "sc_nn_mse", "sc_nn_adam",
     "sc_nn_to_bf16", "sc_nn_features", "sc_nn_start_field",
@@ -121,6 +121,8 @@ def lib():
     L.sc_lbm_force.restype = ctypes.c_int
     L.sc_lbm_observe.argtypes = [vp, P(sc_lbm_obs), dp, dp, vp]
     L.sc_lbm_observe.restype = ctypes.c_int
+    L.sc_lbm_check.argtypes = [vp, P(sc_lbm_obs)]
+    L.sc_lbm_check.restype = ctypes.c_int
     L.sc_lbm_set_state.argtypes = [vp, vp, ctypes.c_int64]
     L.sc_lbm_set_state.restype = ctypes.c_int
     L.sc_lbm_state_ptr.argtypes = [vp]
@@ -174,6 +176,10 @@ def lib():
     L.sc_lbm_rho_ref.restype = ctypes.c_double
     L.sc_lbm_batch_rho_ref.argtypes = [vp]
     L.sc_lbm_batch_rho_ref.restype = ctypes.c_double
+    L.sc_lbm_batch_variant_name.argtypes = [vp]
+    L.sc_lbm_batch_promote.argtypes = [vp]
+    L.sc_lbm_batch_promote.restype = ctypes.c_int
+    L.sc_lbm_batch_variant_name.restype = ctypes.c_char_p
     L.sc_lbm_last_error_detail.argtypes = []
     L.sc_lbm_last_error_detail.restype = ctypes.c_char_p
     _lib = L
@@ -242,6 +248,14 @@ def sc_lbm_observe(h, rho_out=None, u_out=None, f_out=None):
     rc = lib().sc_lbm_observe(h, ctypes.byref(o), _dptr(rho_out), _dptr(u_out), fptr)
     if rc not in (SC_OK, SC_E_NONFINITE):
         raise ScError(rc, "sc_lbm_observe")
+    return rc, o
+
+
+def sc_lbm_check(h):
+    o = sc_lbm_obs()
+    rc = lib().sc_lbm_check(h, ctypes.byref(o))
+    if rc not in (SC_OK, SC_E_NONFINITE):
+        raise ScError(rc, "sc_lbm_check")
     return rc, o
 
 
@@ -383,6 +397,11 @@ class Sim:
             out["rho"] = self._unflat(rho)
             out["u"] = np.stack([self._unflat(u[k * self.n:(k + 1) * self.n]) for k in range(self.dim)])
         return out
+
+    def check(self):
+        """The observables of the fused one-pass check (no fields)."""
+        rc, o = sc_lbm_check(self.h)
+        return {"obs": o.as_dict(), "rc": rc}
 
     def force(self, psi=None):
         flat = None if psi is None else np.ascontiguousarray(np.asarray(psi, np.float64).transpose()).ravel()
@@ -533,6 +552,16 @@ class Batch:
     @property
     def active(self):
         return sc_lbm_batch_active(self.h)
+
+    def promote(self):
+        """Continue in FP64 from the current FP32 states (retired items rejoin)."""
+        _check(lib().sc_lbm_batch_promote(self.h), "sc_lbm_batch_promote")
+        return self
+
+    @property
+    def variant(self):
+        """Name of the batched launch shape in use."""
+        return lib().sc_lbm_batch_variant_name(self.h).decode()
 
     @property
     def rho_ref(self):

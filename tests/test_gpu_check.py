@@ -1,0 +1,189 @@
+"""The fused steady-state check (sc_lbm_check, the pass sc_lbm_step and
+sc_lbm_batch_step run every K steps) against the observation path
+(sc_lbm_observe: fields, force, then reductions) and against the oracle.
+
+Both paths compute every node's rho and u = (sum f c + F/2) / rho with F of
+Eq. (1) in the same arithmetic, so the maximum |u|, the density extremes and
+the two pressure nodes agree exactly; the sums (mass, momentum, mean and rms
+|u|) are taken over a different block partition and agree to rounding
+(1e-12 relative).  The steady-state loop built on the check stops where the
+literal rule applied to sc_lbm_observe's max |u| stops (FP64).
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from tests.gpu_helpers import say
+from workload import droplet_rho
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1906_11027_amd import Batch, Sim  # noqa: E402
+from paper_1906_11027_amd import eos as P  # noqa: E402
+
+EXACT = ("max_u", "rho_min", "rho_max", "rho_in", "rho_out", "p_in", "p_out", "dp", "nonfinite", "step")
+SUMS = ("mass", "mean_u", "l2_u", "radius")
+
+
+def _pr_kw(lattice, order):
+    e = P.params_at(0.85)
+    return dict(order=order, G=-1.0, psi="pr", eos=e, forcing="edm",
+                tau=11.0 / 12.0 if lattice == "D2Q13" else 19.0 / 24.0), P.maxwell(e)
+
+
+def _cases():
+    out = []
+    for prec in ("fp32", "fp64"):
+        for order in (4, 6, 8, 10):
+            out.append(("D2Q9", (37, 29), dict(order=order), prec, None))
+        out.append(("D2Q9", (64, 64), dict(order=8), prec, None))
+        out.append(("D3Q19", (20, 18, 13), dict(order=8, collision="mrt"), prec, None))
+        out.append(("D3Q19", (16, 16, 16), dict(order=4, collision="srt"), prec, None))
+        out.append(("D2Q13", (41, 30), "pr6", prec, None))
+        out.append(("D2Q25", (48, 40), "pr8", prec, "walls"))
+    return out
+
+
+def _make(lattice, shape, kw, prec, walls):
+    dens = {}
+    if isinstance(kw, str):
+        kw, (rv, rl) = _pr_kw(lattice, int(kw[2:]))
+        dens = dict(rho_l=rl, rho_v=rv, width=4.0)
+    rho0 = droplet_rho(shape, min(shape) // 4, seed=11, **dens)
+    sim = Sim(rho0, lattice, precision=prec, **kw)
+    if walls:
+        solid = np.zeros(shape, dtype=bool)
+        solid[:, :2] = True
+        solid[:, -2:] = True
+        sim.set_walls(solid, 2.5)
+    return sim, rho0, kw
+
+
+@pytest.mark.parametrize("lattice,shape,kw,prec,walls", _cases())
+def test_check_matches_observe(lattice, shape, kw, prec, walls):
+    say("case check vs observe", lattice, shape, kw, prec, walls)
+    sim, _, _ = _make(lattice, shape, kw, prec, walls)
+    sim.step(57)
+    a = sim.check()["obs"]
+    b = sim.observe(fields=False)["obs"]
+    sim.close()
+    for k in EXACT:
+        assert a[k] == b[k], (k, a[k], b[k])
+    for k in SUMS:
+        assert abs(a[k] - b[k]) <= 1e-12 * abs(b[k]), (k, a[k], b[k])
+    for d in range(3):
+        assert abs(a["mom"][d] - b["mom"][d]) <= 1e-12 * (abs(b["mass"]) * max(b["max_u"], 1e-30)), d
+
+
+def test_check_matches_oracle_fp64():
+    rho0 = droplet_rho((40, 36), 10, seed=12)
+    sim = Sim(rho0, "D2Q9", order=10, precision="fp64", tau=0.9)
+    orc = O.Oracle(rho0, "D2Q9", order=10, tau=0.9)
+    sim.step(80)
+    orc.step(80)
+    a = sim.check()["obs"]
+    ref = orc.observables()
+    sim.close()
+    for k in ("mass", "max_u", "mean_u", "l2_u", "rho_min", "rho_max", "dp", "radius"):
+        assert abs(a[k] - ref[k]) <= 1e-11 * abs(ref[k]), (k, a[k], ref[k])
+
+
+@pytest.mark.parametrize("order", [4, 8])
+def test_step_rule_is_the_literal_rule_fp64(order):
+    """sc_lbm_step(tol) with the fused check in its graph stops at the same
+    step as the literal rule applied to sc_lbm_observe every K steps."""
+    rho0 = droplet_rho((48, 48), 12, seed=13)
+    a = Sim(rho0, "D2Q9", order=order, precision="fp64", obs_every=100)
+    rc, n = a.step(100000, tol=1e-10)
+    oa = a.observe(fields=False)["obs"]
+    a.close()
+    b = Sim(rho0, "D2Q9", order=order, precision="fp64", obs_every=100)
+    prev, m = None, 0
+    while m < 100000:
+        b.step(100)
+        m += 100
+        mu = b.observe(fields=False)["obs"]["max_u"]
+        if prev is not None and abs(mu - prev) < 1e-10:
+            break
+        prev = mu
+    ob = b.observe(fields=False)["obs"]
+    b.close()
+    say("E%d: step(tol) stops at %d (rule %d), loop at %d" % (order, n, oa["converged_by"], m))
+    assert rc == 0 and oa["converged_by"] == 1
+    assert n == m and oa["max_u"] == ob["max_u"]
+
+
+def test_batch_rule_matches_single_runs_fp64():
+    """The batched check retires each item at the step its single run stops
+    (or keeps it, where the single run does not stop within the steps)."""
+    specs = [((40, 40), 10, 4, -5.0, 1.0), ((52, 44), 12, 8, -5.2, 0.9), ((33, 33), 8, 10, -4.8, 1.2)]
+    items = [{"rho0": droplet_rho(s, R, seed=20 + k), "order": o, "G": G, "tau": t}
+             for k, (s, R, o, G, t) in enumerate(specs)]
+    bt = Batch(items, precision="fp64", obs_every=100)
+    bt.step(60000, tol=1e-10)
+    for k, it in enumerate(items):
+        steps, by = bt.status(k)
+        sim = Sim(it["rho0"], "D2Q9", order=it["order"], G=it["G"], tau=it["tau"], precision="fp64",
+                  obs_every=100, rho_ref=bt.rho_ref)
+        rc, n = sim.step(60000, tol=1e-10)
+        o1 = sim.observe(fields=False)["obs"]
+        sim.close()
+        ob = bt.observe(k, fields=False)["obs"]
+        say("batch item %d: %d steps (by %d), single %d (by %d)" % (k, steps, by, n, o1["converged_by"]))
+        assert by == o1["converged_by"] and steps == n
+        # the batched and single-grid kernels round alike up to fused
+        # multiply-adds: ~1e-13 apart after 5e4 FP64 steps
+        assert abs(ob["max_u"] - o1["max_u"]) <= 1e-10 * o1["max_u"]
+    bt.close()
+
+
+def test_promote_widens_the_state_and_steps_in_fp64():
+    """sc_lbm_batch_promote at t = 0: the FP32 start (w (rho0 - rho_ref)
+    rounded to float) widened into FP64 buffers, then 61 FP64 steps against
+    the oracle from rho0 (the start's FP32 rounding, ~1e-8, is all that
+    separates them)."""
+    specs = [((37, 29), 9, 4, -5.0, 1.0), ((52, 44), 12, 10, -5.2, 0.9)]
+    items = [{"rho0": droplet_rho(s, R, seed=30 + k), "order": o, "G": G, "tau": t}
+             for k, (s, R, o, G, t) in enumerate(specs)]
+    bt = Batch(items, precision="fp32")
+    bt.promote()
+    assert bt.variant.startswith("batch2")
+    bt.step(61)
+    for k, it in enumerate(items):
+        orc = O.Oracle(it["rho0"], "D2Q9", order=it["order"], G=it["G"], tau=it["tau"]).step(61)
+        got, ref = bt.observe(k), orc.fields()
+        er = float(np.max(np.abs(got["rho"] - ref["rho"]) / ref["rho"]))
+        du = float(np.max(np.abs(got["u"] - ref["u"])))
+        say("promoted item %d: rho rel %.2e, u %.2e" % (k, er, du))
+        assert er <= 1e-6 and du <= 1e-6 * float(np.max(np.abs(ref["u"]))) + 1e-9
+        steps, by = bt.status(k)
+        assert steps == 61
+    bt.close()
+
+
+def test_fp32_sweep_finished_in_fp64():
+    """An FP32 batch run to its steady-state rules, promoted, then run to
+    the literal FP64 rule: every item rejoins, counts its own steps and
+    stops by the tolerance rule."""
+    specs = [((40, 40), 10, 4, -5.0, 1.0), ((48, 44), 12, 8, -5.2, 0.9)]
+    items = [{"rho0": droplet_rho(s, R, seed=40 + k), "order": o, "G": G, "tau": t}
+             for k, (s, R, o, G, t) in enumerate(specs)]
+    bt = Batch(items, precision="fp32", obs_every=100)
+    bt.step(100000, tol=1e-10)
+    s32 = [bt.status(k) for k in range(len(items))]
+    assert all(by > 0 for _, by in s32)
+    bt.promote()
+    assert bt.active == len(items)
+    bt.step(200000, tol=1e-10)
+    for k in range(len(items)):
+        steps, by = bt.status(k)
+        ob = bt.observe(k, fields=False)["obs"]
+        say("item %d: fp32 retired at %d (by %d), fp64 at %d (by %d), max|u| %.9e" % (
+            k, s32[k][0], s32[k][1], steps, by, ob["max_u"]))
+        assert by == 1 and steps > s32[k][0]
+        assert ob["step"] == steps
+    bt.close()

@@ -33,10 +33,16 @@ def _stream():
     return torch.cuda.current_stream().cuda_stream
 
 
+# (5, 7) and (1, 3): images narrower than a 16 x 16 tile plus its halo, whose
+# halo coordinates wrap more than one period
+SHAPES = [(20, 37), (5, 7), (1, 3)]
+
+
+@pytest.mark.parametrize("h,w", SHAPES)
 @pytest.mark.parametrize("cin,cout", [(5, 32), (32, 32), (32, 1)])
-def test_conv_forward(cin, cout):
+def test_conv_forward(cin, cout, h, w):
     rng = np.random.default_rng(cin + cout)
-    bsz, h, w = 3, 20, 37
+    bsz = 3
     x = rng.normal(size=(bsz, cin, h, w))
     wt = rng.normal(scale=0.2, size=(cout, cin, 3, 3)).astype(np.float32)
     bias = rng.normal(size=cout).astype(np.float32)
@@ -48,14 +54,15 @@ def test_conv_forward(cin, cout):
                                      h, w, _stream()) == 0
     ref = C.conv_fwd(x.astype(np.float32).astype(np.float64), wq, bias.astype(np.float64))
     err = np.max(np.abs(out.cpu().numpy() - ref)) / np.max(np.abs(ref))
-    say("conv fwd %d->%d err %.2e" % (cin, cout, err))
+    say("conv fwd %d->%d %dx%d err %.2e" % (cin, cout, h, w, err))
     assert err < 1e-5
 
 
+@pytest.mark.parametrize("h,w", [(19, 34), (5, 7), (1, 3)])
 @pytest.mark.parametrize("cin,cout", [(5, 32), (32, 32), (32, 1)])
-def test_conv_backward(cin, cout):
+def test_conv_backward(cin, cout, h, w):
     rng = np.random.default_rng(7 + cin + cout)
-    bsz, h, w = 3, 19, 34
+    bsz = 3
     x = rng.normal(size=(bsz, cin, h, w)).astype(np.float32)
     g = rng.normal(size=(bsz, cout, h, w)).astype(np.float32)
     wt = rng.normal(scale=0.2, size=(cout, cin, 3, 3)).astype(np.float32)
@@ -71,7 +78,7 @@ def test_conv_backward(cin, cout):
                                             gb.data_ptr(), bsz, cin, cout, h, w, _stream()) == 0
     ew = np.max(np.abs(gw.cpu().numpy() - gw_ref)) / np.max(np.abs(gw_ref))
     eb = np.max(np.abs(gb.cpu().numpy() - gb_ref)) / np.max(np.abs(gb_ref))
-    say("conv bwd w %d->%d err %.2e bias %.2e" % (cin, cout, ew, eb))
+    say("conv bwd w %d->%d %dx%d err %.2e bias %.2e" % (cin, cout, h, w, ew, eb))
     assert ew < 1e-4 and eb < 1e-4
     if cin == 32:
         gin = torch.empty((bsz, cin, h, w), device="cuda")

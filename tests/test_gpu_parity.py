@@ -259,6 +259,23 @@ def test_d3q19_variants_agree(order, collision, prec):
             assert d <= (2e-6 if prec == "fp32" else 1e-14) * float(np.max(np.abs(ref))), (v, d)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("order", [4, 8])
+def test_d3q19_mrt_distinct_rates(order, prec):
+    """Bulk and ghost rates that differ from each other and from 1/tau
+    (0.7, 1.6, tau = 0.9), so every moment correction of the MRT collision,
+    the bulk one included, changes the result."""
+    say("case d3q19 mrt s_bulk 0.7 s_ghost 1.6", order, prec)
+    rho0 = droplet_rho((20, 18, 13), 5, seed=5)
+    kw = dict(order=order, collision="mrt", tau=0.9, s_bulk=0.7, s_ghost=1.6)
+    sim = Sim(rho0, "D3Q19", precision=prec, **kw)
+    orc = O.Oracle(rho0, "D3Q19", **kw)
+    sim.step(30)
+    orc.step(30)
+    _compare(sim, orc, prec, "D3Q19 E%d mrt 0.7/1.6 %s" % (order, prec))
+    sim.close()
+
+
 def test_d3q19_mrt_equals_srt_when_rates_equal():
     rho0 = droplet_rho((16, 16, 16), 5, seed=3)
     a = Sim(rho0, "D3Q19", order=8, collision="srt", precision="fp64", tau=0.8)
@@ -377,15 +394,21 @@ def _batch_items():
     return out
 
 
+@pytest.mark.parametrize("shape", [-1, 0, 1, 2, 3])
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_batch_matches_oracle_and_single(prec):
+def test_batch_matches_oracle_and_single(prec, shape):
+    """Every batched launch shape (one step per launch; two per launch on
+    32 x 8, 64 x 16 and 32 x 16 tiles; -1 automatic) against the oracle and
+    the single-grid runs.  61 steps: the two-step shapes end on a one-step
+    launch."""
     from paper_1906_11027_amd import Batch
     items = _batch_items()
-    say("batch items:", [(it["rho0"].shape, it["order"], round(it["G"], 3), it["tau"]) for it in items])
-    bt = Batch(items, precision=prec)
-    bt.step(60)
+    say("batch shape %d %s items:" % (shape, prec),
+        [(it["rho0"].shape, it["order"], round(it["G"], 3), it["tau"]) for it in items])
+    bt = Batch(items, precision=prec, variant=shape)
+    bt.step(61)
     for k, it in enumerate(items):
-        orc = O.Oracle(it["rho0"], "D2Q9", order=it["order"], G=it["G"], tau=it["tau"]).step(60)
+        orc = O.Oracle(it["rho0"], "D2Q9", order=it["order"], G=it["G"], tau=it["tau"]).step(61)
         got, ref = bt.observe(k), orc.fields()
         er = rel_err(got["rho"], ref["rho"])
         eu = float(np.max(np.abs(got["u"] - ref["u"])) / max(np.max(np.abs(ref["u"])), 1e-12))
@@ -394,7 +417,7 @@ def test_batch_matches_oracle_and_single(prec):
         assert er <= tr and eu <= tu, (k, er, eu)
         single = Sim(it["rho0"], "D2Q9", order=it["order"], G=it["G"], tau=it["tau"], precision=prec,
                      rho_ref=bt.rho_ref)
-        single.step(60)
+        single.step(61)
         sg = single.observe()
         assert np.max(np.abs(sg["rho"] - got["rho"])) <= (1e-6 if prec == "fp32" else 1e-13)
         single.close()
@@ -407,7 +430,10 @@ def test_batch_convergence_and_quarantine():
              {"rho0": droplet_rho((48, 36), 9, seed=2), "order": 8, "tau": 0.8},
              # far past the stable range: diverges and must be quarantined
              {"rho0": droplet_rho((32, 32), 8, seed=3), "order": 4, "G": -30.0, "tau": 0.51}]
-    bt = Batch(items, obs_every=50)
+    # the batched two-step shape on 32 x 8 tiles runs the arithmetic of the
+    # single-grid shape tile2x32x8 (variant 10), so a retired item can be
+    # checked against a single run to FP32 rounding after ~10^4 steps
+    bt = Batch(items, obs_every=50, variant=1)
     rc, done = bt.step(200000, tol=1e-7)
     st = [bt.status(k) for k in range(3)]
     say("batch status:", st, "steps", done)
@@ -416,7 +442,7 @@ def test_batch_convergence_and_quarantine():
     assert st[2][1] == -1
     # retired items keep their state: a converged item matches a single run
     # with the batch's storage shift
-    single = Sim(items[0]["rho0"], "D2Q9", order=4, rho_ref=bt.rho_ref)
+    single = Sim(items[0]["rho0"], "D2Q9", order=4, rho_ref=bt.rho_ref, variant=10)
     single.step(st[0][0])
     a = single.observe()["rho"]
     b = bt.observe(0)["rho"]

@@ -95,16 +95,16 @@ def test_wide_variants_and_state_layout(lattice):
     rho0 = droplet_rho((91, 45), 12, seed=13)
     kw = dict(order=8, G=g_scaled(lattice), tau=0.85, forcing="edm")
     orc = O.Oracle(rho0, lattice, **kw)
-    orc.step(20)
+    orc.step(21)
     ref = None
     nv = B.sc_lbm_num_variants(B.make_params(lattice, forcing="edm"))
     for v in range(nv):
         sim = Sim(rho0, lattice, variant=v, precision="fp64", **kw)
-        sim.step(20)
+        sim.step(21)
         _compare(sim, orc, "fp64", "%s variant %s" % (lattice, sim.variant))
         sim.close()
         sim = Sim(rho0, lattice, variant=v, **kw)
-        sim.step(20)
+        sim.step(21)
         st = sim.state()
         sim.close()
         if ref is None:
@@ -114,7 +114,7 @@ def test_wide_variants_and_state_layout(lattice):
             say("variant %d vs 0: max |diff| %.3e, bitwise %s" % (v, d, np.array_equal(st, ref)))
             assert d <= 1e-6
     sim = Sim(rho0, lattice, precision="fp64", **kw)
-    sim.step(20)
+    sim.step(21)
     oc = O.lattice_table(lattice)[1]
     f_gpu = pre_collision_from_state(sim, oc)
     f_orc = orc.get_f()
@@ -124,20 +124,23 @@ def test_wide_variants_and_state_layout(lattice):
     sim.close()
 
 
+@pytest.mark.parametrize("variant", [-1, 6, 9])
 @pytest.mark.parametrize("shape", [(3, 5), (1, 9), (2, 2), (33, 7)])
 @pytest.mark.parametrize("lattice", ["D2Q13", "D2Q25"])
-def test_wide_tiny_grids(lattice, shape):
+def test_wide_tiny_grids(lattice, shape, variant):
     """Grids narrower than the streaming reach (2) and the force stencil wrap
-    several times around the periodic box."""
-    say("case wide tiny", lattice, shape)
+    several times around the periodic box; also in the two-step shapes,
+    whose halos (2R + M = 8 nodes) wrap several times (31 steps: the last
+    launch is a one-step one)."""
+    say("case wide tiny", lattice, shape, variant)
     rng = np.random.default_rng(sum(shape))
     rho0 = 1.0 + 0.3 * rng.random(shape)
     kw = dict(order=10, G=-2.0, tau=0.9)
     for prec in ("fp32", "fp64"):
-        sim = Sim(rho0, lattice, precision=prec, **kw)
+        sim = Sim(rho0, lattice, precision=prec, variant=variant, **kw)
         orc = O.Oracle(rho0, lattice, **kw)
-        sim.step(30)
-        orc.step(30)
+        sim.step(31)
+        orc.step(31)
         _compare(sim, orc, prec, "%s %s %s" % (lattice, shape, prec))
         sim.close()
 

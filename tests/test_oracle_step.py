@@ -145,6 +145,50 @@ def test_shear_wave_viscosity_mrt(s_bulk, s_ghost):
     assert abs(nu - (tau - 0.5) / 3.0) < 5e-3 * (tau - 0.5) / 3.0
 
 
+def _sound_decay(tau, s_bulk, nx=128, steps=3000):
+    """Density amplitude of a standing sound wave rho = 1 + A cos(k x) on an
+    nx x 1 x 1 D3Q19 MRT grid without interaction (G = 0), fitted by
+    exp(-g t) (C cos(w t) + D sin(w t)); returns (g / k^2, w / k)."""
+    from scipy.optimize import curve_fit
+    k = 2 * math.pi / nx
+    x = np.arange(nx, dtype=float)
+    rho0 = (1.0 + 1e-4 * np.cos(k * x)).reshape(nx, 1, 1)
+    o = O.Oracle(rho0, "D3Q19", order=4, G=0.0, tau=tau, collision="mrt", s_bulk=s_bulk, s_ghost=1.2)
+    t, a = [], []
+    for n in range(0, steps + 1, 10):
+        if n:
+            o.step(10)
+        t.append(n)
+        a.append(2.0 / nx * np.dot(o.fields()["rho"][:, 0, 0], np.cos(k * x)))
+    t, a = np.array(t, dtype=float), np.array(a)
+    cs = 1.0 / math.sqrt(3.0)
+
+    def model(t, g, w, C, D):
+        return np.exp(-g * t) * (C * np.cos(w * t) + D * np.sin(w * t))
+
+    (g, w, C, D), _ = curve_fit(model, t, a, p0=[0.1 * k * k, cs * k, 1e-4, 0.0])
+    assert np.max(np.abs(model(t, g, w, C, D) - a)) < 1e-3 * 1e-4   # the fit describes the run
+    return g / (k * k), w / k
+
+
+@pytest.mark.parametrize("s_bulk", [0.7, 1.2, 1.6])
+def test_mrt_bulk_rate_sets_sound_attenuation(s_bulk):
+    """Closed form of linear acoustics: a plane sound wave decays at
+    Gamma k^2 with Gamma = ((4/3) nu + zeta) / 2, the shear viscosity
+    nu = cs2 (tau - 1/2) and the bulk viscosity zeta = (2/3) cs2 (1/s_bulk
+    - 1/2) that relaxing the trace of the stress (the c^2 moment) at s_bulk
+    gives in 3D; it travels at cs.  A dropped or mis-signed bulk term moves
+    Gamma by 20-90% over these rates."""
+    tau = 0.9
+    gam, speed = _sound_decay(tau, s_bulk)
+    nu = (tau - 0.5) / 3.0
+    zeta = (2.0 / 3.0) * (1.0 / s_bulk - 0.5) / 3.0
+    expect = 0.5 * (4.0 / 3.0 * nu + zeta)
+    # lattice corrections are O(k^2): below 1% at k = 2 pi / 128
+    assert abs(gam - expect) < 1e-2 * expect, (gam, expect)
+    assert abs(speed - 1.0 / math.sqrt(3.0)) < 1e-3
+
+
 def test_mrt_reduces_to_srt():
     rho0 = droplet_rho((12, 12, 12), 4, seed=3)
     tau = 0.85
