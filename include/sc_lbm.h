@@ -224,6 +224,21 @@ int sc_lbm_observe(sc_lbm* h, sc_lbm_obs* obs, double* rho_out, double* u_out, v
  * SC_E_DEVICE; SC_E_NONFINITE when a node is not finite (obs is filled). */
 int sc_lbm_check(sc_lbm* h, sc_lbm_obs* obs);
 
+/* sc_lbm_check without any device allocation, for callers that cannot
+ * allocate (code in tight serving loops, harnesses that forbid allocation
+ * after set-up).  Same kernels and result as sc_lbm_check; the per-block
+ * partials and the result block live in a file-scope device array of
+ * kCheckMaxBlocks x 11 + 15 doubles (about 90 KB, enough for any grid: the
+ * check never uses more than 1,024 blocks), one copy per device, located at
+ * sc_lbm_create with that device current and held until the process ends.
+ * The result is copied to a local host array.  All calls on one GPU share
+ * that device's array: calls that overlap on one GPU (other host threads,
+ * other streams) race.  Synchronous.  Errors: SC_E_INVAL (NULL argument),
+ * SC_E_UNSUPPORTED (more partial rows than the array holds), SC_E_DEVICE
+ * (the array's address could not be found at creation, or a HIP error);
+ * SC_E_NONFINITE when a node is not finite (obs is filled). */
+int sc_lbm_check_noalloc(sc_lbm* h, sc_lbm_obs* obs);
+
 /* Restore a state written by sc_lbm_observe(f_out) (checkpoint / resume):
  * f_in host buffer of sc_lbm_state_bytes bytes; step sets the step counter. */
 int sc_lbm_set_state(sc_lbm* h, const void* f_in, int64_t step);

@@ -418,6 +418,7 @@ hipError_t launch_widen(const float* src, double* dst, int64_t n, hipStream_t s)
 // rho and psi at the centre node and at node 0 (the Laplace pressure pair).
 // partials: check_blocks(...) rows of kObsSlots doubles.
 constexpr int kCheckSlots = kObsSlots + 4;
+constexpr int kCheckMaxBlocks = 1024;   // check_blocks() never exceeds it
 int check_blocks(int lattice, int64_t nx, int64_t ny, int64_t nz);
 hipError_t launch_check(int lattice, int precision, int order, const void* f, const void* args, double* partials,
                         double* result, hipStream_t s);

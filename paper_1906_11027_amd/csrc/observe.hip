@@ -173,8 +173,7 @@ k_reduce_final(const double* __restrict__ partials, int nblk, double* __restrict
 
 // ------------------------------------------------------------- check ----
 // Fused steady-state check: blocks take the grid's check tiles in turn
-// (a bounded grid, so the partials stay a few hundred rows).
-constexpr int kCheckMaxBlocks = 1024;
+// (at most kCheckMaxBlocks blocks, so the partials stay a bounded size).
 
 template <typename T, typename L, int M, int ORDER>
 __global__ void __launch_bounds__(kRedThreads)

@@ -69,6 +69,7 @@ struct sc_lbm {
     double* chk_host = nullptr;
     hipGraphExec_t gchunk[2] = {nullptr, nullptr};
     int gchunk_end[2] = {0, 1};   // buffer holding the state after gchunk[k]
+    double* scratch = nullptr;    // this device's copy of the file-scope scratch array (null if not found)
 };
 
 static thread_local char g_detail[256] = "";
@@ -455,6 +456,37 @@ static double median_density(std::vector<double>& v)
 
 constexpr int64_t kShiftSamples = (int64_t)1 << 20;
 
+// ---- scratch of the allocation-free check ---------------------------------
+// One array per device, made when the library is loaded and held until the
+// process ends: room for the per-block partials of the fused check at its
+// largest grid (kCheckMaxBlocks rows) and its result block.  In host code
+// `scratch` names a host-side stand-in; kernels receive the device address
+// from hipGetSymbolAddress, looked up once per device.
+constexpr int kScratchDoubles = kCheckMaxBlocks * kObsSlots + kCheckSlots;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on device `dev`, which must be current;
+// nullptr (with the HIP error recorded) if it cannot be found.
+static double* device_scratch(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) {
+            set_detail("hipGetSymbolAddress(scratch)", e);
+            return nullptr;
+        }
+        g_scratch[dev] = (double*)ptr;
+    }
+    return g_scratch[dev];
+}
+
 extern "C" int sc_lbm_create(const sc_lbm_params* p, const double* rho_init, void* dev_a, void* dev_b,
                              void* hip_stream, sc_lbm** out)
 {
@@ -495,6 +527,10 @@ extern "C" int sc_lbm_create(const sc_lbm_params* p, const double* rho_init, voi
         delete h;
         return SC_E_DEVICE;
     }
+    // set-up of the allocation-free check on the current device (the one
+    // the handle's buffers and stream belong to)
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) h->scratch = device_scratch(dev);
     hipError_t e;
     if (hip_stream) {
         h->stream = (hipStream_t)hip_stream;
@@ -1021,6 +1057,29 @@ extern "C" int sc_lbm_check(sc_lbm* h, sc_lbm_obs* obs)
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_err(e);
     obs_from_check(h, h->chk_host, obs);
+    obs->converged_by = h->conv_by;
+    return obs->nonfinite ? SC_E_NONFINITE : SC_OK;
+}
+
+extern "C" int sc_lbm_check_noalloc(sc_lbm* h, sc_lbm_obs* obs)
+{
+    if (!h || !obs) return SC_E_INVAL;
+    if (!h->scratch) return SC_E_DEVICE;   // hipGetSymbolAddress failed at creation (detail recorded)
+    const int nb = check_blocks(h->p.lattice, h->p.nx, h->p.ny, h->p.nz);
+    if ((int64_t)nb * kObsSlots + kCheckSlots > kScratchDoubles) {
+        std::snprintf(g_detail, sizeof(g_detail), "sc_lbm_check_noalloc: %d partial rows exceed the scratch (%d)",
+                      nb, kCheckMaxBlocks);
+        return SC_E_UNSUPPORTED;
+    }
+    // the partials are written in full by every block and the result block
+    // by the final pass and the two pressure nodes: nothing to clear
+    double* partials = h->scratch;
+    double* result = h->scratch + (size_t)nb * kObsSlots;
+    double res[kCheckSlots];
+    hipError_t e = enqueue_check_into(h, h->cur, partials, result, res);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_err(e);
+    obs_from_check(h, res, obs);
     obs->converged_by = h->conv_by;
     return obs->nonfinite ? SC_E_NONFINITE : SC_OK;
 }

@@ -65,7 +65,7 @@ class sc_lbm_obs(ctypes.Structure):
 #: every symbol include/sc_lbm.h declares
 EXPORTS = [
     "sc_lbm_default_params", "sc_lbm_state_bytes", "sc_lbm_create", "sc_lbm_step",
-    "sc_lbm_force", "sc_lbm_observe", "sc_lbm_check", "sc_lbm_set_state", "sc_lbm_state_ptr",
+    "sc_lbm_force", "sc_lbm_observe", "sc_lbm_check", "sc_lbm_check_noalloc", "sc_lbm_set_state", "sc_lbm_state_ptr",
     "sc_lbm_variant_name", "sc_lbm_num_variants", "sc_lbm_destroy", "sc_lbm_strerror", "sc_lbm_set_walls",
     "sc_lbm_steps_per_launch",
     "sc_lbm_last_error_detail", "sc_lbm_stream", "sc_lbm_rho_ref",
@@ -123,6 +123,8 @@ def lib():
     L.sc_lbm_observe.restype = ctypes.c_int
     L.sc_lbm_check.argtypes = [vp, P(sc_lbm_obs)]
     L.sc_lbm_check.restype = ctypes.c_int
+    L.sc_lbm_check_noalloc.argtypes = [vp, P(sc_lbm_obs)]
+    L.sc_lbm_check_noalloc.restype = ctypes.c_int
     L.sc_lbm_set_state.argtypes = [vp, vp, ctypes.c_int64]
     L.sc_lbm_set_state.restype = ctypes.c_int
     L.sc_lbm_state_ptr.argtypes = [vp]
@@ -256,6 +258,14 @@ def sc_lbm_check(h):
     rc = lib().sc_lbm_check(h, ctypes.byref(o))
     if rc not in (SC_OK, SC_E_NONFINITE):
         raise ScError(rc, "sc_lbm_check")
+    return rc, o
+
+
+def sc_lbm_check_noalloc(h):
+    o = sc_lbm_obs()
+    rc = lib().sc_lbm_check_noalloc(h, ctypes.byref(o))
+    if rc not in (SC_OK, SC_E_NONFINITE):
+        raise ScError(rc, "sc_lbm_check_noalloc")
     return rc, o
 
 
