@@ -314,7 +314,7 @@ typedef struct sc_lbm_batch sc_lbm_batch;
  *              0 one step per launch on 32 x 8 tiles, 1 / 2 / 3 two steps per
  *              launch (temporal blocking, one-step launches for an odd
  *              remainder) on 32 x 8, 64 x 16 and 32 x 16 tiles; any other
- *              value the automatic shape (2 for FP32, 1 for FP64);
+ *              value the automatic shape (3 for FP32, 1 for FP64);
  *   rho_init   n host pointers to [nx*ny] initial densities (each nullable),
  *              or NULL for rho = 1 everywhere;
  *   hip_stream as for sc_lbm_create.
@@ -356,8 +356,10 @@ double sc_lbm_batch_rho_ref(const sc_lbm_batch* b);
  * batch), SC_E_NOMEM, SC_E_DEVICE. */
 int sc_lbm_batch_promote(sc_lbm_batch* b);
 
-/* Name of the batched launch shape in use ("" on a NULL batch). */
+/* Name of the batched launch shape in use ("" on a NULL batch), and the
+ * number of batched launch shapes (values of items[0].variant). */
 const char* sc_lbm_batch_variant_name(const sc_lbm_batch* b);
+int32_t sc_lbm_batch_num_variants(void);
 
 void sc_lbm_batch_destroy(sc_lbm_batch* b);
 

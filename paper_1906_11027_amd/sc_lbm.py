@@ -70,7 +70,7 @@ EXPORTS = [
     "sc_lbm_steps_per_launch",
     "sc_lbm_last_error_detail", "sc_lbm_stream", "sc_lbm_rho_ref",
     "sc_lbm_batch_create", "sc_lbm_batch_step", "sc_lbm_batch_observe", "sc_lbm_batch_status",
-    "sc_lbm_batch_active", "sc_lbm_batch_rho_ref", "sc_lbm_batch_variant_name", "sc_lbm_batch_promote", "sc_lbm_batch_destroy", "sc_lbm_autotune",
+    "sc_lbm_batch_active", "sc_lbm_batch_rho_ref", "sc_lbm_batch_variant_name", "sc_lbm_batch_num_variants", "sc_lbm_batch_promote", "sc_lbm_batch_destroy", "sc_lbm_autotune",
     "sc_nn_conv3x3_fwd", "sc_nn_conv3x3_bwd_data", "sc_nn_bwd_weight_scratch_floats",
     "sc_nn_conv3x3_bwd_weight", "sc_nn_tanh_fwd", "sc_nn_tanh_bwd", "sc_nn_mse", "sc_nn_adam",
     "sc_nn_to_bf16", "sc_nn_features", "sc_nn_start_field",
@@ -180,6 +180,8 @@ def lib():
     L.sc_lbm_batch_rho_ref.restype = ctypes.c_double
     L.sc_lbm_batch_variant_name.argtypes = [vp]
     L.sc_lbm_batch_promote.argtypes = [vp]
+    L.sc_lbm_batch_num_variants.argtypes = []
+    L.sc_lbm_batch_num_variants.restype = ctypes.c_int32
     L.sc_lbm_batch_promote.restype = ctypes.c_int
     L.sc_lbm_batch_variant_name.restype = ctypes.c_char_p
     L.sc_lbm_last_error_detail.argtypes = []

@@ -2,14 +2,15 @@
 
 Tolerances.  FP32 state: density <= 1e-5 relative pointwise and velocity
 <= 1e-3 of max |u| (plus the FP32 momentum resolution, 1e-7 max rho, where
-max |u| is itself near round-off) up to 100 steps.  Beyond that the FP32 rounding drives a
-slow drift of the interface (measured: ~1e-5 at 200 steps, ~2e-4 at 3000,
-largest at interface nodes, for every storage shift), so long runs are
-compared on the observables the method reports (spurious max / mean |u|
-within 1e-3 relative, Laplace jump within 1e-4).  FP64 state: <= 1e-11
-pointwise at any horizon tested.  Launch shapes must agree bitwise, since
-every node's arithmetic is the same in every shape (a differing result
-would mean an LDS halo or indexing fault).
+max |u| is itself near round-off) up to 1,000 steps on the 64^2 droplet.
+With the default storage shift (the median density) the density error
+grows from ~1e-6 after one step to 1-7e-6 at 1,000 steps and ~9e-6 at
+2,000 (interface nodes: the interface position responds to the rounding),
+so longer runs are compared on the observables the method reports
+(spurious max / mean |u| within 1e-3 relative, Laplace jump within 1e-4).
+FP64 state: <= 1e-11 pointwise at any horizon tested.  Launch shapes agree
+to rounding (<= 1e-6 FP32, 1e-14 FP64): every node's arithmetic is the
+same, but the compiler contracts multiply-adds differently per shape.
 """
 import numpy as np
 import pytest
@@ -34,7 +35,9 @@ TOL = {"fp32": (1e-5, 1e-3), "fp64": (1e-11, 1e-9)}
 UFLOOR = {"fp32": 1e-7, "fp64": 1e-15}
 
 
-def _compare(sim, orc, prec, label):
+def _compare(sim, orc, prec, label, floor=True):
+    """floor=False: the velocity must meet the relative tolerance alone (the
+    absolute FP32 floor is not needed where max |u| is well above it)."""
     got = sim.observe()
     ref = orc.fields()
     er = rel_err(got["rho"], ref["rho"])
@@ -44,7 +47,7 @@ def _compare(sim, orc, prec, label):
     say("%s: rho rel err %.3e, u err / max|u| %.3e (max|u| %.3e)" % (label, er, eu, umax))
     tr, tu = TOL[prec]
     assert er <= tr, (label, er)
-    assert du <= tu * umax + UFLOOR[prec] * float(np.max(ref["rho"])), (label, eu)
+    assert du <= tu * umax + (UFLOOR[prec] * float(np.max(ref["rho"])) if floor else 0.0), (label, eu)
     return got, ref
 
 
@@ -53,15 +56,16 @@ def _compare(sim, orc, prec, label):
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 @pytest.mark.parametrize("order", [4, 6, 8, 10])
 def test_d2q9_droplet_64(order, prec):
-    """The 64^2 droplet (R = 16, G = -5, tau = 1) at a short horizon."""
+    """The 64^2 droplet (R = 16, G = -5, tau = 1) pointwise up to 1,000
+    steps, without the absolute velocity floor (max |u| ~ 5e-3 here)."""
     say("case d2q9 64x64 order", order, prec)
     rho0 = droplet_rho((64, 64), 16, seed=1)
     sim = Sim(rho0, "D2Q9", order=order, precision=prec)
     orc = O.Oracle(rho0, "D2Q9", order=order)
-    for steps in (1, 49, 50):
+    for steps in (1, 49, 50, 100, 300, 500):
         sim.step(steps)
         orc.step(steps)
-        _compare(sim, orc, prec, "E%d %s t=%d" % (order, prec, orc.steps))
+        _compare(sim, orc, prec, "E%d %s t=%d" % (order, prec, orc.steps), floor=False)
     sim.close()
 
 
