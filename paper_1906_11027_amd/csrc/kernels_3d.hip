@@ -171,6 +171,129 @@ k_d3q19_march(StepArgs<T> a, int H, int nbx, int nby)
     }
 }
 
+// The same z-march without the register window: a tile node's 19 values are
+// pulled twice, once when its plane enters the psi ring and again when the
+// plane collides R planes later (then L2 hits: the block read those lines
+// R planes before).  The window of R + 1 planes of 19 values is what holds
+// k_d3q19_march at two waves per SIMD; without it the kernel fits WPE waves
+// per SIMD, so more loads are in flight to cover their latency.  The same
+// sum of the same 19 loaded values gives rho in both places, so psi and
+// the collision see one density, as in k_d3q19_march.  One thread per
+// column (TX x TY threads).
+template <typename T, int ORDER, bool MRT, int TX, int TY, int WPE>
+__global__ void __launch_bounds__(TX* TY, sizeof(T) == 8 ? (WPE + 1) / 2 : WPE)
+k_d3q19_march_rl(StepArgs<T> a, int H, int nbx, int nby)
+{
+    using ST = Stencil<3, ORDER>;
+    constexpr int R = ST::R;
+    constexpr int LW = TX + 2 * R;
+    constexpr int LH = TY + 2 * R;
+    constexpr int PL = LW * LH;
+    constexpr int NS = 2 * R + 2;
+    constexpr int NT = TX * TY;
+    constexpr int RING = PL - TX * TY;
+    constexpr int RPERT = (RING + NT - 1) / NT;
+    __shared__ T psi_s[NS * PL];
+
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int64_t n = a.n;
+    const uint32_t TS = sizeof(T), rowb = (uint32_t)nx * TS, planeb = (uint32_t)ny * rowb;
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int tid = ty * TX + tx;
+    const int L = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int x0 = (L % nbx) * TX, y0 = ((L / nbx) % nby) * TY, z0 = (L / (nbx * nby)) * H;
+
+    const int xr = x0 + tx, yr = y0 + ty;
+    const bool inxy = xr < nx && yr < ny;
+    uint32_t xo[3], yo[3];
+    nbr_offsets<T>(xr < nx ? xr : xr % nx, nx, TS, xo);
+    nbr_offsets<T>(yr < ny ? yr : yr % ny, ny, rowb, yo);
+    int rl[RPERT];
+    uint32_t rxo[RPERT][3], ryo[RPERT][3];
+#pragma unroll
+    for (int q = 0; q < RPERT; ++q) {
+        const int i = tid + q * NT;
+        int lx = 0, ly = 0;
+        if (i < R * LW) {
+            ly = i / LW;
+            lx = i - ly * LW;
+        } else if (i < 2 * R * LW) {
+            const int jj = i - R * LW;
+            ly = TY + R + jj / LW;
+            lx = jj % LW;
+        } else if (i < RING) {
+            const int jj = i - 2 * R * LW;
+            ly = R + jj / (2 * R);
+            const int c = jj % (2 * R);
+            lx = c < R ? c : TX + c;
+        }
+        rl[q] = i < RING ? ly * LW + lx : -1;
+        nbr_offsets<T>(wrap_near(x0 - R + lx, nx), nx, TS, rxo[q]);
+        nbr_offsets<T>(wrap_near(y0 - R + ly, ny), ny, rowb, ryo[q]);
+    }
+
+    const int cidx = (ty + R) * LW + tx + R;
+    const int nplanes = H + 2 * R;
+    int zp = wrap_any(z0 - R, nz);   // plane entering the psi ring
+    for (int j = 0; j < nplanes; ++j) {
+        const bool col = j >= 2 * R;
+        const int zr = z0 + j - 2 * R;   // plane that collides in this pass
+        T gc[19];
+        if (col) {   // uniform across the block
+            uint32_t zo[3];
+            nbr_offsets<T>(zr < nz ? zr : zr - nz, nz, planeb, zo);
+            pull_d3q19(a.fin, n, 0u, zo, yo, xo, gc);
+        }
+        {
+            T gt[19], h[RPERT][19];
+            uint32_t zo[3];
+            nbr_offsets<T>(zp, nz, planeb, zo);
+            pull_d3q19(a.fin, n, 0u, zo, yo, xo, gt);
+#pragma unroll
+            for (int q = 0; q < RPERT; ++q)
+                if (rl[q] >= 0) pull_d3q19(a.fin, n, 0u, zo, ryo[q], rxo[q], h[q]);
+            T* slot = psi_s + (j % NS) * PL;
+            slot[cidx] = psi_of(a.rho_ref + sum19(gt), a);
+#pragma unroll
+            for (int q = 0; q < RPERT; ++q)
+                if (rl[q] >= 0) slot[rl[q]] = psi_of(a.rho_ref + sum19(h[q]), a);
+        }
+        zp = zp == nz - 1 ? 0 : zp + 1;
+        __syncthreads();
+        if (col) {
+            int sl[2 * R + 1];
+#pragma unroll
+            for (int d = -R; d <= R; ++d) sl[d + R] = ((j - R + d) % NS) * PL;
+            T sx = T(0), sy = T(0), sz = T(0), ax = T(0), ay = T(0), az = T(0);
+#pragma unroll
+            for (int p = 0; p < ST::NP; ++p) {
+                constexpr PairList P = ST::P;
+                if (p % 8 == 0 && p) __builtin_amdgcn_sched_barrier(0);
+                const int ex = P.e[p][0], ey = P.e[p][1], ez = P.e[p][2];
+                const T vp = psi_s[sl[R + ez] + cidx + ey * LW + ex];
+                const T vm = psi_s[sl[R - ez] + cidx - ey * LW - ex];
+                const T d = vp - vm;
+                if (ex) ax += T(ex) * d;
+                if (ey) ay += T(ey) * d;
+                if (ez) az += T(ez) * d;
+                if (P.shell_end(p)) {
+                    sx += T(P.w[p]) * ax;
+                    sy += T(P.w[p]) * ay;
+                    sz += T(P.w[p]) * az;
+                    ax = ay = az = T(0);
+                }
+            }
+            const T pref = -a.gc0 * psi_s[sl[R] + cidx];
+            collide_d3q19<T, MRT>(gc, sum19(gc), pref * sx, pref * sy, pref * sz, a);
+            if (inxy && zr < nz) {
+                const uint32_t off = (uint32_t)zr * planeb + yo[1] + xo[1];
+#pragma unroll
+                for (int b = 0; b < 19; ++b) st_off(a.fout + b * n, off, gc[b]);
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------ dispatch ----
 struct Shape3D {
     int tx, tyb, rpt, h;
@@ -195,6 +318,12 @@ static const Shape3D kShapes3D[] = {
     {64, 12, 1, 64, "march64x12r1h64pf1"},
     {64, 12, 1, 32, "march64x12r1h32pf1"},
     {64, 12, 1, 16, "march64x12r1h16pf1"},
+    // k_d3q19_march_rl (pulls twice, no register window); rpt holds the
+    // waves per SIMD the FP32 kernel is built for (FP64: half, rounded up).
+    // At 320^3 the FP64 state runs 3-5% faster than on any window shape;
+    // the FP32 state 25% slower (the second pulls miss L2 in part)
+    {64, 8, 4, 64, "rl64x8h64w4"},
+    {64, 8, 4, 32, "rl64x8h32w4"},
 };
 constexpr int kNumShapes3D = sizeof(kShapes3D) / sizeof(kShapes3D[0]);
 
@@ -210,6 +339,16 @@ static hipError_t launch_march(const StepArgs<T>& a, int H, hipStream_t s)
     const int nbz = (a.nz + H - 1) / H;
     hipLaunchKernelGGL((k_d3q19_march<T, ORDER, MRT, TX, TYB, RPT, PF>), dim3(nbx * nby * nbz), block, 0, s,
                        a, H, nbx, nby);
+    return hipGetLastError();
+}
+
+template <typename T, int ORDER, bool MRT, int TX, int TY, int WPE>
+static hipError_t launch_march_rl(const StepArgs<T>& a, int H, hipStream_t s)
+{
+    if (H > a.nz) H = a.nz;
+    const int nbx = (a.nx + TX - 1) / TX, nby = (a.ny + TY - 1) / TY, nbz = (a.nz + H - 1) / H;
+    hipLaunchKernelGGL((k_d3q19_march_rl<T, ORDER, MRT, TX, TY, WPE>), dim3(nbx * nby * nbz), dim3(TX, TY), 0, s, a,
+                       H, nbx, nby);
     return hipGetLastError();
 }
 
@@ -234,6 +373,8 @@ static hipError_t launch_v(const StepArgs<T>& a, int variant, hipStream_t s)
     case 13: return launch_march<T, ORDER, MRT, 64, 12, 1, 1>(a, 64, s);
     case 14: return launch_march<T, ORDER, MRT, 64, 12, 1, 1>(a, 32, s);
     case 15: return launch_march<T, ORDER, MRT, 64, 12, 1, 1>(a, 16, s);
+    case 16: return launch_march_rl<T, ORDER, MRT, 64, 8, 4>(a, 64, s);
+    case 17: return launch_march_rl<T, ORDER, MRT, 64, 8, 4>(a, 32, s);
     default: return hipErrorInvalidValue;
     }
 }
