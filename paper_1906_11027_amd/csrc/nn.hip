@@ -6,14 +6,23 @@
 // bfloat16 for compute (FP32 master copy for the optimiser); every product
 // accumulates in FP32.  Padding is circular (the droplet domain is periodic).
 //
-// conv3x3 forward: a block computes a 16 x 16 pixel tile of one image for all
-// (<= 32) output channels; input channels stream through LDS in chunks of 8
-// (an 18 x 18 halo tile per channel) together with the matching weights; each
-// thread keeps its pixel's Cout accumulators in registers.  Backward-data is
-// the same kernel applied to the channel-transposed, spatially flipped
-// weights.  Backward-weight accumulates per-block partial sums over a fixed
-// share of (tile, image) pairs (a 32 x 288 x 256 contraction per pair), then a
-// column reduction sums the partials in a fixed order (deterministic).
+// The 3 x 3 convolutions are dense contractions and run on the matrix cores:
+//   forward (32 output channels): per 16 x 16 pixel tile, out[p][co] =
+//     sum over 9 taps of x_t[p][ci] W_t[ci][co], one 16 x 16 x 32 bf16 MFMA
+//     per (16 pixels, 16 channels, tap).  The FP32 activations enter as the
+//     exact sum of three bf16 parts (hi + mid + lo, 8 significant bits each),
+//     so each product is the FP32 activation times the bf16 weight, exact,
+//     accumulated in FP32 -- three MFMAs per product, the price of keeping the
+//     activations in full FP32.
+//   backward-data: the forward kernel on the channel-transposed, spatially
+//     flipped weights.
+//   backward-weight: gW_t[co][ci] = sum_p g[co][p] x[ci][p + d_t], a
+//     contraction over pixels, on FP32 16 x 16 x 4 MFMAs (both operands FP32:
+//     no splitting of the output gradient).  Per-block partial sums over a
+//     fixed share of (tile, image) pairs, then a column reduction in a fixed
+//     order (deterministic).
+// The one-output-channel forward (the net's last layer) stays on the vector
+// ALU: a 288-term dot product per pixel.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -103,6 +112,147 @@ k_conv_fwd(const float* __restrict__ in, const uint16_t* __restrict__ w, const f
     }
 }
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// exact split of an FP32 value into three bf16 parts, v = hi + mid + lo:
+// each part truncates the remainder to its top 8 significant bits, and the
+// remainders are exact differences, so 24 bits are carried in all
+__device__ __forceinline__ void split3(float v, uint32_t& hi, uint32_t& mid, uint32_t& lo)
+{
+    const uint32_t u = __float_as_uint(v);
+    const float r1 = v - __uint_as_float(u & 0xffff0000u);
+    const uint32_t u1 = __float_as_uint(r1);
+    const float r2 = r1 - __uint_as_float(u1 & 0xffff0000u);
+    hi = u >> 16;
+    mid = u1 >> 16;
+    lo = __float_as_uint(r2) >> 16;
+}
+
+constexpr int kHaloPx = (TS + 2) * (TS + 2);   // pixels of a tile with its halo
+constexpr int kPxSlot = 32;                     // bf16 per pixel (or weight row) in LDS: 64 B
+constexpr int kPartBf = kHaloPx * kPxSlot;      // one bf16 part of the input tile
+
+// LDS slot s holds 32 bf16 channels as four 16-byte chunks; chunk k is
+// stored at position k ^ ((s >> 2) & 3).  A quarter-wave reads one chunk of
+// 16 consecutive slots, which then fall on 16 distinct bank quads.
+__device__ __forceinline__ int slot_chunk(int s, int k) { return (k ^ (s >> 2)) & 3; }
+
+// Forward 3 x 3 convolution to 32 output channels on bf16 MFMAs.  A block
+// (4 waves) takes (image, 16 x 16 tile) work items in turn; wave v computes
+// tile rows 4v .. 4v+3.  LDS holds the input tile (halo 1, channels padded
+// to 32 with zeros) as three bf16 parts, pixel-major with the channels
+// contiguous, and the weights as [tap][co][ci] bf16, staged once per block
+// (80,640 B in all: two blocks share a CU, so one stages while the other
+// multiplies).  The tile's global loads are all issued before any is used:
+// one round trip per tile.  MFMA operands (16 x 16 x 32):
+// lane l supplies row or column l % 16 and the 8 consecutive k = 8 (l / 16)
+// ...; its accumulator holds rows 4 (l / 16) + i, column l % 16.  Here rows
+// are the pixels of a 16-pixel row segment, columns output channels and k
+// input channels.
+constexpr int kFwdStage = ((MAXC / 2) * kHaloPx + TS * TS - 1) / (TS * TS);   // staging loads per thread
+
+__global__ void __launch_bounds__(TS* TS, 2)
+k_conv_fwd_mfma(const float* __restrict__ in, const uint16_t* __restrict__ w, const float* __restrict__ bias,
+                float* __restrict__ out, int batch, int cin, int h, int wd)
+{
+    __shared__ __align__(16) uint16_t xs[3 * kPartBf];
+    __shared__ __align__(16) uint16_t wsl[9 * MAXC * kPxSlot];
+    const int tid = threadIdx.y * TS + threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int r16 = lane & 15, kq = lane >> 4;
+    const int tiles_x = (wd + TS - 1) / TS, tiles = tiles_x * ((h + TS - 1) / TS);
+    const int nwork = tiles * batch;
+    const int64_t plane = (int64_t)h * wd;
+
+    for (int j = tid; j < 9 * MAXC * MAXC; j += TS * TS) {
+        const int t = j >> 10, co = (j >> 5) & 31, ci = j & 31;
+        const int sl = t * MAXC + co;
+        wsl[sl * kPxSlot + slot_chunk(sl, ci >> 3) * 8 + (ci & 7)] =
+            ci < cin ? w[((int64_t)co * cin + ci) * 9 + t] : (uint16_t)0;
+    }
+    float bv[2];
+#pragma unroll
+    for (int n = 0; n < 2; ++n) bv[n] = bias ? bias[n * 16 + r16] : 0.f;
+
+    for (int wi = blockIdx.x; wi < nwork; wi += gridDim.x) {
+        const int b = wi / tiles, tt = wi - b * tiles;
+        const int x0 = (tt % tiles_x) * TS, y0 = (tt / tiles_x) * TS;
+        const float* inb = in + (int64_t)b * cin * plane;
+        float v0[kFwdStage], v1[kFwdStage];
+#pragma unroll
+        for (int q = 0; q < kFwdStage; ++q) {
+            const int j = tid + q * TS * TS;
+            v0[q] = v1[q] = 0.f;
+            if (j < (MAXC / 2) * kHaloPx) {
+                const int pr = j / kHaloPx, px = j - pr * kHaloPx;
+                const int ly = px / (TS + 2), lx = px - ly * (TS + 2);
+                // 32-bit element offsets within the image (checked on the host)
+                const uint32_t g = (uint32_t)(wrapc(y0 + ly - 1, h) * wd + wrapc(x0 + lx - 1, wd));
+                const uint32_t c = 2 * pr;
+                if ((int)c < cin) v0[q] = inb[c * (uint32_t)plane + g];
+                if ((int)c + 1 < cin) v1[q] = inb[(c + 1) * (uint32_t)plane + g];
+            }
+        }
+        __syncthreads();   // the previous item's reads of xs are done
+#pragma unroll
+        for (int q = 0; q < kFwdStage; ++q) {
+            const int j = tid + q * TS * TS;
+            if (j < (MAXC / 2) * kHaloPx) {
+                const int pr = j / kHaloPx, px = j - pr * kHaloPx;
+                uint32_t h0, m0, l0, h1, m1, l1;
+                split3(v0[q], h0, m0, l0);
+                split3(v1[q], h1, m1, l1);
+                uint32_t* d = (uint32_t*)(xs + px * kPxSlot + slot_chunk(px, pr >> 2) * 8 + 2 * (pr & 3));
+                d[0] = h0 | (h1 << 16);
+                d[kPartBf / 2] = m0 | (m1 << 16);
+                d[kPartBf] = l0 | (l1 << 16);
+            }
+        }
+        __syncthreads();
+
+        f32x4 acc[4][2];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int n = 0; n < 2; ++n) acc[r][n] = f32x4{bv[n], bv[n], bv[n], bv[n]};
+#pragma unroll 1
+        for (int t = 0; t < 9; ++t) {   // rolled: unrolled, the scheduler hoists too many LDS reads
+            const int dy = t / 3, dx = t % 3;
+            const int s0 = t * MAXC + r16, s1 = s0 + 16;
+            const bf16x8 b0 = *(const bf16x8*)(wsl + s0 * kPxSlot + slot_chunk(s0, kq) * 8);
+            const bf16x8 b1 = *(const bf16x8*)(wsl + s1 * kPxSlot + slot_chunk(s1, kq) * 8);
+#pragma unroll
+            for (int part = 0; part < 3; ++part)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int px = (4 * wv + r + dy) * (TS + 2) + r16 + dx;
+                    const bf16x8 a = *(const bf16x8*)(xs + part * kPartBf + px * kPxSlot + slot_chunk(px, kq) * 8);
+                    acc[r][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b0, acc[r][0], 0, 0, 0);
+                    acc[r][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b1, acc[r][1], 0, 0, 0);
+                }
+        }
+        const int xq = x0 + 4 * kq;
+        const bool vec = (wd & 3) == 0 && xq + 3 < wd;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int y = y0 + 4 * wv + r;
+            if (y >= h) continue;
+#pragma unroll
+            for (int n = 0; n < 2; ++n) {
+                float* o = out + ((int64_t)b * MAXC + n * 16 + r16) * plane + (int64_t)y * wd + xq;
+                if (vec) {
+                    *(float4*)o = make_float4(acc[r][n][0], acc[r][n][1], acc[r][n][2], acc[r][n][3]);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (xq + i < wd) o[i] = acc[r][n][i];
+                }
+            }
+        }
+    }
+}
+
 // wt[ci][co][8 - k] = w[co][ci][k]
 __global__ void k_transpose_flip(const uint16_t* __restrict__ w, uint16_t* __restrict__ wt, int cin, int cout)
 {
@@ -113,86 +263,101 @@ __global__ void k_transpose_flip(const uint16_t* __restrict__ w, uint16_t* __res
 }
 
 // partial[blk][(ci*cout + co)*9 + k] and partial[blk][E + co] (bias): the
-// block's share of (tile, image) pairs.  Per pair the gradient is a small
-// contraction over the tile's pixels p, gw[co][ci][k] += g[co][p] in[ci][p+k];
-// thread (cog, ci) = (tid / 32, tid % 32) owns 4 output channels x 9 taps of
-// one input channel, so each pixel costs 4 + 9 LDS reads for 36 FMAs.  The
-// input tile holds every channel, one plane of 18 x 19 + 1 floats each (an
-// odd stride: the 32 channels a half-wave reads sit in 32 different banks).
-constexpr int TPL = (TS + 2) * (TS + 3) + 1;   // floats per input-channel plane in LDS
+// block's share of (tile, image) pairs.  Per pair and tap t the gradient is a
+// contraction over the tile's 256 pixels, gW_t[co][ci] += g[co][p] x[ci][p +
+// d_t], on FP32 16 x 16 x 4 MFMAs: wave v owns the 16 x 16 block (co tile
+// v / 2, ci tile v % 2) of all nine taps (36 accumulator registers); k runs
+// over 4 consecutive pixels of a tile row.  LDS holds the output-gradient
+// tile [co][260] and the input tile with its halo [ci][18 x 18], both FP32;
+// the row strides (4 and 4 mod 64 banks) keep the 16 channel rows a
+// quarter-wave reads in distinct banks.
+constexpr int kGStride = TS * TS + 4;      // floats per output-gradient channel in LDS
+constexpr int kXStride = kHaloPx;          // floats per input channel in LDS (324 = 4 mod 64)
+constexpr int kBwdStage = (MAXC * kHaloPx + TS * TS - 1) / (TS * TS);   // input-tile loads per thread
 
-__global__ void __launch_bounds__(TS* TS)
+__global__ void __launch_bounds__(TS* TS, 2)
 k_conv_bwd_w(const float* __restrict__ in, const float* __restrict__ gout, float* __restrict__ partial, int batch,
              int cin, int cout, int h, int wd)
 {
-    __shared__ float tile[MAXC * TPL];
-    __shared__ float gs[MAXC][TS * TS];
+    __shared__ float gs[MAXC * kGStride];
+    __shared__ float xs[MAXC * kXStride];
     const int tid = threadIdx.y * TS + threadIdx.x;
-    const int ci = tid % MAXC, cog = tid / MAXC;   // 8 groups of 4 output channels
+    const int lane = tid & 63, wv = tid >> 6;
+    const int mt = wv >> 1, nt = wv & 1;   // co tile, ci tile of this wave
+    const int r16 = lane & 15, kq = lane >> 4;
     const int tiles_x = (wd + TS - 1) / TS, tiles_y = (h + TS - 1) / TS;
     const int nwork = tiles_x * tiles_y * batch;
     const int64_t plane = (int64_t)h * wd;
     const int E = cout * cin * 9;
-    float acc[4][9];
+    f32x4 acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
     float bacc = 0.f;
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int k = 0; k < 9; ++k) acc[j][k] = 0.f;
     for (int wi = blockIdx.x; wi < nwork; wi += gridDim.x) {
-        const int b = wi / (tiles_x * tiles_y), t = wi % (tiles_x * tiles_y);
-        const int x0 = (t % tiles_x) * TS, y0 = (t / tiles_x) * TS;
+        const int b = wi / (tiles_x * tiles_y), tt = wi % (tiles_x * tiles_y);
+        const int x0 = (tt % tiles_x) * TS, y0 = (tt / tiles_x) * TS;
         // output-gradient tile, every channel (zero outside the image and
-        // for channels beyond cout)
-        for (int i = tid; i < MAXC * TS * TS; i += TS * TS) {
-            const int co = i / (TS * TS), p = i % (TS * TS);
-            const int x = x0 + p % TS, y = y0 + p / TS;
-            gs[co][p] = (co < cout && x < wd && y < h) ? gout[((int64_t)b * cout + co) * plane + (int64_t)y * wd + x]
-                                                       : 0.f;
+        // for channels beyond cout), and the input tile with a wrapped halo
+        // of one (zero for channels beyond cin): every load issued first
+        float gv[MAXC], xv[kBwdStage];
+        // 32-bit element offsets within the image (checked on the host)
+        const float* gb = gout + (int64_t)b * cout * plane;
+        const float* xb0 = in + (int64_t)b * cin * plane;
+        {
+            const int x = x0 + tid % TS, y = y0 + tid / TS;
+            const bool in_img = x < wd && y < h;
+            const uint32_t po = (uint32_t)(y * wd + x);
+#pragma unroll
+            for (int co = 0; co < MAXC; ++co)
+                gv[co] = (co < cout && in_img) ? gb[(uint32_t)co * (uint32_t)plane + po] : 0.f;
         }
-        // input tile with a wrapped halo of one, every channel
-        for (int i = tid; i < cin * (TS + 2) * (TS + 2); i += TS * TS) {
-            const int c = i / ((TS + 2) * (TS + 2));
-            const int r = i % ((TS + 2) * (TS + 2));
-            const int ly = r / (TS + 2), lx = r % (TS + 2);
-            const int gy = wrapc(y0 + ly - 1, h), gx = wrapc(x0 + lx - 1, wd);
-            tile[c * TPL + ly * (TS + 3) + lx] = in[((int64_t)b * cin + c) * plane + (int64_t)gy * wd + gx];
+#pragma unroll
+        for (int q = 0; q < kBwdStage; ++q) {
+            const int i = tid + q * TS * TS;
+            xv[q] = 0.f;
+            if (i < MAXC * kHaloPx) {
+                const int c = i / kHaloPx, r = i - c * kHaloPx;
+                const int ly = r / (TS + 2), lx = r - ly * (TS + 2);
+                if (c < cin)
+                    xv[q] = xb0[(uint32_t)c * (uint32_t)plane +
+                                (uint32_t)(wrapc(y0 + ly - 1, h) * wd + wrapc(x0 + lx - 1, wd))];
+            }
+        }
+        __syncthreads();   // the previous item's reads of gs and xs are done
+#pragma unroll
+        for (int co = 0; co < MAXC; ++co) gs[co * kGStride + tid] = gv[co];
+#pragma unroll
+        for (int q = 0; q < kBwdStage; ++q) {
+            const int i = tid + q * TS * TS;
+            if (i < MAXC * kHaloPx) xs[i] = xv[q];   // kXStride == kHaloPx: channel-major, contiguous
         }
         __syncthreads();
         if (tid < cout) {
             float sb = 0.f;
-            for (int p = 0; p < TS * TS; ++p) sb += gs[tid][p];
+            for (int p = 0; p < TS * TS; ++p) sb += gs[tid * kGStride + p];
             bacc += sb;
         }
-        if (ci < cin && cog * 4 < cout) {
-            const float* tc = tile + ci * TPL;
-            for (int py = 0; py < TS; ++py) {
-#pragma unroll 4
-                for (int px = 0; px < TS; ++px) {
-                    const int p = py * TS + px;
-                    float g[4], v[9];
+        const float* ga = gs + (mt * 16 + r16) * kGStride;
+        const float* xb = xs + (nt * 16 + r16) * kXStride;
+#pragma unroll 2
+        for (int ks = 0; ks < TS * TS / 4; ++ks) {
+            const int p = 4 * ks + kq;             // pixel of this lane's k
+            const int hp = (p / TS) * (TS + 2) + p % TS;   // its halo index at tap (0, 0)
+            const float av = ga[p];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) g[j] = gs[cog * 4 + j][p];
-#pragma unroll
-                    for (int k = 0; k < 9; ++k) v[k] = tc[(py + k / 3) * (TS + 3) + px + k % 3];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-#pragma unroll
-                        for (int k = 0; k < 9; ++k) acc[j][k] += g[j] * v[k];
-                }
-            }
+            for (int t = 0; t < 9; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, xb[hp + (t / 3) * (TS + 2) + t % 3], acc[t], 0, 0,
+                                                              0);
         }
-        __syncthreads();
     }
     float* pb = partial + (int64_t)blockIdx.x * (E + cout);
-    if (ci < cin) {
+    const int ci = nt * 16 + r16;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int co = cog * 4 + j;
-            if (co < cout)
+    for (int i = 0; i < 4; ++i) {
+        const int co = mt * 16 + 4 * kq + i;
+        if (ci < cin && co < cout)
 #pragma unroll
-                for (int k = 0; k < 9; ++k) pb[(ci * cout + co) * 9 + k] = acc[j][k];
-        }
+            for (int t = 0; t < 9; ++t) pb[(ci * cout + co) * 9 + t] = acc[t][i];
     }
     if (tid < cout) pb[E + tid] = bacc;
 }
@@ -361,10 +526,26 @@ using namespace sclbm::nn;
 
 static int nn_status(hipError_t e) { return e == hipSuccess ? SC_OK : SC_E_DEVICE; }
 
+// compute units of the current device (cached per device): the persistent
+// forward kernel runs two blocks per CU
+static int cu_count()
+{
+    static int cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cache[dev]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 256;
+        cache[dev] = n;
+    }
+    return cache[dev];
+}
+
+// the MFMA kernels address an image's channels with 32-bit element offsets
 static bool conv_shape_ok(int batch, int cin, int cout, int h, int w)
 {
     return batch >= 1 && cin >= 1 && cin <= MAXC && (cout == 1 || cout == MAXC) && h >= 1 && w >= 1 &&
-           batch <= 65535;
+           batch <= 65535 && (int64_t)h * w * MAXC < ((int64_t)1 << 31);
 }
 
 extern "C" int sc_nn_conv3x3_fwd(const float* in, const uint16_t* w, const float* bias, float* out, int32_t batch,
@@ -373,9 +554,12 @@ extern "C" int sc_nn_conv3x3_fwd(const float* in, const uint16_t* w, const float
     if (!in || !w || !out || !conv_shape_ok(batch, cin, cout, h, wd)) return SC_E_INVAL;
     const int tiles = ((wd + TS - 1) / TS) * ((h + TS - 1) / TS);
     dim3 grid(tiles, batch), block(TS, TS);
-    if (cout == MAXC)
-        hipLaunchKernelGGL(k_conv_fwd<MAXC>, grid, block, 0, (hipStream_t)stream, in, w, bias, out, cin, cout, h, wd);
-    else
+    if (cout == MAXC) {
+        const int64_t nwork = (int64_t)tiles * batch;
+        const int nb = (int)(nwork < 2 * cu_count() ? nwork : 2 * cu_count());
+        hipLaunchKernelGGL(k_conv_fwd_mfma, dim3(nb), block, 0, (hipStream_t)stream, in, w, bias, out, batch, cin, h,
+                           wd);
+    } else
         hipLaunchKernelGGL(k_conv_fwd<1>, grid, block, 0, (hipStream_t)stream, in, w, bias, out, cin, cout, h, wd);
     return nn_status(hipGetLastError());
 }

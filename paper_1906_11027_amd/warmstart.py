@@ -97,9 +97,12 @@ class WarmStartNet:
 
     # -------------------------------------------------------------- passes --
     def set_params(self, prm_rows):
-        """prm_rows: [batch][4] normalised parameters (numpy)."""
-        t = self.torch.tensor(np.asarray(prm_rows, dtype=np.float32), device=self.dev)
-        self.prm.copy_(t)
+        """prm_rows: [batch][4] normalised parameters (numpy, or a float32
+        device tensor, which is then used without a host round trip)."""
+        if isinstance(prm_rows, self.torch.Tensor):
+            self.prm.copy_(prm_rows)
+        else:
+            self.prm.copy_(self.torch.tensor(np.asarray(prm_rows, dtype=np.float32), device=self.dev))
         self._chk(B.lib().sc_nn_features(self.prm.data_ptr(), self.acts[0].data_ptr(), self.batch, self.h, self.w,
                                          SCALE_R, self.stream), "sc_nn_features")
 
@@ -177,27 +180,34 @@ def steady_states(items, tol=1e-9, max_steps=200000, obs_every=100, stream=None)
 
 
 def train(net, inputs, targets, epochs=20, lr=2e-3, log=None, seed=0):
-    """inputs: [N][4] normalised parameters; targets: [N][h][w] densities."""
+    """inputs: [N][4] normalised parameters; targets: [N][h][w] densities.
+
+    The whole training set stays in device memory; each epoch's mini-batches
+    are gathered there in a shuffled order, and the loss partials of every
+    mini-batch are kept on the device and read back once per epoch, so the
+    host never waits on the GPU inside an epoch."""
     torch = net.torch
     n = len(inputs)
-    tgt_host = np.asarray(targets, dtype=np.float32)[:, None]
+    tgt_dev = torch.tensor(np.asarray(targets, dtype=np.float32)[:, None], device=net.dev)
+    inp_dev = torch.tensor(np.asarray(inputs, dtype=np.float32), device=net.dev)
+    nbat = n // net.batch
+    loss_rows = torch.zeros((max(nbat, 1), net.nblk_mse), dtype=torch.float64, device=net.dev)
+    tgt = torch.empty((net.batch, 1, net.h, net.w), dtype=torch.float32, device=net.dev)
     rng = np.random.default_rng(seed)
     hist = []
     for ep in range(epochs):
-        order = rng.permutation(n)
-        tot = 0.0
-        nb = 0
-        for s in range(0, n - net.batch + 1, net.batch):
-            idx = order[s:s + net.batch]
-            net.set_params(np.asarray(inputs)[idx])
+        order = torch.tensor(rng.permutation(n)[:nbat * net.batch].reshape(nbat, net.batch), device=net.dev)
+        for k in range(nbat):
+            idx = order[k]
+            net.set_params(inp_dev.index_select(0, idx))
             net.forward()
-            tgt = torch.tensor(np.ascontiguousarray(tgt_host[idx]), device=net.dev)
+            torch.index_select(tgt_dev, 0, idx, out=tgt)
             part = net.loss_and_grad(tgt)
             net.backward()
             net.adam(lr=lr * (0.5 ** (ep // max(1, epochs // 3))))
-            tot += float(part.cpu().numpy().sum()) / (net.batch * net.h * net.w)
-            nb += 1
-        hist.append(tot / max(nb, 1))
+            loss_rows[k].copy_(part)
+        tot = float(loss_rows[:nbat].sum().item()) / (net.batch * net.h * net.w) if nbat else 0.0
+        hist.append(tot / max(nbat, 1))
         if log:
             log("epoch %d loss %.3e" % (ep, hist[-1]))
     return hist
