@@ -292,19 +292,21 @@ def _sweep_items():
 
 def batched_sweep(steps=200):
     """64 droplets drawn like the sweep configuration (sides 64..512, R, G,
-    tau, stencil order per item) advanced together, in every batched launch
-    shape (the automatic one first)."""
+    tau, stencil order per item) advanced together: the batched shape tuner's
+    choice, then every batched launch shape."""
     import torch
 
-    from paper_1906_11027_amd import Batch
+    from paper_1906_11027_amd import Batch, batch_autotune
     from paper_1906_11027_amd import sc_lbm as B
 
     _, items = _sweep_items()
     nodes = sum(it["rho0"].size for it in items)
+    tuned, tuned_ms = batch_autotune(items, steps=64)
+    log("batch autotune: variant %d, %.4f ms/step" % (tuned, tuned_ms))
     st = torch.cuda.Stream()
     shapes = {}
     auto = None
-    for v in [-1] + list(range(B.lib().sc_lbm_batch_num_variants())):
+    for v in [tuned] + list(range(B.lib().sc_lbm_batch_num_variants())):
         bt = Batch(items, stream=st, variant=v)
         name = bt.variant
         bt.step(20)
@@ -317,17 +319,18 @@ def batched_sweep(steps=200):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
         bt.close()
-        if v == -1:
+        if auto is None:
             auto = (name, ms)
         else:
             shapes[name] = round(nodes / ms / 1e3, 1)
     name, ms = auto
     return {"workload": "64 D2Q9 droplets, sides U{64..512}, R, G, tau, order per item (PCG64 seed 1906), "
-                        "FP32, %d steps" % steps, "nodes": nodes, "variant": name, "ms_per_step": ms,
+                        "FP32, %d steps" % steps, "nodes": nodes, "variant": name, "tuned_variant": tuned,
+            "ms_per_step": ms,
             "mlups": nodes / ms / 1e3, "achieved_gbs": nodes * 72 / ms / 1e6, "mlups_by_variant": shapes}
 
 
-def sweep_steady(max_steps=200000, tol=1e-10):
+def sweep_steady(max_steps=200000, tol=1e-10, variant=-1):
     """Wall time for the 64 sweep droplets to reach a steady state (max |u|
     changing by less than tol between checks 100 steps apart): one batched
     FP32 run with its resolution rules, then finished in FP64 to the literal
@@ -342,7 +345,7 @@ def sweep_steady(max_steps=200000, tol=1e-10):
     st = torch.cuda.Stream()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    bt = Batch(items, stream=st, obs_every=100)
+    bt = Batch(items, stream=st, obs_every=100, variant=variant)
     bt.step(max_steps, tol=tol)
     torch.cuda.synchronize()
     t32 = time.perf_counter() - t0
@@ -490,7 +493,7 @@ def main():
         log("batch:", json.dumps(bs))
         extra["batched_sweep_64"] = bs
         if not args.no_steady:
-            ss = sweep_steady()
+            ss = sweep_steady(variant=bs["tuned_variant"])
             log("sweep steady:", json.dumps(ss))
             extra["sweep_steady_64"] = ss
     cpu = None

@@ -361,6 +361,17 @@ int sc_lbm_batch_promote(sc_lbm_batch* b);
 const char* sc_lbm_batch_variant_name(const sc_lbm_batch* b);
 int32_t sc_lbm_batch_num_variants(void);
 
+/* Launch-shape tuner for batched sweeps: times every batched shape on a
+ * scratch batch of the same n items (rho = 1 everywhere; the work does not
+ * depend on the values) the way sc_lbm_batch_step runs it -- graph-replayed
+ * 32-step chunks, steps rounded up to whole chunks, best of three -- and
+ * returns the fastest shape (a value for items[0].variant) and its time per
+ * step in ms.  Allocates and frees one scratch batch per shape on its own
+ * stream; synchronises.  Errors: as sc_lbm_batch_create, SC_E_INVAL for
+ * steps < 1. */
+int sc_lbm_batch_autotune(const sc_lbm_params* items, int32_t n, int32_t steps, int32_t* best_variant,
+                          double* best_ms);
+
 void sc_lbm_batch_destroy(sc_lbm_batch* b);
 
 /* ---- learned warm start: network kernels -------------------------------- */

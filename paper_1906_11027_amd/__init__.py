@@ -6,4 +6,4 @@ The compute path is libsc_lbm.so (C ABI, include/sc_lbm.h); `sc_lbm` is its
 ctypes binding.
 """
 from . import sc_lbm  # noqa: F401
-from .sc_lbm import Batch, Sim  # noqa: F401
+from .sc_lbm import Batch, Sim, batch_autotune  # noqa: F401

@@ -1773,6 +1773,59 @@ extern "C" const char* sc_lbm_batch_variant_name(const sc_lbm_batch* b) { return
 
 extern "C" int32_t sc_lbm_batch_num_variants(void) { return batch_num_shapes(); }
 
+// Batched shape tuner: one scratch batch of the caller's items per shape
+// (rho = 1 everywhere: the kernels do the same work whatever the values),
+// each timed as sc_lbm_batch_step runs it -- a warm-up graph that also
+// builds it, then the best of three runs of whole 32-step graphs.
+extern "C" int sc_lbm_batch_autotune(const sc_lbm_params* items, int32_t n, int32_t steps, int32_t* best_variant,
+                                     double* best_ms)
+{
+    if (!items || n < 1 || steps < 1) return SC_E_INVAL;
+    const int64_t per_rep = ((std::max<int64_t>(steps, kGraphSteps) + kGraphSteps - 1) / kGraphSteps) * kGraphSteps;
+    std::vector<sc_lbm_params> q(items, items + n);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        if (e0) hipEventDestroy(e0);
+        return hip_err(e);
+    }
+    int rc = SC_OK, best = -1;
+    double bms = 1e300;
+    for (int v = 0; v < batch_num_shapes() && rc == SC_OK; ++v) {
+        q[0].variant = v;
+        sc_lbm_batch* b = nullptr;
+        rc = sc_lbm_batch_create(q.data(), n, nullptr, nullptr, &b);
+        if (rc != SC_OK) break;
+        e = batch_run(b, kGraphSteps);
+        double per = 1e300;
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+            e = hipEventRecord(e0, b->stream);
+            if (e == hipSuccess) e = batch_run(b, per_rep);
+            if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess) per = std::min(per, (double)ms / per_rep);
+        }
+        sc_lbm_batch_destroy(b);
+        if (e != hipSuccess) {
+            rc = hip_err(e);
+            break;
+        }
+        if (per < bms) {
+            bms = per;
+            best = v;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc != SC_OK) return rc;
+    if (best_variant) *best_variant = best;
+    if (best_ms) *best_ms = bms;
+    return SC_OK;
+}
+
 extern "C" double sc_lbm_batch_rho_ref(const sc_lbm_batch* b)
 {
     return (b && !b->items.empty()) ? b->items[0]->p.rho_ref : std::nan("");

@@ -70,7 +70,7 @@ EXPORTS = [
     "sc_lbm_steps_per_launch",
     "sc_lbm_last_error_detail", "sc_lbm_stream", "sc_lbm_rho_ref",
     "sc_lbm_batch_create", "sc_lbm_batch_step", "sc_lbm_batch_observe", "sc_lbm_batch_status",
-    "sc_lbm_batch_active", "sc_lbm_batch_rho_ref", "sc_lbm_batch_variant_name", "sc_lbm_batch_num_variants", "sc_lbm_batch_promote", "sc_lbm_batch_destroy", "sc_lbm_autotune",
+    "sc_lbm_batch_active", "sc_lbm_batch_rho_ref", "sc_lbm_batch_variant_name", "sc_lbm_batch_num_variants", "sc_lbm_batch_promote", "sc_lbm_batch_autotune", "sc_lbm_batch_destroy", "sc_lbm_autotune",
     "sc_nn_conv3x3_fwd", "sc_nn_conv3x3_bwd_data", "sc_nn_bwd_weight_scratch_floats",
     "sc_nn_conv3x3_bwd_weight", "sc_nn_tanh_fwd", "sc_nn_tanh_bwd", "sc_nn_mse", "sc_nn_adam",
     "sc_nn_to_bf16", "sc_nn_features", "sc_nn_start_field",
@@ -183,6 +183,9 @@ def lib():
     L.sc_lbm_batch_num_variants.argtypes = []
     L.sc_lbm_batch_num_variants.restype = ctypes.c_int32
     L.sc_lbm_batch_promote.restype = ctypes.c_int
+    L.sc_lbm_batch_autotune.argtypes = [ctypes.POINTER(sc_lbm_params), ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
+    L.sc_lbm_batch_autotune.restype = ctypes.c_int
     L.sc_lbm_batch_variant_name.restype = ctypes.c_char_p
     L.sc_lbm_last_error_detail.argtypes = []
     L.sc_lbm_last_error_detail.restype = ctypes.c_char_p
@@ -502,6 +505,21 @@ def sc_lbm_batch_active(h):
 
 def sc_lbm_batch_destroy(h):
     lib().sc_lbm_batch_destroy(h)
+
+
+def batch_autotune(items, steps=64, **common):
+    """Fastest batched launch shape for these items (dicts as for Batch):
+    returns (variant, ms per step); pass variant=... to Batch to use it."""
+    params = []
+    for it in items:
+        kw = dict(common)
+        kw.update({k: v for k, v in it.items() if k != "rho0"})
+        params.append(make_params("D2Q9", np.asarray(it["rho0"]).shape, **kw))
+    arr = (sc_lbm_params * len(params))(*params)
+    v, ms = ctypes.c_int32(), ctypes.c_double()
+    _check(lib().sc_lbm_batch_autotune(arr, len(params), int(steps), ctypes.byref(v), ctypes.byref(ms)),
+           "sc_lbm_batch_autotune")
+    return v.value, ms.value
 
 
 class Batch:

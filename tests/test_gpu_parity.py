@@ -428,6 +428,29 @@ def test_batch_matches_oracle_and_single(prec, shape):
     bt.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_autotune(prec):
+    """The batched shape tuner returns one of the batched shapes with a
+    positive time per step, and a batch built with its choice matches the
+    automatic shape's result to rounding."""
+    from paper_1906_11027_amd import Batch, batch_autotune
+    from paper_1906_11027_amd import sc_lbm as B
+    items = _batch_items()
+    v, ms = batch_autotune(items, steps=32, precision=prec)
+    say("batch autotune %s: variant %d, %.4f ms per step" % (prec, v, ms))
+    assert 0 <= v < B.lib().sc_lbm_batch_num_variants() and ms > 0
+    a = Batch(items, precision=prec, variant=v)
+    b = Batch(items, precision=prec)
+    say("  tuned %s, automatic %s" % (a.variant, b.variant))
+    a.step(40)
+    b.step(40)
+    for k in range(len(items)):
+        ra, rb = a.observe(k)["rho"], b.observe(k)["rho"]
+        assert np.max(np.abs(ra - rb)) <= (1e-6 if prec == "fp32" else 1e-13) * np.max(np.abs(rb)), k
+    a.close()
+    b.close()
+
+
 def test_batch_convergence_and_quarantine():
     from paper_1906_11027_amd import Batch
     items = [{"rho0": droplet_rho((40, 40), 10, seed=1), "order": 4},
