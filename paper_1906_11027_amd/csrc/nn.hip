@@ -27,6 +27,7 @@
 #include <stdint.h>
 
 #include "../../include/sc_lbm.h"
+#include "kernels.h"   // xcd_swizzle
 
 namespace sclbm {
 namespace nn {
@@ -68,8 +69,11 @@ k_conv_fwd(const float* __restrict__ in, const uint16_t* __restrict__ w, const f
     __shared__ float ws[CCH][9][COUT];   // output channels contiguous: vector LDS reads
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TS + tx;
     const int tiles_x = (wd + TS - 1) / TS;
-    const int x0 = (blockIdx.x % tiles_x) * TS, y0 = (blockIdx.x / tiles_x) * TS;
-    const int b = blockIdx.y;
+    // XCD-aware order: the tiles one XCD runs together are neighbours, so
+    // the cache lines two tiles share are fetched into one L2
+    const int ntl = gridDim.x, L = xcd_swizzle(blockIdx.y * ntl + blockIdx.x, ntl * gridDim.y);
+    const int tl = L % ntl, b = L / ntl;
+    const int x0 = (tl % tiles_x) * TS, y0 = (tl / tiles_x) * TS;
     const int64_t plane = (int64_t)h * wd;
     const float* inb = in + (int64_t)b * cin * plane;
     float acc[COUT];
@@ -175,7 +179,9 @@ k_conv_fwd_mfma(const float* __restrict__ in, const uint16_t* __restrict__ w, co
 #pragma unroll
     for (int n = 0; n < 2; ++n) bv[n] = bias ? bias[n * 16 + r16] : 0.f;
 
-    for (int wi = blockIdx.x; wi < nwork; wi += gridDim.x) {
+    // XCD-aware order: at any time the blocks of one XCD hold neighbouring
+    // tiles, so the cache lines two tiles share are fetched into one L2
+    for (int wi = xcd_swizzle(blockIdx.x, gridDim.x); wi < nwork; wi += gridDim.x) {
         const int b = wi / tiles, tt = wi - b * tiles;
         const int x0 = (tt % tiles_x) * TS, y0 = (tt / tiles_x) * TS;
         const float* inb = in + (int64_t)b * cin * plane;
@@ -273,7 +279,6 @@ __global__ void k_transpose_flip(const uint16_t* __restrict__ w, uint16_t* __res
 // quarter-wave reads in distinct banks.
 constexpr int kGStride = TS * TS + 4;      // floats per output-gradient channel in LDS
 constexpr int kXStride = kHaloPx;          // floats per input channel in LDS (324 = 4 mod 64)
-constexpr int kBwdStage = (MAXC * kHaloPx + TS * TS - 1) / (TS * TS);   // input-tile loads per thread
 
 __global__ void __launch_bounds__(TS* TS, 2)
 k_conv_bwd_w(const float* __restrict__ in, const float* __restrict__ gout, float* __restrict__ partial, int batch,
@@ -289,54 +294,55 @@ k_conv_bwd_w(const float* __restrict__ in, const float* __restrict__ gout, float
     const int nwork = tiles_x * tiles_y * batch;
     const int64_t plane = (int64_t)h * wd;
     const int E = cout * cin * 9;
+    const bool active = mt * 16 < cout && nt * 16 < cin;
     f32x4 acc[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
     float bacc = 0.f;
-    for (int wi = blockIdx.x; wi < nwork; wi += gridDim.x) {
+    for (int wi = xcd_swizzle(blockIdx.x, gridDim.x); wi < nwork; wi += gridDim.x) {   // XCD-aware, as above
         const int b = wi / (tiles_x * tiles_y), tt = wi % (tiles_x * tiles_y);
         const int x0 = (tt % tiles_x) * TS, y0 = (tt / tiles_x) * TS;
         // output-gradient tile, every channel (zero outside the image and
         // for channels beyond cout), and the input tile with a wrapped halo
-        // of one (zero for channels beyond cin): every load issued first
-        float gv[MAXC], xv[kBwdStage];
+        // of one (zero for channels beyond cin): every load issued first.
+        // Thread tid stages pixel tid of the tile and halo pixels tid and
+        // tid + 256 (the latter for tid < 68), all channels.
+        float gv[MAXC], xv[MAXC], xw[MAXC];
         // 32-bit element offsets within the image (checked on the host)
         const float* gb = gout + (int64_t)b * cout * plane;
         const float* xb0 = in + (int64_t)b * cin * plane;
+        const bool two = tid + TS * TS < kHaloPx;
         {
             const int x = x0 + tid % TS, y = y0 + tid / TS;
             const bool in_img = x < wd && y < h;
             const uint32_t po = (uint32_t)(y * wd + x);
+            const int r1 = two ? tid + TS * TS : 0;
+            const uint32_t h0 = (uint32_t)(wrapc(y0 + tid / (TS + 2) - 1, h) * wd + wrapc(x0 + tid % (TS + 2) - 1, wd));
+            const uint32_t h1 = (uint32_t)(wrapc(y0 + r1 / (TS + 2) - 1, h) * wd + wrapc(x0 + r1 % (TS + 2) - 1, wd));
 #pragma unroll
-            for (int co = 0; co < MAXC; ++co)
-                gv[co] = (co < cout && in_img) ? gb[(uint32_t)co * (uint32_t)plane + po] : 0.f;
-        }
-#pragma unroll
-        for (int q = 0; q < kBwdStage; ++q) {
-            const int i = tid + q * TS * TS;
-            xv[q] = 0.f;
-            if (i < MAXC * kHaloPx) {
-                const int c = i / kHaloPx, r = i - c * kHaloPx;
-                const int ly = r / (TS + 2), lx = r - ly * (TS + 2);
-                if (c < cin)
-                    xv[q] = xb0[(uint32_t)c * (uint32_t)plane +
-                                (uint32_t)(wrapc(y0 + ly - 1, h) * wd + wrapc(x0 + lx - 1, wd))];
+            for (int c = 0; c < MAXC; ++c) {
+                const uint32_t co = (uint32_t)c * (uint32_t)plane;
+                gv[c] = (c < cout && in_img) ? gb[co + po] : 0.f;
+                xv[c] = c < cin ? xb0[co + h0] : 0.f;
+                xw[c] = (two && c < cin) ? xb0[co + h1] : 0.f;
             }
         }
         __syncthreads();   // the previous item's reads of gs and xs are done
 #pragma unroll
-        for (int co = 0; co < MAXC; ++co) gs[co * kGStride + tid] = gv[co];
-#pragma unroll
-        for (int q = 0; q < kBwdStage; ++q) {
-            const int i = tid + q * TS * TS;
-            if (i < MAXC * kHaloPx) xs[i] = xv[q];   // kXStride == kHaloPx: channel-major, contiguous
+        for (int c = 0; c < MAXC; ++c) {
+            gs[c * kGStride + tid] = gv[c];
+            xs[c * kXStride + tid] = xv[c];
+            if (two) xs[c * kXStride + tid + TS * TS] = xw[c];
         }
         __syncthreads();
-        if (tid < cout) {
+        {   // bias: thread (co = tid / 8, slice tid % 8) sums 32 pixels
+            const float* gr = gs + (tid >> 3) * kGStride + (tid & 7) * 32;
             float sb = 0.f;
-            for (int p = 0; p < TS * TS; ++p) sb += gs[tid * kGStride + p];
+#pragma unroll 8
+            for (int p = 0; p < 32; ++p) sb += gr[p];
             bacc += sb;
         }
+        if (!active) continue;   // this wave's co or ci tile lies wholly beyond cout or cin
         const float* ga = gs + (mt * 16 + r16) * kGStride;
         const float* xb = xs + (nt * 16 + r16) * kXStride;
 #pragma unroll 2
@@ -359,7 +365,10 @@ k_conv_bwd_w(const float* __restrict__ in, const float* __restrict__ gout, float
 #pragma unroll
             for (int t = 0; t < 9; ++t) pb[(ci * cout + co) * 9 + t] = acc[t][i];
     }
-    if (tid < cout) pb[E + tid] = bacc;
+    // bias partial: the 8 slices of each channel, summed in a fixed order
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) bacc += __shfl_xor(bacc, off, 64);
+    if ((tid & 7) == 0 && (tid >> 3) < cout) pb[E + (tid >> 3)] = bacc;
 }
 
 // Sum the per-block partials in a fixed order: gw[co][ci][k] from the

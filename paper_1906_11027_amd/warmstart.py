@@ -391,6 +391,27 @@ def run_experiment(n_train=2000, n_test=64, side=256, tol=1e-8, epochs=300, batc
                     log=log)
 
 
+def time_training(n=512, side=256, batch=16, epochs=3, seed=0):
+    """Wall time of training epochs on synthetic tanh-profile targets (the
+    network kernels at the experiment's sizes, without the LBM dataset):
+    returns seconds per epoch and per item."""
+    import torch
+    rng = np.random.default_rng(seed)
+    inputs = [normalise(rng.uniform(8, 85), rng.uniform(-5.5, -4.5), 1.0, 8) for _ in range(n)]
+    yy, xx = np.meshgrid(np.arange(side), np.arange(side), indexing="ij")
+    r = np.sqrt((xx - side // 2) ** 2 + (yy - side // 2) ** 2)
+    targets = [np.tanh((r - rng.uniform(8, 85)) / 3.0).astype(np.float32) for _ in range(n)]
+    net = WarmStartNet(side, side, batch, seed=seed + 1)
+    train(net, inputs[:2 * batch], targets[:2 * batch], epochs=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = train(net, inputs, targets, epochs=epochs)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / epochs
+    return {"items": n, "side": side, "batch": batch, "epochs": epochs, "s_per_epoch": dt,
+            "ms_per_item_epoch": dt / n * 1e3, "loss": hist}
+
+
 if __name__ == "__main__":
     import argparse
     import json
@@ -408,7 +429,12 @@ if __name__ == "__main__":
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--jitter", action="store_true", help="dataset runs from the jittered tanh start")
     ap.add_argument("--out", default=None)
+    ap.add_argument("--time-training", action="store_true",
+                    help="only time training epochs on synthetic targets (the network kernels)")
     a = ap.parse_args()
+    if a.time_training:
+        print(json.dumps(time_training(side=a.side)), flush=True)
+        sys.exit(0)
     res = run_experiment(n_train=a.n_train, n_test=a.n_test, side=a.side, tol=a.tol, epochs=a.epochs, lr=a.lr,
                          jitter=a.jitter, tols=tuple(float(t) for t in a.eval_tols.split(",")),
                          log=lambda m: print(m, flush=True))
