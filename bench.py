@@ -134,6 +134,8 @@ TRAFFIC_RATIO = {
     ("d3q19_mrt_e8_320_fp64", "march32x16h32"): (1.460, 1.000),
     ("d3q19_mrt_e8_320_fp64", "march32x8r1h32pf1"): (1.566, 1.000),
     ("d3q19_mrt_e8_320_fp64", "march32x8r1h64pf1"): (1.502, 1.000),
+    ("d3q19_mrt_e8_320_fp64", "rl64x8h64w4"): (2.531, 1.000),
+    ("d3q19_mrt_e8_320_fp64", "rl64x8h32w4"): (2.622, 1.000),
 }
 
 
