@@ -151,3 +151,26 @@ def test_strerror():
     # D2Q9 with the exact difference method runs in the any-lattice family
     assert B.sc_lbm_num_variants(B.make_params("D2Q9", forcing="edm")) == nw
     assert B.sc_lbm_num_variants(B.make_params("D2Q9", order=5)) == 0
+
+
+def test_batch_autotune_rejects_before_any_device_call():
+    L = B.lib()
+    v, ms = ctypes.c_int32(), ctypes.c_double()
+    assert L.sc_lbm_batch_autotune(None, 1, 32, ctypes.byref(v), ctypes.byref(ms)) == B.SC_E_INVAL
+    arr = (B.sc_lbm_params * 1)(B.make_params("D2Q9", (16, 16)))
+    assert L.sc_lbm_batch_autotune(arr, 0, 32, ctypes.byref(v), ctypes.byref(ms)) == B.SC_E_INVAL
+    assert L.sc_lbm_batch_autotune(arr, 1, 0, ctypes.byref(v), ctypes.byref(ms)) == B.SC_E_INVAL
+
+
+def test_conv_shapes_rejected_before_any_device_call():
+    """The MFMA convolution kernels address one image's channels with
+    32-bit element offsets: images whose 32 channels exceed 2^31 elements,
+    and unsupported channel counts, are rejected on the host."""
+    L = B.lib()
+    p = ctypes.c_void_p(4096)   # never dereferenced: every call below is rejected first
+    # 8192 x 8192 x 32 = 2^31 elements
+    assert L.sc_nn_conv3x3_fwd(p, p, p, p, 1, 32, 32, 8192, 8192, None) == B.SC_E_INVAL
+    assert L.sc_nn_conv3x3_fwd(p, p, p, p, 1, 33, 32, 16, 16, None) == B.SC_E_INVAL
+    assert L.sc_nn_conv3x3_fwd(p, p, p, p, 1, 32, 16, 16, 16, None) == B.SC_E_INVAL
+    assert L.sc_nn_conv3x3_fwd(p, p, p, p, 0, 32, 32, 16, 16, None) == B.SC_E_INVAL
+    assert L.sc_nn_conv3x3_bwd_weight(p, p, p, 4, p, p, 1, 32, 32, 8192, 8192, None) == B.SC_E_INVAL
