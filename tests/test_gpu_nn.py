@@ -90,6 +90,44 @@ def test_conv_backward(cin, cout, h, w):
         assert ei < 1e-5
 
 
+def test_conv_items_beyond_one_per_block():
+    """The MFMA kernels are persistent: 512 blocks take (image, 16 x 16 tile)
+    items in turn.  9 images of 128 x 128 (576 items) make some blocks take
+    a second item through the same LDS; forward, weight gradient and
+    backward-data against the oracle."""
+    rng = np.random.default_rng(11)
+    bsz, cin, cout, h, w = 9, 32, 32, 128, 128
+    x = rng.normal(size=(bsz, cin, h, w)).astype(np.float32)
+    g = rng.normal(size=(bsz, cout, h, w)).astype(np.float32)
+    wt = rng.normal(scale=0.2, size=(cout, cin, 3, 3)).astype(np.float32)
+    bias = rng.normal(size=cout).astype(np.float32)
+    bits, wq = _bf16(wt)
+    xd, gd, bd = _dev(x), _dev(g), _dev(bias)
+    wd = torch.tensor(bits.view(np.int16), device="cuda")
+    out = torch.empty((bsz, cout, h, w), device="cuda")
+    assert B.lib().sc_nn_conv3x3_fwd(xd.data_ptr(), wd.data_ptr(), bd.data_ptr(), out.data_ptr(), bsz, cin, cout, h,
+                                     w, _stream()) == 0
+    ref = C.conv_fwd(x.astype(np.float64), wq, bias.astype(np.float64))
+    err = np.max(np.abs(out.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    gin_ref, gw_ref, gb_ref = C.conv_bwd(x.astype(np.float64), wq, g.astype(np.float64))
+    nblk = 512
+    scratch = torch.empty(B.lib().sc_nn_bwd_weight_scratch_floats(cin, cout, nblk), device="cuda")
+    gw = torch.empty((cout, cin, 3, 3), device="cuda")
+    gb = torch.empty(cout, device="cuda")
+    assert B.lib().sc_nn_conv3x3_bwd_weight(xd.data_ptr(), gd.data_ptr(), scratch.data_ptr(), nblk, gw.data_ptr(),
+                                            gb.data_ptr(), bsz, cin, cout, h, w, _stream()) == 0
+    ew = np.max(np.abs(gw.cpu().numpy() - gw_ref)) / np.max(np.abs(gw_ref))
+    eb = np.max(np.abs(gb.cpu().numpy() - gb_ref)) / np.max(np.abs(gb_ref))
+    gin = torch.empty((bsz, cin, h, w), device="cuda")
+    wts = torch.empty(cin * cout * 9, dtype=torch.int16, device="cuda")
+    assert B.lib().sc_nn_conv3x3_bwd_data(gd.data_ptr(), wd.data_ptr(), wts.data_ptr(), gin.data_ptr(), bsz, cin,
+                                          cout, h, w, _stream()) == 0
+    ei = np.max(np.abs(gin.cpu().numpy() - gin_ref)) / np.max(np.abs(gin_ref))
+    say("conv 576 items: fwd %.2e, weight grad %.2e, bias grad %.2e, data grad %.2e" % (err, ew, eb, ei))
+    assert err < 1e-5 and ei < 1e-5
+    assert ew < 1e-4 and eb < 1e-4
+
+
 def test_pointwise_kernels():
     rng = np.random.default_rng(3)
     n = 5000
