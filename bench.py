@@ -16,11 +16,15 @@ to its steady state and the batched 64-droplet sweep.
 
 Timing: HIP events on the library's stream around K graph-replayed steps,
 bracketed by device synchronisation.  The roofline takes the fused kernel's
-time per launch as steps per launch (1, or 2 for the D2Q9 shapes that block
+time per launch as steps per launch (1, or 2 for the shapes that block
 two steps in time) x the event-timed time per step, which includes the gap
 between launches; its traffic is the tuned shape's measured HBM bytes per
-launch (TRAFFIC_RATIO).  The CPU baseline is the FP64 oracle on the host
-cores, on a bounded number of steps of the same workload.
+launch (TRAFFIC_RATIO).  "frac" prices the algorithmic bytes (Q values read
+and written per update) against 8 TB/s; "frac_counted" prices the bytes
+the counters measured, so a two-step launch that moves half its
+algorithmic bytes shows half the fraction there.  The CPU baseline is the
+FP64 oracle on the host cores, on a bounded number of steps of the same
+workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extra] [--no-cpu] [--no-steady]
 """
@@ -235,6 +239,9 @@ def measure(name, steps, warmup, kernel_launches=50):
         "achieved_gbs": achieved, "frac": achieved / HBM_PEAK_GBS, "variant": variant,
         "finite": bool(ok), "max_u": ob["max_u"], "traffic_bytes": traffic,
         "traffic_ratio": None if tr is None else (tr[0] + tr[1]) / 2.0,
+        # the same time against the bytes the counters measured for this
+        # shape: the share of 8 TB/s the kernel really moves
+        "frac_counted": None if tr is None else achieved * (tr[0] + tr[1]) / 2.0 / HBM_PEAK_GBS,
         "steps_per_launch": spl, "launch_ms": spl * ms / steps, "bytes_per_launch": spl * bpn * n,
     }
 
@@ -477,8 +484,8 @@ def main():
             r = measure(name, st, 10, kernel_launches=10)
             log(name + ":", json.dumps(r))
             extra[name] = {k: r[k] for k in ("mlups", "ms_per_step", "single_launch_ms_mean",
-                                             "achieved_gbs", "frac", "variant", "finite", "traffic_ratio",
-                                             "steps_per_launch")}
+                                             "achieved_gbs", "frac", "frac_counted", "variant", "finite",
+                                             "traffic_ratio", "steps_per_launch")}
         cc = copy_ceiling()
         log("copy:", json.dumps(cc))
         extra["copy_ceiling"] = cc
@@ -527,6 +534,7 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(main_r["frac"], 4),
                      "traffic": main_r["traffic_bytes"],
                      "traffic_ratio": main_r["traffic_ratio"],
+                     "frac_counted": None if main_r["frac_counted"] is None else round(main_r["frac_counted"], 4),
                      "kernel": kernel_label(w, main_r),
                      "steps_per_launch": main_r["steps_per_launch"],
                      "kernel_ms_mean": main_r["launch_ms"],
