@@ -396,6 +396,22 @@ int sc_nn_conv3x3_fwd(const float* in, const uint16_t* w, const float* bias, flo
 int sc_nn_conv3x3_bwd_data(const float* gout, const uint16_t* w, uint16_t* wt_scratch, float* gin, int32_t batch,
                            int32_t cin, int32_t cout, int32_t h, int32_t wd, void* stream);
 
+/* The same two passes with the tanh of the net's hidden layers fused into
+ * the store (no separate elementwise pass over the activations):
+ *   sc_nn_conv3x3_fwd_tanh:      out = tanh(conv(in) + bias), cout = 32 only;
+ *                                equals sc_nn_conv3x3_fwd then sc_nn_tanh_fwd;
+ *   sc_nn_conv3x3_bwd_data_tanh: gin = (1 - y^2) conv(gout, w flipped and
+ *                                transposed), y [batch][cin][h][wd] the tanh
+ *                                activation that was the layer's input;
+ *                                equals sc_nn_conv3x3_bwd_data then
+ *                                sc_nn_tanh_bwd(y, gin).
+ * Arguments, layouts and errors otherwise as above. */
+int sc_nn_conv3x3_fwd_tanh(const float* in, const uint16_t* w, const float* bias, float* out, int32_t batch,
+                           int32_t cin, int32_t cout, int32_t h, int32_t wd, void* stream);
+int sc_nn_conv3x3_bwd_data_tanh(const float* gout, const uint16_t* w, uint16_t* wt_scratch, const float* y,
+                                float* gin, int32_t batch, int32_t cin, int32_t cout, int32_t h, int32_t wd,
+                                void* stream);
+
 /* Gradients w.r.t. the weights (gw [cout][cin][9] float32) and biases
  * (gbias [cout]) summed over the batch, through nblk per-block partial rows
  * in partial_scratch (sc_nn_bwd_weight_scratch_floats(cin, cout, nblk)

@@ -156,9 +156,25 @@ __device__ __forceinline__ int slot_chunk(int s, int k) { return (k ^ (s >> 2)) 
 // input channels.
 constexpr int kFwdStage = ((MAXC / 2) * kHaloPx + TS * TS - 1) / (TS * TS);   // staging loads per thread
 
+// Epilogue applied to each output before it is stored (fusing the
+// elementwise pass that would otherwise re-read the whole activation)
+enum ConvEpi { kEpiNone = 0, kEpiTanh = 1, kEpiTanhGrad = 2 };
+
+template <int EPI>
+__device__ __forceinline__ float conv_epi(float v, const float* __restrict__ y, int64_t i)
+{
+    if (EPI == kEpiTanh) return tanhf(v);
+    if (EPI == kEpiTanhGrad) {
+        const float yv = y[i];
+        return v * (1.f - yv * yv);
+    }
+    return v;
+}
+
+template <int EPI>
 __global__ void __launch_bounds__(TS* TS, 2)
 k_conv_fwd_mfma(const float* __restrict__ in, const uint16_t* __restrict__ w, const float* __restrict__ bias,
-                float* __restrict__ out, int batch, int cin, int h, int wd)
+                float* __restrict__ out, const float* __restrict__ y, int batch, int cin, int h, int wd)
 {
     __shared__ __align__(16) uint16_t xs[3 * kPartBf];
     __shared__ __align__(16) uint16_t wsl[9 * MAXC * kPxSlot];
@@ -242,17 +258,20 @@ k_conv_fwd_mfma(const float* __restrict__ in, const uint16_t* __restrict__ w, co
         const bool vec = (wd & 3) == 0 && xq + 3 < wd;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int y = y0 + 4 * wv + r;
-            if (y >= h) continue;
+            const int yy = y0 + 4 * wv + r;
+            if (yy >= h) continue;
 #pragma unroll
             for (int n = 0; n < 2; ++n) {
-                float* o = out + ((int64_t)b * MAXC + n * 16 + r16) * plane + (int64_t)y * wd + xq;
+                const int64_t o0 = ((int64_t)b * MAXC + n * 16 + r16) * plane + (int64_t)yy * wd + xq;
+                float* o = out + o0;
                 if (vec) {
-                    *(float4*)o = make_float4(acc[r][n][0], acc[r][n][1], acc[r][n][2], acc[r][n][3]);
+                    *(float4*)o = make_float4(conv_epi<EPI>(acc[r][n][0], y, o0), conv_epi<EPI>(acc[r][n][1], y, o0 + 1),
+                                              conv_epi<EPI>(acc[r][n][2], y, o0 + 2),
+                                              conv_epi<EPI>(acc[r][n][3], y, o0 + 3));
                 } else {
 #pragma unroll
                     for (int i = 0; i < 4; ++i)
-                        if (xq + i < wd) o[i] = acc[r][n][i];
+                        if (xq + i < wd) o[i] = conv_epi<EPI>(acc[r][n][i], y, o0 + i);
                 }
             }
         }
@@ -557,20 +576,41 @@ static bool conv_shape_ok(int batch, int cin, int cout, int h, int w)
            batch <= 65535 && (int64_t)h * w * MAXC < ((int64_t)1 << 31);
 }
 
+// the 32-output-channel forward on the matrix cores, with its epilogue
+static hipError_t launch_fwd_mfma(int epi, const float* in, const uint16_t* w, const float* bias, float* out,
+                                  const float* y, int batch, int cin, int h, int wd, hipStream_t s)
+{
+    const int tiles = ((wd + TS - 1) / TS) * ((h + TS - 1) / TS);
+    const int64_t nwork = (int64_t)tiles * batch;
+    const int nb = (int)(nwork < 2 * cu_count() ? nwork : 2 * cu_count());
+    const dim3 block(TS, TS);
+    if (epi == kEpiTanh)
+        hipLaunchKernelGGL(k_conv_fwd_mfma<kEpiTanh>, dim3(nb), block, 0, s, in, w, bias, out, y, batch, cin, h, wd);
+    else if (epi == kEpiTanhGrad)
+        hipLaunchKernelGGL(k_conv_fwd_mfma<kEpiTanhGrad>, dim3(nb), block, 0, s, in, w, bias, out, y, batch, cin, h,
+                           wd);
+    else
+        hipLaunchKernelGGL(k_conv_fwd_mfma<kEpiNone>, dim3(nb), block, 0, s, in, w, bias, out, y, batch, cin, h, wd);
+    return hipGetLastError();
+}
+
 extern "C" int sc_nn_conv3x3_fwd(const float* in, const uint16_t* w, const float* bias, float* out, int32_t batch,
                                  int32_t cin, int32_t cout, int32_t h, int32_t wd, void* stream)
 {
     if (!in || !w || !out || !conv_shape_ok(batch, cin, cout, h, wd)) return SC_E_INVAL;
+    if (cout == MAXC)
+        return nn_status(launch_fwd_mfma(kEpiNone, in, w, bias, out, nullptr, batch, cin, h, wd, (hipStream_t)stream));
     const int tiles = ((wd + TS - 1) / TS) * ((h + TS - 1) / TS);
     dim3 grid(tiles, batch), block(TS, TS);
-    if (cout == MAXC) {
-        const int64_t nwork = (int64_t)tiles * batch;
-        const int nb = (int)(nwork < 2 * cu_count() ? nwork : 2 * cu_count());
-        hipLaunchKernelGGL(k_conv_fwd_mfma, dim3(nb), block, 0, (hipStream_t)stream, in, w, bias, out, batch, cin, h,
-                           wd);
-    } else
-        hipLaunchKernelGGL(k_conv_fwd<1>, grid, block, 0, (hipStream_t)stream, in, w, bias, out, cin, cout, h, wd);
+    hipLaunchKernelGGL(k_conv_fwd<1>, grid, block, 0, (hipStream_t)stream, in, w, bias, out, cin, cout, h, wd);
     return nn_status(hipGetLastError());
+}
+
+extern "C" int sc_nn_conv3x3_fwd_tanh(const float* in, const uint16_t* w, const float* bias, float* out,
+                                      int32_t batch, int32_t cin, int32_t cout, int32_t h, int32_t wd, void* stream)
+{
+    if (!in || !w || !out || !conv_shape_ok(batch, cin, cout, h, wd) || cout != MAXC) return SC_E_INVAL;
+    return nn_status(launch_fwd_mfma(kEpiTanh, in, w, bias, out, nullptr, batch, cin, h, wd, (hipStream_t)stream));
 }
 
 extern "C" int sc_nn_conv3x3_bwd_data(const float* gout, const uint16_t* w, uint16_t* wt_scratch, float* gin,
@@ -585,6 +625,20 @@ extern "C" int sc_nn_conv3x3_bwd_data(const float* gout, const uint16_t* w, uint
     // gradient w.r.t. the input: convolution of gout (cout channels) with the
     // flipped, transposed weights (cin output channels), no bias
     return sc_nn_conv3x3_fwd(gout, wt_scratch, nullptr, gin, batch, cout, cin, h, wd, stream);
+}
+
+extern "C" int sc_nn_conv3x3_bwd_data_tanh(const float* gout, const uint16_t* w, uint16_t* wt_scratch, const float* y,
+                                           float* gin, int32_t batch, int32_t cin, int32_t cout, int32_t h, int32_t wd,
+                                           void* stream)
+{
+    if (!gout || !w || !wt_scratch || !y || !gin || !conv_shape_ok(batch, cin, cout, h, wd) || cin != MAXC)
+        return SC_E_INVAL;
+    const int nw = cin * cout * 9;
+    hipLaunchKernelGGL(k_transpose_flip, (nw + 255) / 256, 256, 0, (hipStream_t)stream, w, wt_scratch, cin, cout);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return nn_status(e);
+    return nn_status(
+        launch_fwd_mfma(kEpiTanhGrad, gout, wt_scratch, nullptr, gin, y, batch, cout, h, wd, (hipStream_t)stream));
 }
 
 extern "C" int32_t sc_nn_bwd_weight_scratch_floats(int32_t cin, int32_t cout, int32_t nblk)

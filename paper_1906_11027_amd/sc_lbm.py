@@ -71,7 +71,8 @@ EXPORTS = [
     "sc_lbm_last_error_detail", "sc_lbm_stream", "sc_lbm_rho_ref",
     "sc_lbm_batch_create", "sc_lbm_batch_step", "sc_lbm_batch_observe", "sc_lbm_batch_status",
     "sc_lbm_batch_active", "sc_lbm_batch_rho_ref", "sc_lbm_batch_variant_name", "sc_lbm_batch_num_variants", "sc_lbm_batch_promote", "sc_lbm_batch_autotune", "sc_lbm_batch_destroy", "sc_lbm_autotune",
-    "sc_nn_conv3x3_fwd", "sc_nn_conv3x3_bwd_data", "sc_nn_bwd_weight_scratch_floats",
+    "sc_nn_conv3x3_fwd", "sc_nn_conv3x3_fwd_tanh", "sc_nn_conv3x3_bwd_data", "sc_nn_conv3x3_bwd_data_tanh",
+    "sc_nn_bwd_weight_scratch_floats",
     "sc_nn_conv3x3_bwd_weight", "sc_nn_tanh_fwd", "sc_nn_tanh_bwd", "sc_nn_mse", "sc_nn_adam",
     "sc_nn_to_bf16", "sc_nn_features", "sc_nn_start_field",
 ]
@@ -157,6 +158,8 @@ def lib():
     L.sc_lbm_autotune.restype = ctypes.c_int
     i32, i64, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
     L.sc_nn_conv3x3_fwd.argtypes = [vp, vp, vp, vp, i32, i32, i32, i32, i32, vp]
+    L.sc_nn_conv3x3_fwd_tanh.argtypes = [vp, vp, vp, vp, i32, i32, i32, i32, i32, vp]
+    L.sc_nn_conv3x3_bwd_data_tanh.argtypes = [vp, vp, vp, vp, vp, i32, i32, i32, i32, i32, vp]
     L.sc_nn_conv3x3_bwd_data.argtypes = [vp, vp, vp, vp, i32, i32, i32, i32, i32, vp]
     L.sc_nn_bwd_weight_scratch_floats.argtypes = [i32, i32, i32]
     L.sc_nn_bwd_weight_scratch_floats.restype = i32
@@ -168,7 +171,8 @@ def lib():
     L.sc_nn_to_bf16.argtypes = [vp, vp, i64, vp]
     L.sc_nn_features.argtypes = [vp, vp, i32, i32, i32, f32, vp]
     L.sc_nn_start_field.argtypes = [vp, vp, vp, vp, i32, i32, i32, f32, ctypes.c_double, ctypes.c_double, vp]
-    for name in ("sc_nn_conv3x3_fwd", "sc_nn_conv3x3_bwd_data", "sc_nn_conv3x3_bwd_weight", "sc_nn_tanh_fwd",
+    for name in ("sc_nn_conv3x3_fwd", "sc_nn_conv3x3_fwd_tanh", "sc_nn_conv3x3_bwd_data",
+                 "sc_nn_conv3x3_bwd_data_tanh", "sc_nn_conv3x3_bwd_weight", "sc_nn_tanh_fwd",
                  "sc_nn_tanh_bwd", "sc_nn_mse", "sc_nn_adam", "sc_nn_to_bf16", "sc_nn_features",
                  "sc_nn_start_field"):
         getattr(L, name).restype = ctypes.c_int

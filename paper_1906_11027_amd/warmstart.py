@@ -107,15 +107,15 @@ class WarmStartNet:
                                          SCALE_R, self.stream), "sc_nn_features")
 
     def forward(self):
+        """The five convolutions; the hidden layers' tanh is fused into the
+        convolution's store."""
         L = B.lib()
         for li in range(5):
             cin, cout = CHANNELS[li], CHANNELS[li + 1]
-            self._chk(L.sc_nn_conv3x3_fwd(self.acts[li].data_ptr(), self.Wb[li].data_ptr(), self.b[li].data_ptr(),
-                                          self.acts[li + 1].data_ptr(), self.batch, cin, cout, self.h, self.w,
-                                          self.stream), "conv fwd")
-            if li < 4:
-                self._chk(L.sc_nn_tanh_fwd(self.acts[li + 1].data_ptr(), self.acts[li + 1].numel(), self.stream),
-                          "tanh fwd")
+            fn = L.sc_nn_conv3x3_fwd_tanh if li < 4 else L.sc_nn_conv3x3_fwd
+            self._chk(fn(self.acts[li].data_ptr(), self.Wb[li].data_ptr(), self.b[li].data_ptr(),
+                         self.acts[li + 1].data_ptr(), self.batch, cin, cout, self.h, self.w, self.stream),
+                      "conv fwd")
         return self.acts[5]
 
     def loss_and_grad(self, target):
@@ -127,20 +127,22 @@ class WarmStartNet:
         return self.mse_part
 
     def backward(self):
+        """Gradients of every layer.  The input gradient of layers 1..4 is
+        multiplied by the tanh derivative of their input activation in the
+        same pass (sc_nn_conv3x3_bwd_data_tanh), so gact[li] holds the
+        gradient w.r.t. layer li's pre-activation when layer li - 1 uses it."""
         L = B.lib()
         for li in range(4, -1, -1):
             cin, cout = CHANNELS[li], CHANNELS[li + 1]
             g = self.gact[li + 1]
-            if li < 4:
-                self._chk(L.sc_nn_tanh_bwd(self.acts[li + 1].data_ptr(), g.data_ptr(), g.numel(), self.stream),
-                          "tanh bwd")
             self._chk(L.sc_nn_conv3x3_bwd_weight(self.acts[li].data_ptr(), g.data_ptr(), self.wscratch.data_ptr(),
                                                  self.nblk_w, self.gW[li].data_ptr(), self.gb[li].data_ptr(),
                                                  self.batch, cin, cout, self.h, self.w, self.stream), "bwd w")
             if li > 0:
-                self._chk(L.sc_nn_conv3x3_bwd_data(g.data_ptr(), self.Wb[li].data_ptr(), self.wt.data_ptr(),
-                                                   self.gact[li].data_ptr(), self.batch, cin, cout, self.h, self.w,
-                                                   self.stream), "bwd data")
+                self._chk(L.sc_nn_conv3x3_bwd_data_tanh(g.data_ptr(), self.Wb[li].data_ptr(), self.wt.data_ptr(),
+                                                        self.acts[li].data_ptr(), self.gact[li].data_ptr(),
+                                                        self.batch, cin, cout, self.h, self.w, self.stream),
+                          "bwd data")
 
     def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         self.t += 1

@@ -128,6 +128,42 @@ def test_conv_items_beyond_one_per_block():
     assert ew < 1e-4 and eb < 1e-4
 
 
+@pytest.mark.parametrize("h,w,bsz", [(20, 37, 3), (5, 7, 2), (128, 128, 9)])
+def test_fused_tanh_passes(h, w, bsz):
+    """The convolutions with the tanh fused into their store give what the
+    separate passes give: forward then tanh, backward-data then the tanh
+    derivative of the layer's input (same operations in the same order)."""
+    rng = np.random.default_rng(h + w)
+    cin = cout = 32
+    x = rng.normal(size=(bsz, cin, h, w)).astype(np.float32)
+    y = np.tanh(rng.normal(size=(bsz, cin, h, w))).astype(np.float32)
+    g = rng.normal(size=(bsz, cout, h, w)).astype(np.float32)
+    bits, _ = _bf16(rng.normal(scale=0.2, size=(cout, cin, 3, 3)).astype(np.float32))
+    xd, yd, gd, bd = _dev(x), _dev(y), _dev(g), _dev(rng.normal(size=cout).astype(np.float32))
+    wd = torch.tensor(bits.view(np.int16), device="cuda")
+    L, st = B.lib(), _stream()
+    a, b = torch.empty((bsz, cout, h, w), device="cuda"), torch.empty((bsz, cout, h, w), device="cuda")
+    assert L.sc_nn_conv3x3_fwd(xd.data_ptr(), wd.data_ptr(), bd.data_ptr(), a.data_ptr(), bsz, cin, cout, h, w,
+                               st) == 0
+    assert L.sc_nn_tanh_fwd(a.data_ptr(), a.numel(), st) == 0
+    assert L.sc_nn_conv3x3_fwd_tanh(xd.data_ptr(), wd.data_ptr(), bd.data_ptr(), b.data_ptr(), bsz, cin, cout, h, w,
+                                    st) == 0
+    df = float((a - b).abs().max())
+    wts = torch.empty(cin * cout * 9, dtype=torch.int16, device="cuda")
+    c, e = torch.empty((bsz, cin, h, w), device="cuda"), torch.empty((bsz, cin, h, w), device="cuda")
+    assert L.sc_nn_conv3x3_bwd_data(gd.data_ptr(), wd.data_ptr(), wts.data_ptr(), c.data_ptr(), bsz, cin, cout, h,
+                                    w, st) == 0
+    assert L.sc_nn_tanh_bwd(yd.data_ptr(), c.data_ptr(), c.numel(), st) == 0
+    assert L.sc_nn_conv3x3_bwd_data_tanh(gd.data_ptr(), wd.data_ptr(), wts.data_ptr(), yd.data_ptr(), e.data_ptr(),
+                                         bsz, cin, cout, h, w, st) == 0
+    db = float((c - e).abs().max())
+    say("fused tanh %dx%d: forward max diff %.1e, backward-data max diff %.1e" % (h, w, df, db))
+    assert df <= 1e-6 and db <= 1e-6 * float(c.abs().max())
+    # one output channel has no fused form (the net's last layer is linear)
+    assert L.sc_nn_conv3x3_fwd_tanh(xd.data_ptr(), wd.data_ptr(), bd.data_ptr(), b.data_ptr(), bsz, cin, 1, h, w,
+                                    st) == B.SC_E_INVAL
+
+
 def test_pointwise_kernels():
     rng = np.random.default_rng(3)
     n = 5000
