@@ -339,6 +339,8 @@ def evaluate(ds, epochs=300, batch=16, lr=1e-3, fp64_baseline=8, seed=2026, tols
         "err_rms_median": {"tanh": float(np.median([rms(b, k) for b, k in zip(bases, test_idx)])),
                            "raw_prediction": float(np.median([rms(p, k) for p, k in zip(raw, test_idx)])),
                            "learned": float(np.median([rms(p, k) for p, k in zip(starts, test_idx)]))},
+        "test_items": [{"R": float(it["R"]), "G": float(it["G"]), "tau": float(it["tau"]), "order": int(it["order"])}
+                       for it in test_items],
         "runs": {},
     }
     for tol in tols:
@@ -354,7 +356,8 @@ def evaluate(ds, epochs=300, batch=16, lr=1e-3, fp64_baseline=8, seed=2026, tols
             extra = t_inf if name.startswith("learned") else 0.0
             out[name] = {"steps_mean": float(np.mean(steps)), "steps_median": float(np.median(steps)),
                          "wall_s_per_item": (wall + extra) / nt, "converged": int(sum(1 for v in by if v > 0)),
-                         "fields": f, "steps": steps}
+                         "quarantined": int(sum(1 for v in by if v < 0)), "fields": f, "steps": steps,
+                         "converged_by": [int(v) for v in by]}
             log("%s tol %s: mean steps %.0f, %.4f s per droplet" % (name, key, out[name]["steps_mean"],
                                                                   out[name]["wall_s_per_item"]))
         for name in list(out):
