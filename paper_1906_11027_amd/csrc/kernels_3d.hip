@@ -13,6 +13,8 @@
 // ring and the 2R extra planes per block are pulled twice (L2 hits).
 // One barrier per plane: the 2R + 2 slots keep the next write away from the
 // 2R + 1 planes still being read.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace sclbm {
@@ -27,9 +29,18 @@ __device__ __forceinline__ void pull_d3q19(const T* __restrict__ f, int64_t n, u
         g[b] = ld_off(f + b * n, zo[1 - D3Q19::cz[b]] + yo[1 - D3Q19::cy[b]] + xo[1 - D3Q19::cx[b]]);
 }
 
+// LDS of one march block: the psi ring
+template <typename T, int ORDER, int TX, int TYB, int RPT>
+constexpr int march_lds_floats()
+{
+    using ST = Stencil<3, ORDER>;
+    return (2 * ST::R + 2) * (TX + 2 * ST::R) * (TYB * RPT + 2 * ST::R);
+}
+
+// One block's march over logical column segment L (x tile fastest, then y
+// tile, then z segment).
 template <typename T, int ORDER, bool MRT, int TX, int TYB, int RPT, int PF>
-__global__ void __launch_bounds__(TX* TYB)
-k_d3q19_march(StepArgs<T> a, int H, int nbx, int nby)
+__device__ __forceinline__ void march_item(const StepArgs<T>& a, int H, int nbx, int nby, int L, T* __restrict__ psi_s)
 {
     using ST = Stencil<3, ORDER>;
     constexpr int R = ST::R;
@@ -42,14 +53,12 @@ k_d3q19_march(StepArgs<T> a, int H, int nbx, int nby)
     constexpr int W = R + 1 + PF;        // f register window (PF = 1: next plane in flight)
     constexpr int RING = PL - TX * TY;   // halo nodes per plane
     constexpr int RPERT = (RING + NT - 1) / NT;
-    __shared__ T psi_s[NS * PL];
 
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int64_t n = a.n;
     const uint32_t TS = sizeof(T), rowb = (uint32_t)nx * TS, planeb = (uint32_t)ny * rowb;
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = ty * TX + tx;
-    const int L = xcd_swizzle(blockIdx.x, gridDim.x);
     const int x0 = (L % nbx) * TX, y0 = ((L / nbx) % nby) * TY, z0 = (L / (nbx * nby)) * H;
 
     const int xr = x0 + tx;
@@ -168,6 +177,35 @@ k_d3q19_march(StepArgs<T> a, int H, int nbx, int nby)
                 }
             }
         }
+    }
+}
+
+template <typename T, int ORDER, bool MRT, int TX, int TYB, int RPT, int PF>
+__global__ void __launch_bounds__(TX* TYB)
+k_d3q19_march(StepArgs<T> a, int H, int nbx, int nby)
+{
+    __shared__ T psi_s[march_lds_floats<T, ORDER, TX, TYB, RPT>()];
+    march_item<T, ORDER, MRT, TX, TYB, RPT, PF>(a, H, nbx, nby, xcd_swizzle(blockIdx.x, gridDim.x), psi_s);
+}
+
+// Persistent form: as many blocks as fit on the device at once, each taking
+// column segments in generations of gridDim.x.  All blocks start together
+// and every segment is the same work, so a generation's segments march in
+// step; the XCD swizzle within a generation gives each XCD a compact patch
+// of neighbouring columns.  A tile's halo ring, the edge rows of its
+// neighbours, is then read while the neighbours hold those planes in the
+// XCD's L2, not planes later, after it has been evicted.
+template <typename T, int ORDER, bool MRT, int TX, int TYB, int RPT, int PF>
+__global__ void __launch_bounds__(TX* TYB)
+k_d3q19_march_p(StepArgs<T> a, int H, int nbx, int nby, int nitems)
+{
+    __shared__ T psi_s[march_lds_floats<T, ORDER, TX, TYB, RPT>()];
+    const int nb = gridDim.x, b = blockIdx.x;
+    for (int base = 0; base < nitems; base += nb) {
+        const int r = nitems - base < nb ? nitems - base : nb;
+        if (b >= r) break;   // uniform across the block
+        if (base) __syncthreads();   // the previous segment's reads of the ring are done
+        march_item<T, ORDER, MRT, TX, TYB, RPT, PF>(a, H, nbx, nby, base + xcd_swizzle(b, r), psi_s);
     }
 }
 
@@ -324,6 +362,13 @@ static const Shape3D kShapes3D[] = {
     // the FP32 state 25% slower (the second pulls miss L2 in part)
     {64, 8, 4, 64, "rl64x8h64w4"},
     {64, 8, 4, 32, "rl64x8h32w4"},
+    // persistent k_d3q19_march_p (segments in generations of resident blocks):
+    // 7% faster than the one-segment-per-block launch at 320^3 (FP32 MRT E8,
+    // fetch 1.32 vs 1.37 of the algorithmic reads) and 6% at 128^3; the
+    // 64 x 12 and 32 x 8 tiles were slower in this form too
+    {64, 8, 1, 64, "pmarch64x8r1h64pf1"},
+    {64, 8, 1, 32, "pmarch64x8r1h32pf1"},
+    {64, 8, 1, 16, "pmarch64x8r1h16pf1"},
 };
 constexpr int kNumShapes3D = sizeof(kShapes3D) / sizeof(kShapes3D[0]);
 
@@ -339,6 +384,32 @@ static hipError_t launch_march(const StepArgs<T>& a, int H, hipStream_t s)
     const int nbz = (a.nz + H - 1) / H;
     hipLaunchKernelGGL((k_d3q19_march<T, ORDER, MRT, TX, TYB, RPT, PF>), dim3(nbx * nby * nbz), block, 0, s,
                        a, H, nbx, nby);
+    return hipGetLastError();
+}
+
+// persistent march: one generation of blocks is what the device holds at once
+template <typename T, int ORDER, bool MRT, int TX, int TYB, int RPT, int PF>
+static hipError_t launch_march_p(const StepArgs<T>& a, int H, hipStream_t s)
+{
+    if (H > a.nz) H = a.nz;
+    const int nbx = (a.nx + TX - 1) / TX, nby = (a.ny + TYB * RPT - 1) / (TYB * RPT);
+    const int nitems = nbx * nby * ((a.nz + H - 1) / H);
+    static int per_cu = 0, cus = 0;   // per process: one device type
+    if (!per_cu) {
+        int dev = 0, n = 0, c = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_d3q19_march_p<T, ORDER, MRT, TX, TYB, RPT, PF>,
+                                                         TX * TYB, 0) == hipSuccess &&
+            hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0 && c > 0) {
+            cus = c;
+            per_cu = n;
+        } else {
+            return hipErrorUnknown;
+        }
+    }
+    const int nb = std::min(nitems, per_cu * cus);
+    hipLaunchKernelGGL((k_d3q19_march_p<T, ORDER, MRT, TX, TYB, RPT, PF>), dim3(nb), dim3(TX, TYB), 0, s, a, H, nbx,
+                       nby, nitems);
     return hipGetLastError();
 }
 
@@ -375,6 +446,9 @@ static hipError_t launch_v(const StepArgs<T>& a, int variant, hipStream_t s)
     case 15: return launch_march<T, ORDER, MRT, 64, 12, 1, 1>(a, 16, s);
     case 16: return launch_march_rl<T, ORDER, MRT, 64, 8, 4>(a, 64, s);
     case 17: return launch_march_rl<T, ORDER, MRT, 64, 8, 4>(a, 32, s);
+    case 18: return launch_march_p<T, ORDER, MRT, 64, 8, 1, 1>(a, 64, s);
+    case 19: return launch_march_p<T, ORDER, MRT, 64, 8, 1, 1>(a, 32, s);
+    case 20: return launch_march_p<T, ORDER, MRT, 64, 8, 1, 1>(a, 16, s);
     default: return hipErrorInvalidValue;
     }
 }
