@@ -106,6 +106,11 @@ TRAFFIC_RATIO = {
     ("d3q19_mrt_e8_320", "march64x12r1h64pf1"): (1.304, 1.000),
     ("d3q19_mrt_e8_320", "march64x12r1h32pf1"): (1.378, 1.000),
     ("d3q19_mrt_e8_320", "march64x12r1h16pf1"): (1.505, 1.000),
+    # the three persistent 64 x 8 shapes share one grid (one block per CU):
+    # their mean over the autotuner's dispatches
+    ("d3q19_mrt_e8_320", "pmarch64x8r1h64pf1"): (1.320, 1.000),
+    ("d3q19_mrt_e8_320", "pmarch64x8r1h32pf1"): (1.320, 1.000),
+    ("d3q19_mrt_e8_320", "pmarch64x8r1h16pf1"): (1.320, 1.000),
     ("d2q13_e6_pr_edm_8192", "wide2x32x8t256"): (0.633, 0.500),
     ("d2q13_e6_pr_edm_8192", "wide2x64x8t512"): (0.563, 0.500),
     ("d2q13_e6_pr_edm_8192", "wide2x64x16t1024"): (0.563, 0.500),
