@@ -365,7 +365,9 @@ static const Shape3D kShapes3D[] = {
     // persistent k_d3q19_march_p (segments in generations of resident blocks):
     // 7% faster than the one-segment-per-block launch at 320^3 (FP32 MRT E8,
     // fetch 1.32 vs 1.37 of the algorithmic reads) and 6% at 128^3; the
-    // 64 x 12 and 32 x 8 tiles were slower in this form too
+    // 64 x 12 and 32 x 8 tiles were slower in this form too, and so was a
+    // strip order of the segments (1 or 2 tile columns per strip: 4% and 2%
+    // slower at 320^3, the x halo then crossing XCDs)
     {64, 8, 1, 64, "pmarch64x8r1h64pf1"},
     {64, 8, 1, 32, "pmarch64x8r1h32pf1"},
     {64, 8, 1, 16, "pmarch64x8r1h16pf1"},
