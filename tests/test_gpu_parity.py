@@ -263,6 +263,37 @@ def test_d3q19_variants_agree(order, collision, prec):
             assert d <= (2e-6 if prec == "fp32" else 1e-14) * float(np.max(np.abs(ref))), (v, d)
 
 
+def test_d3q19_persistent_march_generations():
+    """The persistent march takes column segments in generations of the
+    blocks that fit at once (one 512-thread block per CU).  A 192 x 64 x 192
+    grid has 3 x 8 x 12 = 288 segments of 64 x 8 x 16 nodes, more than one
+    generation; the persistent shape must give the state of the
+    one-segment-per-block shape, which does the same arithmetic per node."""
+    from paper_1906_11027_amd import sc_lbm as B
+    rho0 = droplet_rho((192, 64, 192), 20, seed=6)
+    states = {}
+    for v in ("march64x8r1h16pf1", "pmarch64x8r1h16pf1"):
+        idx = next(i for i in range(B.sc_lbm_num_variants(B.make_params("D3Q19", (8, 8, 8))))
+                   if _d3q19_variant_name(i) == v)
+        sim = Sim(rho0, "D3Q19", order=8, collision="mrt", variant=idx)
+        assert sim.variant == v
+        sim.step(12)
+        states[v] = sim.state().astype(np.float64)
+        sim.close()
+    a, b = states["march64x8r1h16pf1"], states["pmarch64x8r1h16pf1"]
+    d = float(np.max(np.abs(a - b)))
+    say("persistent vs one-segment-per-block march, 288 segments: max |diff| %.2e" % d)
+    assert d <= 2e-6 * float(np.max(np.abs(a)))
+
+
+def _d3q19_variant_name(i):
+    """Name of D3Q19 launch shape i (from a throwaway 8^3 handle)."""
+    sim = Sim(droplet_rho((8, 8, 8), 2, seed=1), "D3Q19", order=4, variant=i)
+    name = sim.variant
+    sim.close()
+    return name
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 @pytest.mark.parametrize("order", [4, 8])
 def test_d3q19_mrt_distinct_rates(order, prec):
