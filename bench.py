@@ -494,6 +494,10 @@ def main():
         cc = copy_ceiling()
         log("copy:", json.dumps(cc))
         extra["copy_ceiling"] = cc
+        # counted traffic against what a device copy streams on this GPU
+        for r in extra.values():
+            if isinstance(r, dict) and r.get("traffic_ratio"):
+                r["frac_of_copy"] = r["achieved_gbs"] * r["traffic_ratio"] / cc["gbs"]
         if not args.no_steady:
             sd = steady_droplet()
             log("steady:", json.dumps(sd))
