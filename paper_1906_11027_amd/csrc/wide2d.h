@@ -504,6 +504,12 @@ static hipError_t launch_wide_shape(const StepArgs<T>& a, int variant, hipStream
     case 9:
         if constexpr (!WALLS) return launch_wide_tile2<T, L, ORDER, EDM, 128, 8, 1024>(a, s);
         return hipErrorInvalidValue;
+    case 10:
+        if constexpr (!WALLS) return launch_wide_tile2<T, L, ORDER, EDM, 64, 8, 1024>(a, s);
+        return hipErrorInvalidValue;
+    case 11:
+        if constexpr (!WALLS) return launch_wide_tile2<T, L, ORDER, EDM, 64, 12, 768>(a, s);
+        return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
 }
