@@ -491,7 +491,10 @@ static hipError_t launch_wide_shape(const StepArgs<T>& a, int variant, hipStream
     // wide rows use more of each cache line the pulls touch (reach M in x)
     case 4: return launch_wide_tile<T, L, ORDER, EDM, WALLS, 128, 16, 2>(a, s);
     case 5: return launch_wide_tile<T, L, ORDER, EDM, WALLS, 256, 8, 2>(a, s);
-    // two steps per launch (no walls: the wall kernels step one at a time)
+    // two steps per launch (no walls: the wall kernels step one at a time);
+    // at 8192^2 the tuner picks 64 x 8 with 1024 threads for D2Q13 E6 and
+    // 64 x 12 with 1024 for D2Q25 E8 (its 156 KB of LDS in FP32); a 32 x 16
+    // tile with 512 threads was slower on both
     case 6:
         if constexpr (!WALLS) return launch_wide_tile2<T, L, ORDER, EDM, 32, 8, 256>(a, s);
         return hipErrorInvalidValue;
@@ -509,6 +512,9 @@ static hipError_t launch_wide_shape(const StepArgs<T>& a, int variant, hipStream
         return hipErrorInvalidValue;
     case 11:
         if constexpr (!WALLS) return launch_wide_tile2<T, L, ORDER, EDM, 64, 12, 768>(a, s);
+        return hipErrorInvalidValue;
+    case 12:
+        if constexpr (!WALLS) return launch_wide_tile2<T, L, ORDER, EDM, 64, 12, 1024>(a, s);
         return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
