@@ -313,6 +313,9 @@ static hipError_t launch_order(const StepArgs<T>& a, int variant, hipStream_t s)
     // thread (the 256^2 grid has one 32 x 8 tile per CU)
     case 15: return launch_tile2<T, ORDER, 32, 8, 512>(a, s);
     case 16: return launch_tile2<T, ORDER, 32, 8, 1024>(a, s);
+    // measured and dropped: 64 x 32 and 128 x 16 tiles with 1024 threads
+    // (fewer halo nodes per tile node, but one block per CU); at 8192^2 the
+    // tuner kept 64 x 16 (FP32) and 32 x 16 (FP64)
     default: return hipErrorInvalidValue;
     }
 }
