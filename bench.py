@@ -115,12 +115,18 @@ TRAFFIC_RATIO = {
     ("d2q13_e6_pr_edm_8192", "wide2x64x8t512"): (0.563, 0.500),
     ("d2q13_e6_pr_edm_8192", "wide2x64x16t1024"): (0.563, 0.500),
     ("d2q13_e6_pr_edm_8192", "wide2x128x8t1024"): (0.533, 0.500),
+    ("d2q13_e6_pr_edm_8192", "wide2x64x8t1024"): (0.563, 0.500),
+    ("d2q13_e6_pr_edm_8192", "wide2x64x12t768"): (0.564, 0.500),
+    ("d2q13_e6_pr_edm_8192", "wide2x64x12t1024"): (0.564, 0.500),
     ("d2q13_e6_pr_edm_8192", "wide128x16r2"): (1.366, 1.000),
     ("d2q13_e6_pr_edm_8192", "wide256x8r2"): (1.372, 1.000),
     ("d2q13_e6_pr_edm_8192", "wide64x16r2"): (1.798, 1.000),
     ("d2q13_e6_pr_edm_8192", "wide64x16r4"): (1.864, 1.000),
     ("d2q25_e8_pr_edm_8192", "wide2x32x8t256"): (0.669, 0.500),
     ("d2q25_e8_pr_edm_8192", "wide2x64x8t512"): (0.600, 0.500),
+    ("d2q25_e8_pr_edm_8192", "wide2x64x8t1024"): (0.642, 0.500),
+    ("d2q25_e8_pr_edm_8192", "wide2x64x12t768"): (0.583, 0.500),
+    ("d2q25_e8_pr_edm_8192", "wide2x64x12t1024"): (0.592, 0.500),
     ("d2q25_e8_pr_edm_8192", "wide128x16r2"): (1.439, 1.000),
     ("d2q25_e8_pr_edm_8192", "wide256x8r2"): (1.401, 1.000),
     ("d2q25_e8_pr_edm_8192", "wide64x16r2"): (1.797, 1.000),
