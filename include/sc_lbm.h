@@ -314,7 +314,7 @@ typedef struct sc_lbm_batch sc_lbm_batch;
  *              0 one step per launch on 32 x 8 tiles, 1 / 2 / 3 two steps per
  *              launch (temporal blocking, one-step launches for an odd
  *              remainder) on 32 x 8, 64 x 16 and 32 x 16 tiles; any other
- *              value the automatic shape (3 for FP32, 1 for FP64);
+ *              value the automatic shape (3 for FP32, 2 for FP64);
  *   rho_init   n host pointers to [nx*ny] initial densities (each nullable),
  *              or NULL for rho = 1 everywhere;
  *   hip_stream as for sc_lbm_create.

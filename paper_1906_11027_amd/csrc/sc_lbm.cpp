@@ -23,12 +23,13 @@ using namespace sclbm;
 namespace {
 
 constexpr int kGraphSteps = 32;   // steps per captured graph (even)
-// automatic batched launch shapes (batch_shape_*): two steps per launch on
-// 32 x 16 tiles with 512 threads (FP32: 72.8 GLUPS on the 64-droplet sweep,
-// against 62-63 for the 64 x 16 and 32 x 8 tiles) and on 32 x 8 tiles (FP64,
-// whose wider shapes spill registers)
+// automatic batched launch shapes (batch_shape_*), two steps per launch:
+// FP32 on 32 x 16 tiles with 512 threads (72.7 GLUPS on the 64-droplet
+// sweep, against 63 for the 64 x 16 and 32 x 8 tiles), FP64 on 64 x 16
+// tiles with 1024 threads (34.5 GLUPS, against 28-29 for 32 x 8 and
+// 32 x 16); sc_lbm_batch_autotune measures them all
 constexpr int kBatchShapeFP32 = 3;
-constexpr int kBatchShapeFP64 = 1;
+constexpr int kBatchShapeFP64 = 2;
 constexpr int kFloorWindow = 50;   // checks the FP32 resolution rule fits a line to
 constexpr int kFloorHorizon = 300; // checks ahead over which that line's drift must stay in the band
 
