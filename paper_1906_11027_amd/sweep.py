@@ -7,8 +7,10 @@ start with its seeded +-1e-3 jitter -- are run to the steady-state rule
 (max|u| changing by less than `tol` between checks every K steps; an FP32
 state also stops on its resolution floor) two ways on the same GPU:
 
-    batched   one FP32 sweep, one launch per step over the active droplets'
-              tiles, converged droplets leaving the work list;
+    batched   one FP32 sweep, one launch per two steps over the active
+              droplets' tiles (the batched tuner's shape), converged droplets
+              leaving the work list; then the same batch widened to FP64
+              (sc_lbm_batch_promote) and finished to the literal rule;
     per-drop  plain FP64 runs, one droplet after the other (each with its own
               graph-replayed step loop).
 
@@ -24,7 +26,7 @@ import time
 
 import numpy as np
 
-from .sc_lbm import Batch, Sim
+from .sc_lbm import Batch, Sim, batch_autotune
 
 
 def _items(n_items, seed):
@@ -38,16 +40,26 @@ def run(n_items=64, tol=1e-10, max_steps=200000, obs_every=100, seed=1906, log=p
     import torch
     its, items = _items(n_items, seed)
     nodes = [it["rho0"].size for it in items]
+    shape, _ = batch_autotune(items, steps=64)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    bt = Batch(items, obs_every=obs_every)
+    bt = Batch(items, obs_every=obs_every, variant=shape)
     bt.step(max_steps, tol=tol)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     b_steps, b_by = zip(*[bt.status(k) for k in range(n_items)])
     b_obs = [bt.observe(k, fields=False)["obs"] for k in range(n_items)]
+    log("batched FP32 (%s): %.2f s, converged %d of %d" % (bt.variant, t_batch, sum(1 for v in b_by if v > 0),
+                                                          n_items))
+    bt.promote()
+    bt.step(max_steps, tol=tol)
+    torch.cuda.synchronize()
+    t_promoted = time.perf_counter() - t0
+    p_steps, p_by = zip(*[bt.status(k) for k in range(n_items)])
+    p_obs = [bt.observe(k, fields=False)["obs"] for k in range(n_items)]
     bt.close()
-    log("batched FP32: %.2f s, converged %d of %d" % (t_batch, sum(1 for v in b_by if v > 0), n_items))
+    log("then FP64 to the literal rule: %.2f s in all, converged %d of %d" % (
+        t_promoted, sum(1 for v in p_by if v == 1), n_items))
     f_steps, f_wall, f_rc, f_obs = [], [], [], []
     t0 = time.perf_counter()
     for k, it in enumerate(items):
@@ -70,11 +82,16 @@ def run(n_items=64, tol=1e-10, max_steps=200000, obs_every=100, seed=1906, log=p
     # field at rest, where |u| is round-off of either precision
     drops = [k for k in both if f_obs[k]["rho_max"] - f_obs[k]["rho_min"] > 0.5]
 
-    def rel(key, k):
-        return abs(b_obs[k][key] - f_obs[k][key]) / max(abs(f_obs[k][key]), 1e-300)
-    agree = {key: {"median": float(np.median([rel(key, k) for k in drops])) if drops else None,
-                   "max": float(np.max([rel(key, k) for k in drops])) if drops else None}
-             for key in ("max_u", "mean_u", "dp", "rho_min", "rho_max")}
+    def rel(obs, key, k):
+        return abs(obs[k][key] - f_obs[k][key]) / max(abs(f_obs[k][key]), 1e-300)
+
+    def agreement(obs, ks):
+        return {key: {"median": float(np.median([rel(obs, key, k) for k in ks])) if ks else None,
+                      "max": float(np.max([rel(obs, key, k) for k in ks])) if ks else None}
+                for key in ("max_u", "mean_u", "dp", "rho_min", "rho_max")}
+    agree = agreement(b_obs, drops)
+    both_p = [k for k in range(n_items) if f_conv[k] and p_by[k] == 1]
+    drops_p = [k for k in both_p if f_obs[k]["rho_max"] - f_obs[k]["rho_min"] > 0.5]
     return {
         "items": n_items, "tol": tol, "max_steps": max_steps, "obs_every": obs_every, "nodes_total": int(sum(nodes)),
         "batched_fp32": {"wall_s": t_batch, "steps_max": int(max(b_steps)), "steps_mean": float(np.mean(b_steps)),
@@ -85,6 +102,13 @@ def run(n_items=64, tol=1e-10, max_steps=200000, obs_every=100, seed=1906, log=p
         "per_droplet_fp64": {"wall_s": t_fp64, "steps_mean": float(np.mean(f_steps)),
                              "converged": int(sum(f_conv)), "nonfinite": int(sum(1 for rc in f_rc if rc != 0))},
         "speedup_wall": t_fp64 / t_batch,
+        "batched_fp32_then_fp64": {"wall_s": t_promoted, "steps_mean": float(np.mean(p_steps)),
+                                   "converged": int(sum(1 for v in p_by if v == 1)),
+                                   "nonfinite": int(sum(1 for v in p_by if v < 0)),
+                                   "not_converged": int(sum(1 for v in p_by if v == 0))},
+        "speedup_wall_fp64_finish": t_fp64 / t_promoted,
+        "droplets_both_fp64_finish": len(drops_p),
+        "steady_observables_fp64_finish_vs_fp64_rel": agreement(p_obs, drops_p),
         "converged_both": len(both),
         "steps_mean_both": {"batched_fp32": float(np.mean([b_steps[k] for k in both])) if both else None,
                             "per_droplet_fp64": float(np.mean([f_steps[k] for k in both])) if both else None},
@@ -94,6 +118,8 @@ def run(n_items=64, tol=1e-10, max_steps=200000, obs_every=100, seed=1906, log=p
                       "tau": its[k]["tau"], "batched_steps": int(b_steps[k]), "batched_by": int(b_by[k]),
                       "fp64_steps": f_steps[k], "fp64_rc": f_rc[k], "fp64_wall_s": f_wall[k],
                       "obs_fp32": {q: b_obs[k][q] for q in ("max_u", "mean_u", "dp", "rho_min", "rho_max")},
+                      "fp64_finish_steps": int(p_steps[k]), "fp64_finish_by": int(p_by[k]),
+                      "obs_fp64_finish": {q: p_obs[k][q] for q in ("max_u", "mean_u", "dp", "rho_min", "rho_max")},
                       "obs_fp64": {q: f_obs[k][q] for q in ("max_u", "mean_u", "dp", "rho_min", "rho_max")}}
                      for k in range(n_items)],
     }
