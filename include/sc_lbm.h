@@ -348,7 +348,13 @@ double sc_lbm_batch_rho_ref(const sc_lbm_batch* b);
  * FP32 to its steady-state rule is then finished to the literal rule (the
  * max |u| change below tol) with the FP64 state, whose resolution the rule
  * needs.  Each item's state is widened exactly into new FP64 buffers (same
- * storage shift rho_ref, freshly allocated; the FP32 buffers are freed);
+ * storage shift rho_ref, freshly allocated; the FP32 buffers are freed),
+ * then cleared of the net momentum the FP32 rounding gathered: the step
+ * conserves momentum and every item starts with none (Sec. 2, Eq. (3)-(4):
+ * the forcing adds sum F = 0 on the periodic grid), and a widened state
+ * that kept it would drift across the lattice and never meet the literal
+ * rule.  Every node's populations take the equilibrium change of the
+ * uniform velocity -J/M at its own density (masses unchanged);
  * items retired by a convergence rule rejoin the work list with their
  * convergence history cleared, quarantined items stay out, and every item
  * keeps its own step count.  The batch then runs the automatic FP64 launch

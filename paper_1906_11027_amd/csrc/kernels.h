@@ -440,6 +440,13 @@ hipError_t launch_batch_d2q9(int shape, const void* items, const int2* work, int
 // item): cwork lists (item, 16 x 16 tile) entries, one block each, whose
 // partial rows are cwork's indices; citems lists (item, first entry, entry
 // count) per active item; results holds kCheckSlots doubles per item.
+// Net momentum of an FP64 D2Q9 state (shifted storage, n nodes):
+// momentum_blocks() rows of (sum g, sum g c_x, sum g c_y) partials; and the
+// shift g_b += 3 w_b rho_x (c_b . u) of every node, which adds rho_x u to its
+// momentum and leaves its mass unchanged.
+int momentum_blocks();
+hipError_t launch_d2q9_mass_momentum(const double* g, int64_t n, double* partial, hipStream_t s);
+hipError_t launch_d2q9_momentum_shift(double* g, int64_t n, double rho_ref, double ux, double uy, hipStream_t s);
 int batch_check_tile();
 hipError_t launch_batch_check(const void* items, const int2* cwork, int ncwork, const int4* citems, int nactive,
                               int parity, int precision, const void* common, double* partials, double* results,

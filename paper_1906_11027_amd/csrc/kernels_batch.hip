@@ -318,4 +318,69 @@ hipError_t launch_batch_check(const void* items, const int2* cwork, int ncwork, 
     return hipGetLastError();
 }
 
+// ------------------------------------------- net momentum of a state ----
+// Stored mass and momentum of one FP64 D2Q9 state (shifted storage):
+// partial[blk] = (sum g_b, sum g_b c_bx, sum g_b c_by) over the block's
+// grid-stride share of the n nodes; a fixed-order tree in LDS per block.
+constexpr int kMomThreads = 256;
+
+__global__ void __launch_bounds__(kMomThreads)
+k_d2q9_mass_momentum(const double* __restrict__ g, int64_t n, double* __restrict__ partial)
+{
+    __shared__ double red[3][kMomThreads];
+    double m = 0.0, jx = 0.0, jy = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kMomThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kMomThreads) {
+#pragma unroll
+        for (int b = 0; b < 9; ++b) {
+            const double v = g[b * n + i];
+            m += v;
+            jx += D2Q9::cx[b] * v;
+            jy += D2Q9::cy[b] * v;
+        }
+    }
+    red[0][threadIdx.x] = m;
+    red[1][threadIdx.x] = jx;
+    red[2][threadIdx.x] = jy;
+    __syncthreads();
+    for (int w = kMomThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) partial[blockIdx.x * 3 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Every node's populations move by the equilibrium change of a uniform
+// velocity shift du at the node's own (post-collision) density:
+// g_b += 3 w_b rho_x (c_b . du).  The node's mass is unchanged (sum_b w_b c_b
+// = 0) and its momentum grows by rho_x du, the state's by M du.
+__global__ void k_d2q9_momentum_shift(double* __restrict__ g, int64_t n, double rho_ref, double ux, double uy)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double rho = rho_ref;
+#pragma unroll
+        for (int b = 0; b < 9; ++b) rho += g[b * n + i];
+#pragma unroll
+        for (int b = 1; b < 9; ++b)
+            g[b * n + i] += 3.0 * D2Q9::w[b] * rho * (D2Q9::cx[b] * ux + D2Q9::cy[b] * uy);
+    }
+}
+
+int momentum_blocks() { return 256; }
+
+hipError_t launch_d2q9_mass_momentum(const double* g, int64_t n, double* partial, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_d2q9_mass_momentum, dim3(momentum_blocks()), dim3(kMomThreads), 0, s, g, n, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_d2q9_momentum_shift(double* g, int64_t n, double rho_ref, double ux, double uy, hipStream_t s)
+{
+    const int64_t nb = (n + 255) / 256;
+    hipLaunchKernelGGL(k_d2q9_momentum_shift, dim3((unsigned)(nb < 4096 ? nb : 4096)), dim3(256), 0, s, g, n,
+                       rho_ref, ux, uy);
+    return hipGetLastError();
+}
+
 }  // namespace sclbm

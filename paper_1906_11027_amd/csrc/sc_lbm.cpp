@@ -1684,6 +1684,43 @@ static void drop_obs(sc_lbm* h)
     h->obs.ready = false;
 }
 
+// Take the net momentum out of every widened item's state.  The step
+// conserves momentum exactly, and every batch item starts with none (f at
+// rest, and the interaction forces sum to zero on the periodic grid); the
+// FP32 stage's rounding has gathered a little (a drift of ~1e-8 per step on
+// the sweep's droplets), which the FP64 state would keep: its droplet would
+// then cross the lattice and its max |u| keep changing, so the literal rule
+// is never met.  Each node's populations take the equilibrium change of the
+// uniform velocity -J/M at its own density; masses are unchanged.
+static hipError_t batch_remove_momentum(sc_lbm_batch* b)
+{
+    const int nb = momentum_blocks();
+    double* part = nullptr;
+    hipError_t e = hipMalloc(&part, sizeof(double) * 3 * nb);
+    std::vector<double> hp(3 * (size_t)nb);
+    for (int i = 0; i < b->n && e == hipSuccess; ++i) {
+        sc_lbm* h = b->items[i];
+        double* g = (double*)h->f[h->cur];
+        e = launch_d2q9_mass_momentum(g, h->n, part, b->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hp.data(), part, sizeof(double) * 3 * nb, hipMemcpyDeviceToHost, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) break;
+        double m = 0.0, jx = 0.0, jy = 0.0;
+        for (int k = 0; k < nb; ++k) {
+            m += hp[3 * k];
+            jx += hp[3 * k + 1];
+            jy += hp[3 * k + 2];
+        }
+        const double M = m + h->p.rho_ref * (double)h->n;
+        if (!(M > 0.0) || !std::isfinite(M) || !std::isfinite(jx) || !std::isfinite(jy)) continue;   // quarantined
+        e = launch_d2q9_momentum_shift(g, h->n, h->p.rho_ref, -jx / M, -jy / M, b->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    hipFree(part);
+    return e;
+}
+
 extern "C" int sc_lbm_batch_promote(sc_lbm_batch* b)
 {
     if (!b || b->precision != SC_FP32_SHIFTED) return SC_E_INVAL;
@@ -1742,6 +1779,7 @@ extern "C" int sc_lbm_batch_promote(sc_lbm_batch* b)
     }
     if (e == hipSuccess) e = hipMemcpyAsync(desc, dd.data(), dd.size(), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e == hipSuccess) e = batch_remove_momentum(b);
     if (e != hipSuccess) {
         // the items may already point into the new pool: keep it (freed with the batch)
         hipFree(b->pool);

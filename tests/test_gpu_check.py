@@ -165,6 +165,31 @@ def test_promote_widens_the_state_and_steps_in_fp64():
     bt.close()
 
 
+def test_promote_removes_the_gathered_momentum():
+    """An FP32 batch run to its rules has gathered a little net momentum by
+    rounding (the step conserves momentum and the start has none).
+    sc_lbm_batch_promote takes it out: afterwards the total momentum is zero
+    to FP64 rounding, and every item keeps its mass (to the precision of the
+    FP32 state's own mass sum)."""
+    specs = [((67, 67), 19, 6, -4.9, 1.2), ((60, 52), 14, 8, -5.1, 1.0)]
+    items = [{"rho0": droplet_rho(s, R, seed=50 + k), "order": o, "G": G, "tau": t}
+             for k, (s, R, o, G, t) in enumerate(specs)]
+    bt = Batch(items, precision="fp32", obs_every=100)
+    bt.step(20000, tol=1e-10)
+    before = [bt.observe(k, fields=False)["obs"] for k in range(len(items))]
+    bt.promote()
+    after = [bt.observe(k, fields=False)["obs"] for k in range(len(items))]
+    for k, (b, a) in enumerate(zip(before, after)):
+        jb, ja = float(np.hypot(*b["mom"][:2])), float(np.hypot(*a["mom"][:2]))
+        say("item %d: |J| %.3e before, %.3e after promotion; mass %.12e -> %.12e" % (
+            k, jb, ja, b["mass"], a["mass"]))
+        assert ja <= 1e-12 * a["mass"]
+        # the FP32 state's observables sum densities formed in FP32 (1e-8
+        # relative here); the shift itself changes no node's mass
+        assert abs(a["mass"] - b["mass"]) <= 1e-7 * b["mass"]
+    bt.close()
+
+
 def test_fp32_sweep_finished_in_fp64():
     """An FP32 batch run to its steady-state rules, promoted, then run to
     the literal FP64 rule: every item rejoins, counts its own steps and
