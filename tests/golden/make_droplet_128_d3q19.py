@@ -8,7 +8,7 @@ through the centre at 2,000 steps and at the end.
 
 Only the oracle computes these values.  The stored file came from
     python tests/golden/make_droplet_128_d3q19.py
-(20,000 steps; about 6 h on 7 cores).  The run saves the oracle's
+(20,000 steps; 5.8 h on 6 OpenMP threads).  The run saves the oracle's
 distributions every `ckpt_every` steps to --ckpt (outside the repository)
 and resumes from there when restarted: a step depends only on the
 distributions, so a resumed run is bitwise the same as an uninterrupted one.
