@@ -390,6 +390,166 @@ k_conv_bwd_w(const float* __restrict__ in, const float* __restrict__ gout, float
     if ((tid & 7) == 0 && (tid >> 3) < cout) pb[E + (tid >> 3)] = bacc;
 }
 
+// The 32 -> 32 weight gradient on bf16 MFMAs.  The same contraction over
+// pixels, gW_t[co][ci] += g[co][p] x[ci][p + d_t], with both operands split
+// exactly into three bf16 parts and the six part products whose weights
+// reach 2^-24 summed (hi.hi, hi.mid, mid.hi, hi.lo, mid.mid, lo.hi): FP32
+// operands to within about 2^-24 of each product.  k runs over 32 pixels
+// (two tile rows) per MFMA, 8 consecutive pixels of one row per lane.  A tap
+// shifts the input by dx = 0, 1, 2 columns, so its 8-pixel run is 16-byte
+// aligned (one vector read), 4-byte aligned (four dword reads) or 2-byte
+// aligned (five dword reads realigned by v_alignbyte).  LDS: the input tile
+// with its halo as [part][ci][18 rows][24 columns] and the output gradient as
+// [part][co][256 + 8]; channel strides of 220 and 132 dwords put the 16
+// channels a quarter-wave reads on distinct bank quads.  One block per CU
+// (135 KB of LDS); wave v owns the 16 x 16 block (co tile v / 2, ci tile
+// v % 2) of all nine taps.  The bias gradient sums the FP32 output gradient
+// per thread and channel, then over the block in a fixed order.
+constexpr int kXRS = 24;                       // bf16 per input row in LDS (18 + pad, 16-byte rows)
+constexpr int kXCS = 18 * kXRS + 8;            // bf16 per input channel (220 dwords = 28 mod 64)
+constexpr int kXPart = MAXC * kXCS;
+constexpr int kGCS = TS * TS + 8;              // bf16 per output-gradient channel (132 dwords = 4 mod 64)
+constexpr int kGPart = MAXC * kGCS;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <int DX>
+__device__ __forceinline__ bf16x8 x_run(const uint16_t* __restrict__ xs, int e)
+{
+    if (DX == 0) return *(const bf16x8*)(xs + e);
+    u32x4 v;
+    if (DX == 2) {
+        const uint32_t* d = (const uint32_t*)(xs + e);
+        v = u32x4{d[0], d[1], d[2], d[3]};
+    } else {
+        const uint32_t* d = (const uint32_t*)(xs + e - 1);
+        const uint32_t d0 = d[0], d1 = d[1], d2 = d[2], d3 = d[3], d4 = d[4];
+        v = u32x4{__builtin_amdgcn_alignbyte(d1, d0, 2), __builtin_amdgcn_alignbyte(d2, d1, 2),
+                  __builtin_amdgcn_alignbyte(d3, d2, 2), __builtin_amdgcn_alignbyte(d4, d3, 2)};
+    }
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+__global__ void __launch_bounds__(TS* TS, 1)
+k_conv_bwd_w_bf16(const float* __restrict__ in, const float* __restrict__ gout, float* __restrict__ partial,
+                  int batch, int h, int wd)
+{
+    __shared__ __align__(16) uint16_t xs[3 * kXPart];
+    __shared__ __align__(16) uint16_t gs[3 * kGPart];
+    const int tid = threadIdx.y * TS + threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int mt = wv >> 1, nt = wv & 1;
+    const int r16 = lane & 15, kq = lane >> 4;
+    const int tiles_x = (wd + TS - 1) / TS, tiles_y = (h + TS - 1) / TS;
+    const int nwork = tiles_x * tiles_y * batch;
+    const int64_t plane = (int64_t)h * wd;
+    constexpr int E = MAXC * MAXC * 9;
+    f32x4 acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum[MAXC];
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c) bsum[c] = 0.f;
+    const bool two = tid + TS * TS < kHaloPx;
+    const int r1 = two ? tid + TS * TS : 0;
+    // the tile's loads for the next work item are issued before this one's
+    // products, so their latency hides behind the MFMAs (one block per CU)
+    float gv[MAXC], xv[MAXC], xw[MAXC];
+    auto load = [&](int wi) {
+        const int b = wi / (tiles_x * tiles_y), tt = wi % (tiles_x * tiles_y);
+        const int x0 = (tt % tiles_x) * TS, y0 = (tt / tiles_x) * TS;
+        const float* gb = gout + (int64_t)b * MAXC * plane;
+        const float* xb0 = in + (int64_t)b * MAXC * plane;
+        const int x = x0 + tid % TS, y = y0 + tid / TS;
+        const bool in_img = x < wd && y < h;
+        const uint32_t po = (uint32_t)(y * wd + x);
+        const uint32_t h0 = (uint32_t)(wrapc(y0 + tid / (TS + 2) - 1, h) * wd + wrapc(x0 + tid % (TS + 2) - 1, wd));
+        const uint32_t h1 = (uint32_t)(wrapc(y0 + r1 / (TS + 2) - 1, h) * wd + wrapc(x0 + r1 % (TS + 2) - 1, wd));
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) {
+            const uint32_t co = (uint32_t)c * (uint32_t)plane;
+            gv[c] = in_img ? gb[co + po] : 0.f;
+            xv[c] = xb0[co + h0];
+            xw[c] = two ? xb0[co + h1] : 0.f;
+        }
+    };
+    int wi = xcd_swizzle(blockIdx.x, gridDim.x);
+    if (wi < nwork) load(wi);
+    for (; wi < nwork; wi += gridDim.x) {
+        __syncthreads();   // the previous item's reads of gs and xs are done
+        {
+            const int ly0 = tid / (TS + 2), lx0 = tid % (TS + 2);
+            const int ly1 = r1 / (TS + 2), lx1 = r1 % (TS + 2);
+#pragma unroll
+            for (int c = 0; c < MAXC; ++c) {
+                bsum[c] += gv[c];
+                uint32_t p0, p1, p2;
+                split3(gv[c], p0, p1, p2);
+                uint16_t* gd = gs + c * kGCS + tid;
+                gd[0] = (uint16_t)p0;
+                gd[kGPart] = (uint16_t)p1;
+                gd[2 * kGPart] = (uint16_t)p2;
+                split3(xv[c], p0, p1, p2);
+                uint16_t* xd = xs + c * kXCS + ly0 * kXRS + lx0;
+                xd[0] = (uint16_t)p0;
+                xd[kXPart] = (uint16_t)p1;
+                xd[2 * kXPart] = (uint16_t)p2;
+                if (two) {
+                    split3(xw[c], p0, p1, p2);
+                    uint16_t* xe = xs + c * kXCS + ly1 * kXRS + lx1;
+                    xe[0] = (uint16_t)p0;
+                    xe[kXPart] = (uint16_t)p1;
+                    xe[2 * kXPart] = (uint16_t)p2;
+                }
+            }
+        }
+        __syncthreads();
+        if (wi + (int)gridDim.x < nwork) load(wi + gridDim.x);
+        const uint16_t* ga = gs + (mt * 16 + r16) * kGCS;
+        const int xb = (nt * 16 + r16) * kXCS;
+#pragma unroll 1
+        for (int ch = 0; ch < TS * TS / 32; ++ch) {
+            const int p0 = 32 * ch + 8 * kq;           // this lane's 8 pixels
+            const int ry = p0 / TS, cx0 = p0 % TS;     // tile row, first column
+            bf16x8 a[3];
+#pragma unroll
+            for (int gp = 0; gp < 3; ++gp) a[gp] = *(const bf16x8*)(ga + gp * kGPart + p0);
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int dy = t / 3, dx = t % 3;
+                const int e = xb + (ry + dy) * kXRS + cx0 + dx;
+#pragma unroll
+                for (int xp = 0; xp < 3; ++xp) {
+                    const int ex = e + xp * kXPart;
+                    const bf16x8 bv = dx == 0 ? x_run<0>(xs, ex) : (dx == 1 ? x_run<1>(xs, ex) : x_run<2>(xs, ex));
+#pragma unroll
+                    for (int gp = 0; gp + xp < 3; ++gp)
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[gp], bv, acc[t], 0, 0, 0);
+                }
+            }
+        }
+    }
+    float* pb = partial + (int64_t)blockIdx.x * (E + MAXC);
+    const int ci = nt * 16 + r16;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int co = mt * 16 + 4 * kq + i;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) pb[(ci * MAXC + co) * 9 + t] = acc[t][i];
+    }
+    // bias: each thread's per-channel sums, then over the block in a fixed
+    // order (thread 0, 1, ...) through LDS
+    __syncthreads();
+    float* red = (float*)xs;   // MAXC x 256 floats fit in the input tile's LDS
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c) red[c * (TS * TS) + tid] = bsum[c];
+    __syncthreads();
+    if (tid < MAXC) {
+        float sb = 0.f;
+        for (int k = 0; k < TS * TS; ++k) sb += red[tid * (TS * TS) + k];
+        pb[E + tid] = sb;
+    }
+}
+
 // Sum the per-block partials in a fixed order: gw[co][ci][k] from the
 // ci-major partial entries, gbias[co] from the trailing bias columns.  A block
 // covers 64 columns with 4 row groups (rows r = g mod 4), combined in group
@@ -654,7 +814,11 @@ extern "C" int sc_nn_conv3x3_bwd_weight(const float* in, const float* gout, floa
         return SC_E_INVAL;
     const int E = cin * cout * 9;
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_conv_bwd_w, nblk, dim3(TS, TS), 0, s, in, gout, partial_scratch, batch, cin, cout, h, wd);
+    if (cin == MAXC && cout == MAXC)
+        hipLaunchKernelGGL(k_conv_bwd_w_bf16, nblk, dim3(TS, TS), 0, s, in, gout, partial_scratch, batch, h, wd);
+    else
+        hipLaunchKernelGGL(k_conv_bwd_w, nblk, dim3(TS, TS), 0, s, in, gout, partial_scratch, batch, cin, cout, h,
+                           wd);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return nn_status(e);
     hipLaunchKernelGGL(k_sum_partials, (E + cout + kSumCols - 1) / kSumCols, kSumCols * kSumGroups, 0, s,
