@@ -170,13 +170,21 @@ __device__ __forceinline__ void collide_d2q9_srt(T (&g)[9], T drho, T Fx, T Fy, 
     const T usq = T(1.5) * (ux * ux + uy * uy);
     const T uF = ux * Fx + uy * Fy;
     const T om = a.omega, gu = a.guo;
+    // Velocities b and b + 2 (b = 1, 2, 5, 6) are opposite.  Over such a
+    // pair the relaxed equilibrium plus the Guo source, om feq + gu phihat,
+    // splits into a part even in c and a part odd in c:
+    //   even  w [K0 + cu (a1 cu + a2 cF)],  K0 = om (drho - rho usq) - 3 gu u.F,
+    //         a1 = 4.5 om rho, a2 = 9 gu;
+    //   odd   w (b1 cu + b2 cF),            b1 = 3 om rho, b2 = 3 gu,
+    // with cu = c.u and cF = c.F formed once per pair, and
+    //   g*_{+-} = g_{+-} + (even +- odd - om g_{+-}).
     // Collision conserves mass exactly; the rest population closes the
     // balance in difference form, g0* = g0 + sum_{b>=1} (g_b - g_b*): the
     // increments are small, so the node's mass keeps only the rounding of
     // the stored g0* (not that of two 9-term sums of O(rho) values).
-    // Velocities b and b + 2 (b = 1, 2, 5, 6) are opposite: over such a pair
-    // feq and the Guo source split into a part even in c and a part odd in c,
-    // so each pair's c.u and c.F are formed once (as for D3Q19 below).
+    const T K0 = om * (drho - rho * usq) - T(3) * gu * uF;
+    const T a1 = T(4.5) * om * rho, a2 = T(9) * gu;
+    const T b1 = T(3) * om * rho, b2 = T(3) * gu;
     T dm = T(0);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -185,13 +193,11 @@ __device__ __forceinline__ void collide_d2q9_srt(T (&g)[9], T drho, T Fx, T Fy, 
         const T cu = T(D2Q9::cx[bp]) * ux + T(D2Q9::cy[bp]) * uy;
         const T cF = T(D2Q9::cx[bp]) * Fx + T(D2Q9::cy[bp]) * Fy;
         const T w = T(D2Q9::w[bp]);
-        const T es = w * (drho + rho * (T(4.5) * cu * cu - usq));
-        const T ea = w * rho * (T(3) * cu);
-        const T ps = gu * w * (T(9) * cu * cF - T(3) * uF);
-        const T pa = gu * w * (T(3) * cF);
+        const T S = w * (K0 + cu * (a1 * cu + a2 * cF));
+        const T A = w * (b1 * cu + b2 * cF);
         const T gp = g[bp], gm = g[bm];
-        const T np = gp - om * (gp - (es + ea)) + (ps + pa);
-        const T nm = gm - om * (gm - (es - ea)) + (ps - pa);
+        const T np = gp + ((S + A) - om * gp);
+        const T nm = gm + ((S - A) - om * gm);
         dm += (gp - np) + (gm - nm);
         g[bp] = np;
         g[bm] = nm;
@@ -272,50 +278,54 @@ __device__ __forceinline__ void collide_d3q19(T (&g)[19], T drho, T Fx, T Fy, T 
     // collide_d2q9_srt): dm = sum_{b>=1} (g_b - g_b*), g0* = g0 + dm
     T dm = T(0);
     if (!MRT) {
+        // om feq + gu phihat over a pair, even and odd parts as in the D2Q9
+        // collision: w [K0 + cu (a1 cu + a2 cF)] and w (b1 cu + b2 cF)
         const T om = a.omega, gu = a.guo;
+        const T K0 = om * (drho - rho * usq) - T(3) * gu * uF;
+        const T a1 = T(4.5) * om * rho, a2 = T(9) * gu;
+        const T b1 = T(3) * om * rho, b2 = T(3) * gu;
 #pragma unroll
         for (int b = 1; b < 19; b += 2) {
             const T cu = T(L::cx[b]) * ux + T(L::cy[b]) * uy + T(L::cz[b]) * uz;
             const T cF = T(L::cx[b]) * Fx + T(L::cy[b]) * Fy + T(L::cz[b]) * Fz;
             const T w = T(L::w[b]);
-            const T es = w * (drho + rho * (T(4.5) * cu * cu - usq));
-            const T ea = w * rho * (T(3) * cu);
-            const T ps = gu * w * (T(9) * cu * cF - T(3) * uF);
-            const T pa = gu * w * (T(3) * cF);
+            const T S = w * (K0 + cu * (a1 * cu + a2 * cF));
+            const T A = w * (b1 * cu + b2 * cF);
             const T gp = g[b], gm = g[b + 1];
-            const T np = gp - om * (gp - (es + ea)) + (ps + pa);
-            const T nm = gm - om * (gm - (es - ea)) + (ps - pa);
+            const T np = gp + ((S + A) - om * gp);
+            const T nm = gm + ((S - A) - om * gm);
             dm += (gp - np) + (gm - nm);
             g[b] = np;
             g[b + 1] = nm;
         }
         g[0] += dm;
     } else {
+        // BGK at the ghost rate sg with the Guo source (1 - sg/2) phihat, plus
+        // for each moment k of the bulk and shear groups
+        //   (sg - s_k) [m_k . v] m_k / |m_k|^2,  v = f - feq + phihat / 2.
+        // Pass 1 forms the moments m_k . v; every m_k is even in c, so a pair
+        // enters through v_b + v_{b+1} = (g_b + g_{b+1}) - 2 feq_even + phihat_even
+        //   = (g_b + g_{b+1}) - w [V0 + 9 cu (rho cu - cF)],
+        //   V0 = 2 (drho - rho usq) + 3 u.F.
+        // Pass 2 applies BGK, source and the (even) moment correction d of the
+        // pair in one increment: g*_{+-} = g_{+-} + ((even + d) +- odd - sg g_{+-}),
+        // even and odd as in the SRT branch with om -> sg, gu -> 1 - sg/2.
         const T sg = a.s_ghost;
         const T gh = T(1) - T(0.5) * sg;
         // the rest population enters only the bulk moment (19 c^2 - 30 = -30)
         const T w0 = T(L::w[0]);
         const T v0 = (g[0] - w0 * (drho - rho * usq)) + T(0.5) * (w0 * (T(-3) * uF));
+        const T V0 = T(2) * (drho - rho * usq) + T(3) * uF;
         T mb = T(-30) * v0, m1 = T(0), m2 = T(0), m3 = T(0), m4 = T(0), m5 = T(0);
+        T cuv[9], cFv[9];
 #pragma unroll
         for (int b = 1; b < 19; b += 2) {
             const int cx = L::cx[b], cy = L::cy[b], cz = L::cz[b];
             const T cu = T(cx) * ux + T(cy) * uy + T(cz) * uz;
             const T cF = T(cx) * Fx + T(cy) * Fy + T(cz) * Fz;
-            const T w = T(L::w[b]);
-            const T es = w * (drho + rho * (T(4.5) * cu * cu - usq));
-            const T ea = w * rho * (T(3) * cu);
-            const T ps = w * (T(9) * cu * cF - T(3) * uF);
-            const T pa = w * (T(3) * cF);
-            const T gp = g[b], gm = g[b + 1];
-            const T nep = gp - (es + ea), nem = gm - (es - ea);
-            const T php = ps + pa, phm = ps - pa;
-            const T vs = (nep + T(0.5) * php) + (nem + T(0.5) * phm);   // v_b + v_{b+1}
-            const T gnp = gp - sg * nep + gh * php;
-            const T gnm = gm - sg * nem + gh * phm;
-            dm += (gp - gnp) + (gm - gnm);
-            g[b] = gnp;
-            g[b + 1] = gnm;
+            cuv[b / 2] = cu;
+            cFv[b / 2] = cF;
+            const T vs = (g[b] + g[b + 1]) - T(L::w[b]) * (V0 + T(9) * cu * (rho * cu - cF));
             const int c2 = cx * cx + cy * cy + cz * cz;
             mb += T(19 * c2 - 30) * vs;
             const int p1 = 2 * cx * cx - cy * cy - cz * cz, p2 = cy * cy - cz * cz;
@@ -329,8 +339,11 @@ __device__ __forceinline__ void collide_d3q19(T (&g)[19], T drho, T Fx, T Fy, T 
         const T ks = sg - a.omega;
         const T k1 = ks * m1 * T(1.0 / 36.0), k2 = ks * m2 * T(1.0 / 12.0);
         const T k3 = ks * m3 * T(0.25), k4 = ks * m4 * T(0.25), k5 = ks * m5 * T(0.25);
+        const T K0 = sg * (drho - rho * usq) - T(3) * gh * uF;
+        const T a1 = T(4.5) * sg * rho, a2 = T(9) * gh;
+        const T b1 = T(3) * sg * rho, b2 = T(3) * gh;
 #pragma unroll
-        for (int b = 1; b < 19; b += 2) {   // the correction is even in c: one per pair
+        for (int b = 1; b < 19; b += 2) {
             const int cx = L::cx[b], cy = L::cy[b], cz = L::cz[b];
             const int c2 = cx * cx + cy * cy + cz * cz;
             T d = kb * T(19 * c2 - 30);
@@ -340,10 +353,16 @@ __device__ __forceinline__ void collide_d3q19(T (&g)[19], T drho, T Fx, T Fy, T 
             if (cx * cy) d += k3 * T(cx * cy);
             if (cy * cz) d += k4 * T(cy * cz);
             if (cx * cz) d += k5 * T(cx * cz);
-            const T fp = g[b] + d, fm = g[b + 1] + d;
-            dm += (g[b] - fp) + (g[b + 1] - fm);
-            g[b] = fp;
-            g[b + 1] = fm;
+            const T cu = cuv[b / 2], cF = cFv[b / 2];
+            const T w = T(L::w[b]);
+            const T Sd = w * (K0 + cu * (a1 * cu + a2 * cF)) + d;
+            const T A = w * (b1 * cu + b2 * cF);
+            const T gp = g[b], gm = g[b + 1];
+            const T np = gp + ((Sd + A) - sg * gp);
+            const T nm = gm + ((Sd - A) - sg * gm);
+            dm += (gp - np) + (gm - nm);
+            g[b] = np;
+            g[b + 1] = nm;
         }
         g[0] += dm;
     }

@@ -79,15 +79,32 @@ __device__ __forceinline__ void d2q9_tile2_body(const StepArgs<T>& a, int x0, in
     // loop has a compile-time bound and is unrolled, so the pulls of all its
     // nodes are in flight together.  The pulled values stay in registers for
     // phase 2, whose (R+1)-halo region lies inside this one.
+    // A tile whose pulled region lies inside the grid (one test per block)
+    // takes its addresses without wrapping.
     constexpr int K1 = (P1N + NT - 1) / NT;
     T g[K1][9];
     {
+        if (x0 > H1 && x0 + TX + H1 < nx && y0 > H1 && y0 + TY + H1 < ny) {
 #pragma unroll
-        for (int q = 0; q < K1; ++q) {
-            const int i = tid + q * NT;
-            if (i < P1N) {
-                const int ly = i / P1W, lx = i - ly * P1W;
-                pull_global(x0 - H1 + lx, y0 - H1 + ly, g[q]);
+            for (int q = 0; q < K1; ++q) {
+                const int i = tid + q * NT;
+                if (i < P1N) {
+                    const int ly = i / P1W, lx = i - ly * P1W;
+                    const uint32_t own = (uint32_t)(y0 - H1 + ly) * rowb + (uint32_t)(x0 - H1 + lx) * TS;
+#pragma unroll
+                    for (int b = 0; b < 9; ++b)
+                        g[q][b] = ld_off(a.fin + b * n, own - (uint32_t)D2Q9::cy[b] * rowb -
+                                                            (uint32_t)(D2Q9::cx[b] * (int)TS));
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < K1; ++q) {
+                const int i = tid + q * NT;
+                if (i < P1N) {
+                    const int ly = i / P1W, lx = i - ly * P1W;
+                    pull_global(x0 - H1 + lx, y0 - H1 + ly, g[q]);
+                }
             }
         }
 #pragma unroll

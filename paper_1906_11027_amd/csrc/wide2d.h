@@ -60,6 +60,17 @@ __device__ __forceinline__ void pull_lat(const T* __restrict__ f, int64_t n, con
     for (int b = 0; b < L::Q; ++b) g[b] = ld_off(f + b * n, yo[M - L::cy[b]] + xo[M - L::cx[b]]);
 }
 
+// the same pull for a node whose neighbours need no wrapping: own is the
+// node's byte offset, rowb the byte stride of a row
+template <typename T, typename L>
+__device__ __forceinline__ void pull_lat_inner(const T* __restrict__ f, int64_t n, uint32_t own, uint32_t rowb,
+                                               T (&g)[L::Q])
+{
+#pragma unroll
+    for (int b = 0; b < L::Q; ++b)
+        g[b] = ld_off(f + b * n, own - (uint32_t)L::cy[b] * rowb - (uint32_t)(L::cx[b] * (int)sizeof(T)));
+}
+
 // index of -c_b in the lattice's velocity list
 template <typename L>
 constexpr int opposite(int b)
@@ -103,10 +114,14 @@ constexpr bool has_opposite_pairs()
 //   Guo:  u = (j + F/2)/rho,  g* = g - (g - geq(u))/tau + (1 - 1/(2 tau)) phihat(u, F)
 //   EDM:  v = j/rho, dv = F/rho,  g* = g - (g - geq(v))/tau + feq(v + dv) - feq(v)
 // with feq = w rho [1 + c.u/cs2 + (c.u)^2/(2 cs2^2) - u^2/(2 cs2)] and
-// phihat = w [(c - u)/cs2 + (c.u) c / cs2^2] . F.  The EDM increment is
-// expanded as a difference (c.dv (2 c.v + c.dv) etc.) so it carries no
-// cancellation of two equilibria.  Both conserve mass exactly.  The rest
-// population closes the balance in difference form,
+// phihat = w [(c - u)/cs2 + (c.u) c / cs2^2] . F.  Over a pair of opposite
+// velocities (b, -b) the relaxed equilibrium plus the source splits into a
+// part even in c and a part odd in c, each a short polynomial in c.u and c.F
+// (Guo) or c.v and c.s with s = v + dv (EDM), and
+//   g*_{+-} = g_{+-} + (even +- odd - om g_{+-}).
+// The EDM increment enters through (c.s)^2 - (c.v)^2 and s^2 - v^2, never as
+// the difference of two computed equilibria.  Both conserve mass exactly.
+// The rest population closes the balance in difference form,
 //   g0* = g0 + sum_{b>=1} (g_b - g_b*),
 // whose terms are the small collision increments: the only rounding left in
 // the node's mass is that of the stored g0*, where summing the populations
@@ -120,8 +135,11 @@ __device__ __forceinline__ void collide_lat(T (&g)[L::Q], T drho, T Fx, T Fy, co
     T jx = T(0), jy = T(0);
 #pragma unroll
     for (int b = 1; b < Q; ++b) {
-        if (L::cx[b]) jx += T(L::cx[b]) * g[b];
-        if (L::cy[b]) jy += T(L::cy[b]) * g[b];
+        const int m = opposite<L>(b);
+        if (m < b) continue;
+        const T d = g[b] - g[m];
+        if (L::cx[b]) jx += T(L::cx[b]) * d;
+        if (L::cy[b]) jy += T(L::cy[b]) * d;
     }
     const T inv = fast_rcp(rho);
     T dm = T(0);   // sum of g_b - g_b* over b >= 1
@@ -134,8 +152,10 @@ __device__ __forceinline__ void collide_lat(T (&g)[L::Q], T drho, T Fx, T Fy, co
         const T usq = T(0.5 * ics) * (ux * ux + uy * uy);
         const T uF = ux * Fx + uy * Fy;
         const T gu = a.guo;
-        // over each pair (b, -b) feq and the Guo source split into a part
-        // even in c and a part odd in c; c.u and c.F are formed once per pair
+        // om feq + gu phihat:  even  w [K0 + cu (a1 cu + a2 cF)],  odd  w (b1 cu + b2 cF)
+        const T K0 = om * (drho - rho * usq) - gu * T(ics) * uF;
+        const T a1 = om * rho * T(ics2h), a2 = gu * T(2.0 * ics2h);
+        const T b1 = om * rho * T(ics), b2 = gu * T(ics);
 #pragma unroll
         for (int b = 1; b < Q; ++b) {
             const int m = opposite<L>(b);
@@ -143,37 +163,41 @@ __device__ __forceinline__ void collide_lat(T (&g)[L::Q], T drho, T Fx, T Fy, co
             const T cu = T(L::cx[b]) * ux + T(L::cy[b]) * uy;
             const T cF = T(L::cx[b]) * Fx + T(L::cy[b]) * Fy;
             const T w = T(L::w[b]);
-            const T es = w * (drho + rho * (T(ics2h) * cu * cu - usq));
-            const T ea = w * rho * (T(ics) * cu);
-            const T ps = gu * w * (T(2.0 * ics2h) * cu * cF - T(ics) * uF);
-            const T pa = gu * w * (T(ics) * cF);
+            const T S = w * (K0 + cu * (a1 * cu + a2 * cF));
+            const T A = w * (b1 * cu + b2 * cF);
             const T gp = g[b], gm = g[m];
-            const T np = gp - om * (gp - (es + ea)) + (ps + pa);
-            const T nm = gm - om * (gm - (es - ea)) + (ps - pa);
+            const T np = gp + ((S + A) - om * gp);
+            const T nm = gm + ((S - A) - om * gm);
             dm += (gp - np) + (gm - nm);
             g[b] = np;
             g[m] = nm;
         }
     } else {
         const T vx = jx * inv, vy = jy * inv;
-        const T dx = Fx * inv, dy = Fy * inv;
+        const T sx = vx + Fx * inv, sy = vy + Fy * inv;   // s = v + F/rho
         const T vsq = T(0.5 * ics) * (vx * vx + vy * vy);
-        const T dsq = T(0.5 * ics) * (dx * (T(2) * vx + dx) + dy * (T(2) * vy + dy));
-        // the same even/odd split for feq(v) and feq(v + F/rho) - feq(v)
+        const T ssq = T(0.5 * ics) * (sx * sx + sy * sy);
+        // om feq(v) + feq(s) - feq(v):
+        //   even  w [om drho + rho (ics2h t - K1)],  t = (c.s)^2 + (om - 1)(c.v)^2,
+        //         K1 = (om - 1) vsq + ssq;
+        //   odd   w rho ics (c.s + (om - 1) c.v)
+        const T omm1 = om - T(1);
+        const T K0 = om * drho;
+        const T K1 = omm1 * vsq + ssq;
+        const T ri = rho * T(ics);
 #pragma unroll
         for (int b = 1; b < Q; ++b) {
             const int m = opposite<L>(b);
             if (m < b) continue;
             const T cv = T(L::cx[b]) * vx + T(L::cy[b]) * vy;
-            const T cd = T(L::cx[b]) * dx + T(L::cy[b]) * dy;
+            const T cs = T(L::cx[b]) * sx + T(L::cy[b]) * sy;
             const T w = T(L::w[b]);
-            const T es = w * (drho + rho * (T(ics2h) * cv * cv - vsq));
-            const T ea = w * rho * (T(ics) * cv);
-            const T ds = w * rho * (T(ics2h) * cd * (T(2) * cv + cd) - dsq);
-            const T da = w * rho * (T(ics) * cd);
+            const T q = omm1 * cv;
+            const T S = w * (K0 + rho * (T(ics2h) * (cs * cs + q * cv) - K1));
+            const T A = (w * ri) * (cs + q);
             const T gp = g[b], gm = g[m];
-            const T np = gp - om * (gp - (es + ea)) + (ds + da);
-            const T nm = gm - om * (gm - (es - ea)) + (ds - da);
+            const T np = gp + ((S + A) - om * gp);
+            const T nm = gm + ((S - A) - om * gm);
             dm += (gp - np) + (gm - nm);
             g[b] = np;
             g[m] = nm;
@@ -370,18 +394,32 @@ k_wide_tile2(StepArgs<T> a, int nbx, int nby, int sw)
     const int x0 = bx * TX, y0 = by * TY;
 
     // phase 1 (the per-thread node loop has a compile-time bound and is
-    // unrolled, so all of a thread's pulls are in flight together)
+    // unrolled, so all of a thread's pulls are in flight together).  A tile
+    // whose pulled region lies inside the grid (one test per block) takes
+    // its addresses without wrapping.
     constexpr int K1 = (P1N + NT - 1) / NT;
     T g[K1][Q];
+    if (x0 >= H1 + M && x0 + TX + H1 + M <= nx && y0 >= H1 + M && y0 + TY + H1 + M <= ny) {
 #pragma unroll
-    for (int q = 0; q < K1; ++q) {
-        const int i = tid + q * NT;
-        if (i < P1N) {
-            const int ly = i / P1W, lx = i - ly * P1W;
-            uint32_t xo[2 * M + 1], yo[2 * M + 1];
-            offsets_m<M>(wrap_near(x0 - H1 + lx, nx), nx, TS, xo);
-            offsets_m<M>(wrap_near(y0 - H1 + ly, ny), ny, rowb, yo);
-            pull_lat<T, L, M>(a.fin, n, xo, yo, g[q]);
+        for (int q = 0; q < K1; ++q) {
+            const int i = tid + q * NT;
+            if (i < P1N) {
+                const int ly = i / P1W, lx = i - ly * P1W;
+                pull_lat_inner<T, L>(a.fin, n, (uint32_t)(y0 - H1 + ly) * rowb + (uint32_t)(x0 - H1 + lx) * TS,
+                                     rowb, g[q]);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < K1; ++q) {
+            const int i = tid + q * NT;
+            if (i < P1N) {
+                const int ly = i / P1W, lx = i - ly * P1W;
+                uint32_t xo[2 * M + 1], yo[2 * M + 1];
+                offsets_m<M>(wrap_near(x0 - H1 + lx, nx), nx, TS, xo);
+                offsets_m<M>(wrap_near(y0 - H1 + ly, ny), ny, rowb, yo);
+                pull_lat<T, L, M>(a.fin, n, xo, yo, g[q]);
+            }
         }
     }
 #pragma unroll
