@@ -11,12 +11,19 @@ Stored:
           steady-state rule holds: max|u| checked every 100 steps and the run
           stopped at the first check whose change from the previous check is
           below 1e-10 (the literal rule, FP64).  The step it stopped at, the
-          observables and the centre lines there.
+          observables and the centre lines there;
+  tails   for each steady item that converges, the same oracle run sampled
+          every `tail_every` (500) steps up to `tail_steps` (200,000): the
+          observables at each sample.  The literal rule can fire at a turning
+          point of max|u| while the state still relaxes, so a run that stops
+          elsewhere is compared with the oracle's state at its own step.
 
 Only the oracle computes these values.  The stored file came from
     python tests/golden/make_sweep_64_oracle.py
 (each item in its own single-threaded process, -j of them at a time; about
-25 min with -j 2).
+25 min with -j 2), and the tails were added to it by
+    python tests/golden/make_sweep_64_oracle.py --tails-only -j 3
+(about 20 min).
 """
 import argparse
 import json
@@ -80,6 +87,21 @@ def run_steady(k, tol, every, max_steps):
     return r
 
 
+def run_tail(k, every, steps):
+    from oracle import oracle as O
+    t0 = time.time()
+    o = _oracle(k)
+    at, obs = [], {}
+    while o.steps < steps:
+        o.step(every)
+        fl = o.fields()
+        ob = _plain(O.observables(fl, o.cs2, o.G, o.c0))
+        at.append(o.steps)
+        for key in ("max_u", "mean_u", "l2_u", "dp", "rho_min", "rho_max", "mass"):
+            obs.setdefault(key, []).append(ob[key])
+    return {"item": k, "every": every, "steps": at, "obs": obs, "seconds": time.time() - t0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("-j", type=int, default=2)
@@ -90,8 +112,31 @@ def main():
     ap.add_argument("--max-steps", type=int, default=400000)
     ap.add_argument("--items", type=int, default=N_ITEMS, help="first N items only (for a quick check)")
     ap.add_argument("--out", default=OUT)
+    ap.add_argument("--tail-every", type=int, default=500)
+    ap.add_argument("--tail-steps", type=int, default=200000)
+    ap.add_argument("--tails-only", action="store_true",
+                    help="add the tails of the converged steady items to the existing file")
     a = ap.parse_args()
     os.environ["OMP_NUM_THREADS"] = "1"   # one core per item; set before any worker loads the oracle
+    if a.tails_only:
+        with open(a.out) as fh:
+            res = json.load(fh)
+        ks = [s["item"] for s in res["steady"] if s["converged"]]
+        t0 = time.time()
+        with ProcessPoolExecutor(max_workers=a.j) as ex:
+            fs = {ex.submit(run_tail, k, a.tail_every, a.tail_steps): k for k in ks}
+            tails = []
+            for f in fs:
+                r = f.result()
+                tails.append(r)
+                print("tail item %d: %d samples, %.0f s (total %.0f s)" % (
+                    r["item"], len(r["steps"]), r["seconds"], time.time() - t0), flush=True)
+        res["tail_every"], res["tail_steps"] = a.tail_every, a.tail_steps
+        res["tails"] = sorted(tails, key=lambda r: r["item"])
+        with open(a.out, "w") as fh:
+            json.dump(res, fh)
+        print("wrote", a.out, flush=True)
+        return
     from workload import sweep_items
     its = sweep_items(N_ITEMS, seed=SEED)
     smallest = sorted(range(N_ITEMS), key=lambda i: (its[i]["side"], i))[:a.n_steady]

@@ -23,10 +23,14 @@ steady  the 4 smallest items to the steady-state rule (max |u| change below
           rounding of its stored populations absorbs the mode's per-step
           growth (expected failure);
         - the FP32 batch finished in FP64 (sc_lbm_batch_promote, then the
-          literal rule): the oracle's steady observables to 2e-4 (max |u|),
-          2e-5 (mean |u|) and 1e-5 (Laplace jump, density extremes), the
-          spread of states that all meet the rule; item 27's slow mode,
-          which the FP32 stage does not resolve, develops in the FP64 stage.
+          literal rule): the observables of the oracle's own run at the step
+          where the finish stopped (the stored samples every 500 steps,
+          interpolated) to 1e-4 (max |u|), 5e-5 (mean |u|) and 1e-5 (Laplace
+          jump, density extremes): the FP32 stage's deviation, decaying in
+          the FP64 stage.  The rule can fire at a turning point of
+          max |u| while the state still relaxes, so the finish and the
+          oracle may stop far apart; item 27's slow mode, which the FP32
+          stage does not resolve, develops in the FP64 stage.
 """
 import json
 import math
@@ -186,6 +190,16 @@ def test_sweep_steady_fp32_batch(fp32_sweep, k):
     assert abs(ob["dp"] - ro["dp"]) <= 1e-4 * abs(ro["dp"])
 
 
+def _tail_at(k, step):
+    """The oracle's observables of item k at `step`, linearly interpolated
+    between its samples every `tail_every` steps (the slow relaxation moves
+    max|u| by about 1e-9 per 500 steps there)."""
+    t = next(r for r in GOLD["tails"] if r["item"] == k)
+    at = np.asarray(t["steps"], dtype=float)
+    assert at[0] <= step <= at[-1], (k, step, at[-1])
+    return {key: float(np.interp(step, at, np.asarray(v))) for key, v in t["obs"].items()}
+
+
 @pytest.mark.parametrize("k", [s["item"] for s in GOLD["steady"]])
 def test_sweep_steady_fp32_then_fp64(fp32_sweep, k):
     ref = _steady_ref(k)
@@ -196,16 +210,21 @@ def test_sweep_steady_fp32_then_fp64(fp32_sweep, k):
     if not _finite(ref["obs"]):
         assert by32 == -1 and by == -1
         return
-    ro = ref["obs"]
     assert by == 1
+    # The literal rule stops at the first check whose max|u| differs from the
+    # previous one by less than 1e-10.  Near a turning point of max|u| it can
+    # fire while the state still relaxes (item 63: the oracle stops at 5,200
+    # steps, and its max|u| falls by another 5e-4 of itself over the next
+    # 100,000), so the two runs may stop far apart.  The finished state is
+    # compared with the oracle's own run at the step where the finish stopped.
+    # What remains is the FP32 stage's deviation at the promotion, decaying in
+    # the FP64 stage: item 41 is promoted 2.2e-4 (max |u|) from the oracle's
+    # run at the same step and stops 1,100 FP64 steps later with 3.2e-5 left.
+    ro = _tail_at(k, steps)
     errs = {key: abs(ob[key] - ro[key]) / abs(ro[key]) for key in ("max_u", "mean_u", "dp", "rho_min", "rho_max")}
-    say("item %d finished in FP64 vs oracle: %s" % (k, " ".join("%s %.1e" % kv for kv in sorted(errs.items()))))
-    # Both runs stop where max |u| changes by less than 1e-10 per check, at
-    # different steps; a slowly converging state still moves by many such
-    # changes after that (item 63: 5e-6 of max |u| between the two stops;
-    # item 27, whose slow mode converges last, 9.3e-5 in max |u| and 7e-8
-    # in mean |u|)
-    assert errs["max_u"] <= 2e-4, (k, ob["max_u"], ro["max_u"])
-    assert errs["mean_u"] <= 2e-5, (k, ob["mean_u"], ro["mean_u"])
+    say("item %d finished in FP64 vs the oracle at step %d: %s" % (
+        k, steps, " ".join("%s %.1e" % kv for kv in sorted(errs.items()))))
+    assert errs["max_u"] <= 1e-4, (k, ob["max_u"], ro["max_u"])
+    assert errs["mean_u"] <= 5e-5, (k, ob["mean_u"], ro["mean_u"])
     for key in ("dp", "rho_min", "rho_max"):
         assert errs[key] <= 1e-5, (k, key, ob[key], ro[key])
