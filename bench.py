@@ -80,77 +80,86 @@ Q_OF = {"D2Q9": 9, "D3Q19": 19, "D2Q13": 13, "D2Q25": 25}
 # summary under profiles/).  Keyed by workload and launch shape; a shape
 # without an entry reports traffic null.  Re-measure after a kernel change.
 TRAFFIC_RATIO = {
-    # FP32 state: measured with the kernels of this tree (two-step D2Q9 body in
-    # tile2.h, any-lattice two-step shapes, 768-thread D3Q19 shapes)
-    ("d2q9_e8_256", "tile2x32x8t1024"): (0.675, 0.500),
-    ("d2q9_e8_256", "tile2x32x8t512"): (0.687, 0.500),
+    # measured with the kernels of this tree (pair-increment collisions,
+    # unwrapped pulls for interior two-step tiles)
+    ("d2q9_e8_256", "tile2x32x8t1024"): (0.678, 0.500),
+    ("d2q9_e8_256", "tile2x32x8t512"): (0.685, 0.500),
     ("d2q9_e8_256", "tile2x16x16"): (0.907, 0.500),
-    ("d2q9_e8_256", "tile2x32x16"): (0.690, 0.500),
-    ("d2q9_e8_256", "tile2x32x32"): (0.687, 0.500),
-    ("d2q9_e8_256", "tile2x32x8"): (0.696, 0.500),
-    ("d2q9_e8_256", "tile2x64x16"): (0.686, 0.500),
-    ("d2q9_e8_256", "tile2x64x8"): (0.693, 0.500),
-    ("d2q9_e8_256", "tile32x8r1"): (1.160, 1.000),
-    ("d2q9_e8_256", "tile64x4r1"): (1.167, 1.000),
+    ("d2q9_e8_256", "tile2x32x16"): (0.691, 0.500),
+    ("d2q9_e8_256", "tile2x32x32"): (0.684, 0.500),
+    ("d2q9_e8_256", "tile2x32x8"): (0.697, 0.500),
+    ("d2q9_e8_256", "tile2x64x16"): (0.687, 0.500),
+    ("d2q9_e8_256", "tile2x64x8"): (0.695, 0.500),
+    ("d2q9_e8_256", "tile32x8r1"): (1.157, 1.000),
+    ("d2q9_e8_256", "tile64x4r1"): (1.159, 1.000),
     ("d2q9_e8_8192", "tile2x32x8t1024"): (0.626, 0.500),
     ("d2q9_e8_8192", "tile2x32x8t512"): (0.626, 0.500),
-    ("d2q9_e8_8192", "tile2x16x16"): (1.415, 0.523),
-    ("d2q9_e8_8192", "tile2x32x16"): (0.655, 0.500),
+    ("d2q9_e8_8192", "tile2x16x16"): (1.450, 0.521),
+    ("d2q9_e8_8192", "tile2x32x16"): (0.647, 0.500),
     ("d2q9_e8_8192", "tile2x32x32"): (0.638, 0.500),
-    ("d2q9_e8_8192", "tile2x32x8"): (0.631, 0.500),
+    ("d2q9_e8_8192", "tile2x32x8"): (0.632, 0.500),
     ("d2q9_e8_8192", "tile2x64x16"): (0.563, 0.500),
     ("d2q9_e8_8192", "tile2x64x8"): (0.563, 0.500),
-    ("d2q9_e8_8192", "tile64x16r4"): (1.534, 1.000),
-    ("d3q19_mrt_e8_320", "march64x8r1h64pf1"): (1.383, 1.000),
-    ("d3q19_mrt_e8_320", "march64x8r1h32pf1"): (1.503, 1.000),
-    ("d3q19_mrt_e8_320", "march64x12r1h64pf1"): (1.304, 1.000),
-    ("d3q19_mrt_e8_320", "march64x12r1h32pf1"): (1.378, 1.000),
-    ("d3q19_mrt_e8_320", "march64x12r1h16pf1"): (1.505, 1.000),
+    ("d2q9_e8_8192", "tile64x16r4"): (1.543, 1.000),
+    ("d3q19_mrt_e8_320", "march64x8r1h64pf1"): (1.428, 1.000),
+    ("d3q19_mrt_e8_320", "march64x8r1h32pf1"): (1.562, 1.000),
+    ("d3q19_mrt_e8_320", "march64x12r1h64pf1"): (1.322, 1.000),
+    ("d3q19_mrt_e8_320", "march64x12r1h32pf1"): (1.395, 1.000),
+    ("d3q19_mrt_e8_320", "march64x12r1h16pf1"): (1.523, 1.000),
+    ("d3q19_mrt_e8_320", "rl64x8h64w4"): (2.726, 1.000),
+    ("d3q19_mrt_e8_320", "rl64x8h32w4"): (2.818, 1.000),
     # the three persistent 64 x 8 shapes share one grid (one block per CU):
     # their mean over the autotuner's dispatches
-    ("d3q19_mrt_e8_320", "pmarch64x8r1h64pf1"): (1.320, 1.000),
-    ("d3q19_mrt_e8_320", "pmarch64x8r1h32pf1"): (1.320, 1.000),
-    ("d3q19_mrt_e8_320", "pmarch64x8r1h16pf1"): (1.320, 1.000),
-    ("d2q13_e6_pr_edm_8192", "wide2x32x8t256"): (0.633, 0.500),
-    ("d2q13_e6_pr_edm_8192", "wide2x64x8t512"): (0.563, 0.500),
-    ("d2q13_e6_pr_edm_8192", "wide2x64x16t1024"): (0.563, 0.500),
-    ("d2q13_e6_pr_edm_8192", "wide2x128x8t1024"): (0.533, 0.500),
-    ("d2q13_e6_pr_edm_8192", "wide2x64x8t1024"): (0.563, 0.500),
-    ("d2q13_e6_pr_edm_8192", "wide2x64x12t768"): (0.564, 0.500),
-    ("d2q13_e6_pr_edm_8192", "wide2x64x12t1024"): (0.564, 0.500),
-    ("d2q13_e6_pr_edm_8192", "wide128x16r2"): (1.366, 1.000),
-    ("d2q13_e6_pr_edm_8192", "wide256x8r2"): (1.372, 1.000),
-    ("d2q13_e6_pr_edm_8192", "wide64x16r2"): (1.798, 1.000),
-    ("d2q13_e6_pr_edm_8192", "wide64x16r4"): (1.864, 1.000),
-    ("d2q25_e8_pr_edm_8192", "wide2x32x8t256"): (0.669, 0.500),
-    ("d2q25_e8_pr_edm_8192", "wide2x64x8t512"): (0.600, 0.500),
-    ("d2q25_e8_pr_edm_8192", "wide2x64x8t1024"): (0.642, 0.500),
-    ("d2q25_e8_pr_edm_8192", "wide2x64x12t768"): (0.583, 0.500),
-    ("d2q25_e8_pr_edm_8192", "wide2x64x12t1024"): (0.592, 0.500),
-    ("d2q25_e8_pr_edm_8192", "wide128x16r2"): (1.439, 1.000),
-    ("d2q25_e8_pr_edm_8192", "wide256x8r2"): (1.401, 1.000),
-    ("d2q25_e8_pr_edm_8192", "wide64x16r2"): (1.797, 1.000),
-    ("d2q25_e8_pr_edm_8192", "wide64x16r4"): (2.117, 1.000),
-    # FP64 state and the 128^3 D3Q19 workload: the kernels' arithmetic is
-    # unchanged since these were measured
+    ("d3q19_mrt_e8_320", "pmarch64x8r1h64pf1"): (1.330, 1.000),
+    ("d3q19_mrt_e8_320", "pmarch64x8r1h32pf1"): (1.330, 1.000),
+    ("d3q19_mrt_e8_320", "pmarch64x8r1h16pf1"): (1.330, 1.000),
     ("d3q19_mrt_e8_128", "march64x8r1h16pf1"): (1.253, 1.000),
     ("d3q19_mrt_e8_128", "march64x8r1h32pf1"): (1.198, 1.000),
     ("d3q19_mrt_e8_128", "march64x8r1h64pf1"): (1.198, 1.000),
     ("d3q19_mrt_e8_128", "march64x8r1h16"): (1.253, 1.000),
+    ("d3q19_mrt_e8_128", "pmarch64x8r1h16pf1"): (1.253, 1.000),
+    ("d3q19_mrt_e8_128", "pmarch64x8r1h32pf1"): (1.198, 1.000),
+    ("d3q19_mrt_e8_128", "pmarch64x8r1h64pf1"): (1.198, 1.000),
+    ("d3q19_mrt_e8_128", "rl64x8h64w4"): (1.196, 1.000),
+    ("d3q19_mrt_e8_128", "rl64x8h32w4"): (1.265, 1.000),
+    ("d2q13_e6_pr_edm_8192", "wide2x32x8t256"): (0.633, 0.500),
+    ("d2q13_e6_pr_edm_8192", "wide2x64x8t512"): (0.563, 0.500),
+    ("d2q13_e6_pr_edm_8192", "wide2x64x16t1024"): (0.566, 0.500),
+    ("d2q13_e6_pr_edm_8192", "wide2x128x8t1024"): (0.534, 0.500),
+    ("d2q13_e6_pr_edm_8192", "wide2x64x8t1024"): (0.565, 0.500),
+    ("d2q13_e6_pr_edm_8192", "wide2x64x12t768"): (0.564, 0.500),
+    ("d2q13_e6_pr_edm_8192", "wide2x64x12t1024"): (0.564, 0.500),
+    ("d2q13_e6_pr_edm_8192", "wide128x16r2"): (1.360, 1.000),
+    ("d2q13_e6_pr_edm_8192", "wide256x8r2"): (1.355, 1.000),
+    ("d2q13_e6_pr_edm_8192", "wide64x16r2"): (1.795, 1.000),
+    ("d2q13_e6_pr_edm_8192", "wide64x16r4"): (1.863, 1.000),
+    ("d2q25_e8_pr_edm_8192", "wide2x32x8t256"): (0.666, 0.500),
+    ("d2q25_e8_pr_edm_8192", "wide2x64x8t512"): (0.606, 0.500),
+    ("d2q25_e8_pr_edm_8192", "wide2x64x8t1024"): (0.676, 0.500),
+    ("d2q25_e8_pr_edm_8192", "wide2x64x12t768"): (0.597, 0.500),
+    ("d2q25_e8_pr_edm_8192", "wide2x64x12t1024"): (0.617, 0.500),
+    ("d2q25_e8_pr_edm_8192", "wide128x16r2"): (1.442, 1.000),
+    ("d2q25_e8_pr_edm_8192", "wide256x8r2"): (1.407, 1.000),
+    ("d2q25_e8_pr_edm_8192", "wide64x16r2"): (1.796, 1.000),
+    ("d2q25_e8_pr_edm_8192", "wide64x16r4"): (2.138, 1.000),
+    # FP64 state (write above 1: the shapes whose window spills to scratch)
     ("d2q9_e8_8192_fp64", "tile2x16x16"): (0.626, 0.500),
-    ("d2q9_e8_8192_fp64", "tile2x32x8"): (0.564, 0.500),
-    ("d2q9_e8_8192_fp64", "tile2x32x8t512"): (0.564, 0.500),
-    ("d2q9_e8_8192_fp64", "tile2x32x8t1024"): (0.564, 0.500),
-    ("d2q9_e8_8192_fp64", "tile2x32x16"): (0.564, 0.500),
-    ("d2q9_e8_8192_fp64", "tile2x32x32"): (0.564, 0.500),
+    ("d2q9_e8_8192_fp64", "tile2x32x8"): (0.563, 0.500),
+    ("d2q9_e8_8192_fp64", "tile2x32x8t512"): (0.563, 0.500),
+    ("d2q9_e8_8192_fp64", "tile2x32x8t1024"): (0.563, 0.500),
+    ("d2q9_e8_8192_fp64", "tile2x32x16"): (0.563, 0.500),
+    ("d2q9_e8_8192_fp64", "tile2x32x32"): (0.563, 0.500),
     ("d2q9_e8_8192_fp64", "tile2x64x8"): (0.532, 0.500),
-    ("d2q9_e8_8192_fp64", "tile2x64x16"): (0.534, 0.500),
-    ("d3q19_mrt_e8_320_fp64", "march32x16h16"): (1.620, 1.000),
-    ("d3q19_mrt_e8_320_fp64", "march32x16h32"): (1.460, 1.000),
-    ("d3q19_mrt_e8_320_fp64", "march32x8r1h32pf1"): (1.566, 1.000),
-    ("d3q19_mrt_e8_320_fp64", "march32x8r1h64pf1"): (1.502, 1.000),
-    ("d3q19_mrt_e8_320_fp64", "rl64x8h64w4"): (2.531, 1.000),
-    ("d3q19_mrt_e8_320_fp64", "rl64x8h32w4"): (2.622, 1.000),
+    ("d2q9_e8_8192_fp64", "tile2x64x16"): (0.533, 0.500),
+    ("d3q19_mrt_e8_320_fp64", "march32x16h16"): (1.639, 1.000),
+    ("d3q19_mrt_e8_320_fp64", "march32x16h32"): (1.459, 1.000),
+    ("d3q19_mrt_e8_320_fp64", "march32x8r1h32pf1"): (1.633, 1.000),
+    ("d3q19_mrt_e8_320_fp64", "march32x8r1h64pf1"): (1.560, 1.000),
+    ("d3q19_mrt_e8_320_fp64", "pmarch64x8r1h64pf1"): (3.357, 1.906),
+    ("d3q19_mrt_e8_320_fp64", "pmarch64x8r1h32pf1"): (3.357, 1.906),
+    ("d3q19_mrt_e8_320_fp64", "pmarch64x8r1h16pf1"): (3.357, 1.906),
+    ("d3q19_mrt_e8_320_fp64", "rl64x8h64w4"): (2.538, 1.000),
+    ("d3q19_mrt_e8_320_fp64", "rl64x8h32w4"): (2.627, 1.000),
 }
 
 
