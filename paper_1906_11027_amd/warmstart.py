@@ -387,7 +387,7 @@ def evaluate(ds, epochs=300, batch=16, lr=1e-3, fp64_baseline=8, seed=2026, tols
     return res
 
 
-def run_experiment(n_train=2000, n_test=64, side=256, tol=1e-8, epochs=300, batch=16, lr=1e-3,
+def run_experiment(n_train=2000, n_test=200, side=256, tol=1e-8, epochs=300, batch=16, lr=1e-3,
                    max_steps=150000, obs_every=200, chunk=64, fp64_baseline=8, seed=2026, jitter=False,
                    tols=(1e-10,), log=print):
     """The 256^2 warm-start experiment: dataset from batched sweeps, then evaluate()."""
@@ -426,7 +426,7 @@ if __name__ == "__main__":
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     ap = argparse.ArgumentParser(description="learned warm start experiment (droplet sweep on side^2 grids)")
     ap.add_argument("--n-train", type=int, default=2000)
-    ap.add_argument("--n-test", type=int, default=64)
+    ap.add_argument("--n-test", type=int, default=200)
     ap.add_argument("--side", type=int, default=256)
     ap.add_argument("--tol", type=float, default=1e-8, help="steady-state rule of the dataset runs")
     ap.add_argument("--eval-tols", default="1e-10", help="rules the starts are compared at")

@@ -124,6 +124,25 @@ def test_wide_variants_and_state_layout(lattice):
     sim.close()
 
 
+@pytest.mark.parametrize("lattice,forcing", [("D2Q9", "guo"), ("D2Q13", "edm"), ("D2Q25", "edm")])
+def test_two_step_interior_and_edge_tiles(lattice, forcing):
+    """Every launch shape on a ragged 283 x 61 grid, large enough that each
+    two-step shape (tiles up to 128 x 8 and 64 x 16) has tiles whose pulled
+    region lies inside the grid (unwrapped addresses) beside tiles at its
+    edge (wrapped ones): FP64 state against the oracle after 13 steps (six
+    two-step launches and a one-step one)."""
+    rho0 = droplet_rho((283, 61), 20, seed=14)
+    kw = dict(order=8, G=g_scaled(lattice), tau=0.85, forcing=forcing)
+    orc = O.Oracle(rho0, lattice, **kw)
+    orc.step(13)
+    for v in range(B.sc_lbm_num_variants(B.make_params(lattice, forcing=forcing))):
+        say("case interior/edge tiles", lattice, forcing, "variant", v)
+        sim = Sim(rho0, lattice, variant=v, precision="fp64", **kw)
+        sim.step(13)
+        _compare(sim, orc, "fp64", "%s %s variant %s" % (lattice, forcing, sim.variant))
+        sim.close()
+
+
 @pytest.mark.parametrize("variant", [-1, 6, 9])
 @pytest.mark.parametrize("shape", [(3, 5), (1, 9), (2, 2), (33, 7)])
 @pytest.mark.parametrize("lattice", ["D2Q13", "D2Q25"])
