@@ -117,15 +117,18 @@ __device__ __forceinline__ void strip_tile(int L, int nbx, int nby, int sw, int&
 // than 2^32 bytes (checked on the host), so a node is addressed as the plane's
 // uniform base pointer (scalar registers) plus a 32-bit per-lane byte offset,
 // the global-load form with a scalar base and a 32-bit vector offset.
+// The state is device global memory; the accesses say so, so that pointers
+// read from memory (the batched work list's items) also take global rather
+// than flat loads and stores.
 template <typename T>
 __device__ __forceinline__ T ld_off(const T* __restrict__ base, uint32_t off)
 {
-    return *(const T*)((const char*)base + off);
+    return *(const __attribute__((address_space(1))) T*)((const char*)base + off);
 }
 template <typename T>
 __device__ __forceinline__ void st_off(T* __restrict__ base, uint32_t off, T v)
 {
-    *(T*)((char*)base + off) = v;
+    *(__attribute__((address_space(1))) T*)((char*)base + off) = v;
 }
 
 // ---------------------------------------------------------------- D2Q9 ----
