@@ -160,6 +160,9 @@ TRAFFIC_RATIO = {
     ("d3q19_mrt_e8_320_fp64", "pmarch64x8r1h64pf1"): (3.357, 1.906),
     ("d3q19_mrt_e8_320_fp64", "pmarch64x8r1h32pf1"): (3.357, 1.906),
     ("d3q19_mrt_e8_320_fp64", "pmarch64x8r1h16pf1"): (3.357, 1.906),
+    # the persistent 32 x 8 shapes share one grid: their mean
+    ("d3q19_mrt_e8_320_fp64", "pmarch32x8r1h64pf1"): (1.395, 1.000),
+    ("d3q19_mrt_e8_320_fp64", "pmarch32x8r1h32pf1"): (1.395, 1.000),
     ("d3q19_mrt_e8_320_fp64", "rl64x8h64w4"): (2.538, 1.000),
     ("d3q19_mrt_e8_320_fp64", "rl64x8h32w4"): (2.627, 1.000),
 }
