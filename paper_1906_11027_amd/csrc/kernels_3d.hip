@@ -373,8 +373,8 @@ static const Shape3D kShapes3D[] = {
     {64, 8, 1, 16, "pmarch64x8r1h16pf1"},
     // the persistent form of the 256-thread window march, whose FP64
     // window fits in registers (256 VGPRs, two waves per SIMD): the FP64
-    // state at 320^3 runs 3.35 ms per step against 3.39 for the re-pull
-    // march and fetches 1.40 of the algorithmic reads against 2.54
+    // state at 320^3 runs within 1% of the re-pull march (3.35-3.39 ms per
+    // step) and fetches 1.40 of the algorithmic reads against 2.54
     {32, 8, 1, 64, "pmarch32x8r1h64pf1"},
     {32, 8, 1, 32, "pmarch32x8r1h32pf1"},
 };
