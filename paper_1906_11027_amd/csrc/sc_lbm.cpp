@@ -129,7 +129,7 @@ static const char* const kShapesWide[] = {"wide64x8r2",     "wide32x8r1",     "w
                                           "wide64x16r2",    "wide128x16r2",   "wide256x8r2",
                                           "wide2x32x8t256", "wide2x64x8t512", "wide2x64x16t1024",
                                           "wide2x128x8t1024", "wide2x64x8t1024", "wide2x64x12t768",
-                                          "wide2x64x12t1024"};
+                                          "wide2x64x12t1024", "wide2x64x16t768", "wide2x128x12t1024"};
 int num_variants_wide() { return (int)(sizeof(kShapesWide) / sizeof(kShapesWide[0])); }
 // shapes 6.. advance two steps per launch (no walls)
 int variant_steps_wide(int v) { return v >= 6 ? 2 : 1; }

@@ -335,6 +335,11 @@ k_wide_tile(StepArgs<T> a, int nbx, int nby, int sw)
 //            collide, store.
 // The state is read and written once per two updates; the (R + M) halo of
 // phase 2 is collided again by the neighbouring tiles.
+// The LDS copy s1 keeps each population only where phases 3 and 4 pull it:
+// population b of the node at phase-2 coordinates (cx, cy) is pulled by the
+// phase-3 node (cx + c_bx - M, cy + c_by - M), so plane b is the psi2 region
+// (P2W x P2H) shifted by (M - c_b).  A pull then reads every plane at the
+// pulling node's own psi2 index, and s1 holds Q P2N values instead of Q C1N.
 template <int Q, int R, int M, int TX, int TY>
 struct WideTile2 {
     static constexpr int H1 = 2 * R + M, P1W = TX + 2 * H1, P1H = TY + 2 * H1, P1N = P1W * P1H;
@@ -343,7 +348,7 @@ struct WideTile2 {
     template <typename T>
     static constexpr size_t lds_bytes()
     {
-        return sizeof(T) * ((size_t)P1N + P2N + (size_t)Q * C1N);
+        return sizeof(T) * ((size_t)P1N + P2N + (size_t)Q * P2N);
     }
 };
 
@@ -379,11 +384,11 @@ k_wide_tile2(StepArgs<T> a, int nbx, int nby, int sw)
     constexpr int R = Stencil<2, ORDER>::R;
     using W = WideTile2<Q, R, M, TX, TY>;
     constexpr int H1 = W::H1, P1W = W::P1W, P1N = W::P1N;
-    constexpr int HC = W::HC, C1W = W::C1W, C1H = W::C1H, C1N = W::C1N;
-    constexpr int P2W = W::P2W, P2N = W::P2N;
+    constexpr int C1W = W::C1W, C1H = W::C1H;
+    constexpr int P2W = W::P2W, P2H = W::P2H, P2N = W::P2N;
     __shared__ T psi1[P1N];
     __shared__ T psi2[P2N];
-    __shared__ T s1[Q * C1N];
+    __shared__ T s1[Q * P2N];
 
     const int nx = a.nx, ny = a.ny;
     const int64_t n = a.n;
@@ -439,27 +444,28 @@ k_wide_tile2(StepArgs<T> a, int nbx, int nby, int sw)
                 T Fx, Fy;
                 wide_force_at<T, ORDER>(psi1 + ly * P1W + lx, P1W, a.gc0, Fx, Fy);
                 collide_lat<T, L, EDM>(g[q], TreeSum<0, Q>::of(g[q]), Fx, Fy, a);
-                const int ci = cy * C1W + cx;
 #pragma unroll
-                for (int b = 0; b < Q; ++b) s1[b * C1N + ci] = g[q][b];
+                for (int b = 0; b < Q; ++b) {
+                    const int wx = cx - (M - L::cx[b]), wy = cy - (M - L::cy[b]);
+                    if (wx >= 0 && wx < P2W && wy >= 0 && wy < P2H) s1[b * P2N + wy * P2W + wx] = g[q][b];
+                }
             }
         }
     }
     __syncthreads();
-    // pull at t+2 of the node at s1 coordinates (cx, cy)
-    auto pull_s1 = [&](int cx, int cy, T (&h)[Q]) {
+    // pull at t+2 of the node at psi2 index i
+    auto pull_s1 = [&](int i, T (&h)[Q]) {
 #pragma unroll
-        for (int b = 0; b < Q; ++b) h[b] = s1[b * C1N + (cy - L::cy[b]) * C1W + cx - L::cx[b]];
+        for (int b = 0; b < Q; ++b) h[b] = s1[b * P2N + i];
     };
-    // phase 3: psi at t+2 on the tile + R (s1 coordinates offset by M)
+    // phase 3: psi at t+2 on the tile + R
     constexpr int K3 = (P2N + NT - 1) / NT;
 #pragma unroll
     for (int q = 0; q < K3; ++q) {
         const int i = tid + q * NT;
         if (i < P2N) {
-            const int ly = i / P2W, lx = i - ly * P2W;
             T h[Q];
-            pull_s1(lx + M, ly + M, h);
+            pull_s1(i, h);
             psi2[i] = psi_of(a.rho_ref + TreeSum<0, Q>::of(h), a);
         }
     }
@@ -472,7 +478,7 @@ k_wide_tile2(StepArgs<T> a, int nbx, int nby, int sw)
         if (i >= TX * TY) break;
         const int lx = i % TX, ly = i / TX;
         T h[Q];
-        pull_s1(lx + HC, ly + HC, h);
+        pull_s1((ly + R) * P2W + lx + R, h);
         T Fx, Fy;
         wide_force_at<T, ORDER>(psi2 + (ly + R) * P2W + lx + R, P2W, a.gc0, Fx, Fy);
         collide_lat<T, L, EDM>(h, TreeSum<0, Q>::of(h), Fx, Fy, a);
@@ -530,8 +536,8 @@ static hipError_t launch_wide_shape(const StepArgs<T>& a, int variant, hipStream
     case 4: return launch_wide_tile<T, L, ORDER, EDM, WALLS, 128, 16, 2>(a, s);
     case 5: return launch_wide_tile<T, L, ORDER, EDM, WALLS, 256, 8, 2>(a, s);
     // two steps per launch (no walls: the wall kernels step one at a time);
-    // at 8192^2 the tuner picks 64 x 8 with 1024 threads for D2Q13 E6 and
-    // 64 x 12 with 1024 for D2Q25 E8 (its 156 KB of LDS in FP32); a 32 x 16
+    // at 8192^2 the tuner picks 64 x 12 with 768 threads for D2Q13 E6 and
+    // 64 x 16 with 768 for D2Q25 E8 (150 KB of LDS in FP32); a 32 x 16
     // tile with 512 threads was slower on both
     case 6:
         if constexpr (!WALLS) return launch_wide_tile2<T, L, ORDER, EDM, 32, 8, 256>(a, s);
@@ -553,6 +559,14 @@ static hipError_t launch_wide_shape(const StepArgs<T>& a, int variant, hipStream
         return hipErrorInvalidValue;
     case 12:
         if constexpr (!WALLS) return launch_wide_tile2<T, L, ORDER, EDM, 64, 12, 1024>(a, s);
+        return hipErrorInvalidValue;
+    // larger tiles, which the windowed post-collision copy fits in LDS:
+    // 64 x 16 for D2Q25 E8 (150 KB in FP32), 128 x 12 for D2Q13
+    case 13:
+        if constexpr (!WALLS) return launch_wide_tile2<T, L, ORDER, EDM, 64, 16, 768>(a, s);
+        return hipErrorInvalidValue;
+    case 14:
+        if constexpr (!WALLS) return launch_wide_tile2<T, L, ORDER, EDM, 128, 12, 1024>(a, s);
         return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
