@@ -486,7 +486,7 @@ k_wide_tile2(StepArgs<T> a, int nbx, int nby, int sw)
         if (xr < nx && yr < ny) {
             const uint32_t off = (uint32_t)yr * rowb + (uint32_t)xr * TS;
 #pragma unroll
-            for (int b = 0; b < Q; ++b) st_off(a.fout + b * n, off, h[b]);
+            for (int b = 0; b < Q; ++b) st_off_nt(a.fout + b * n, off, h[b]);
         }
     }
 }
