@@ -537,8 +537,9 @@ static hipError_t launch_wide_shape(const StepArgs<T>& a, int variant, hipStream
     case 5: return launch_wide_tile<T, L, ORDER, EDM, WALLS, 256, 8, 2>(a, s);
     // two steps per launch (no walls: the wall kernels step one at a time);
     // at 8192^2 the tuner picks 64 x 12 with 768 threads for D2Q13 E6 and
-    // 64 x 16 with 768 for D2Q25 E8 (150 KB of LDS in FP32); a 32 x 16
-    // tile with 512 threads was slower on both
+    // 64 x 16 with 1024 for D2Q25 E8 (150 KB of LDS in FP32).  A 32 x 16
+    // tile with 512 threads (80 KB for D2Q25, two blocks per CU) tied on
+    // D2Q25 (2.28 ms per step) and was 4% slower on D2Q13.
     case 6:
         if constexpr (!WALLS) return launch_wide_tile2<T, L, ORDER, EDM, 32, 8, 256>(a, s);
         return hipErrorInvalidValue;
