@@ -2,7 +2,6 @@
 a nested-loop evaluation of its defining sum, and every gradient against
 central finite differences of the loss."""
 import numpy as np
-import pytest
 
 from oracle import conv as C
 
