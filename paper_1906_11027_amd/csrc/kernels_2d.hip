@@ -241,7 +241,7 @@ k_d2q9_tile2(StepArgs<T> a, int nbx, int nby, int sw)
     __shared__ T s1[9 * LD::C1N];
     int bx, by;
     strip_tile(xcd_swizzle(blockIdx.x, gridDim.x), nbx, nby, sw, bx, by);
-    d2q9_tile2_body<T, ORDER, TX, TY, NT>(a, bx * TX, by * TY, psi1, psi2, s1);
+    d2q9_tile2_body<T, ORDER, TX, TY, NT, true>(a, bx * TX, by * TY, psi1, psi2, s1);
 }
 
 // ------------------------------------------------------------ dispatch ----

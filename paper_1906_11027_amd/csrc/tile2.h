@@ -32,8 +32,10 @@ struct Tile2Lds {
 
 // The two steps of one tile at origin (x0, y0); psi1, psi2 and s1 point to
 // LDS of at least the sizes of Tile2Lds<R, TX, TY>.  Every thread of the
-// NT-thread block calls it (barriers inside).
-template <typename T, int ORDER, int TX, int TY, int NT>
+// NT-thread block calls it (barriers inside).  NTSTORE marks the output
+// stores non-temporal (the single-grid kernel; the batched sweep keeps
+// plain stores).
+template <typename T, int ORDER, int TX, int TY, int NT, bool NTSTORE = false>
 __device__ __forceinline__ void d2q9_tile2_body(const StepArgs<T>& a, int x0, int y0, T* __restrict__ psi1,
                                                 T* __restrict__ psi2, T* __restrict__ s1)
 {
@@ -167,7 +169,10 @@ __device__ __forceinline__ void d2q9_tile2_body(const StepArgs<T>& a, int x0, in
         if (xr < nx && yr < ny) {
             const uint32_t off = (uint32_t)yr * rowb + (uint32_t)xr * TS;
 #pragma unroll
-            for (int b = 0; b < 9; ++b) st_off(a.fout + b * n, off, g[b]);
+            for (int b = 0; b < 9; ++b) {
+                if constexpr (NTSTORE) st_off_nt(a.fout + b * n, off, g[b]);
+                else st_off(a.fout + b * n, off, g[b]);
+            }
         }
     }
 }
