@@ -84,8 +84,8 @@ TRAFFIC_RATIO = {
     # unwrapped pulls for interior two-step tiles; the D3Q19 FP32 window
     # marches re-counted after the state accesses took the global address
     # space, which changed their register allocation; the any-lattice and
-    # the single-grid D2Q9 two-step shapes re-counted with their
-    # non-temporal stores)
+    # the single-grid D2Q9 two-step shapes and the FP64 D3Q19 marches
+    # re-counted with their non-temporal stores)
     ("d2q9_e8_256", "tile2x32x8t1024"): (0.678, 0.500),
     ("d2q9_e8_256", "tile2x32x8t512"): (0.685, 0.500),
     ("d2q9_e8_256", "tile2x16x16"): (0.907, 0.557),
@@ -163,18 +163,18 @@ TRAFFIC_RATIO = {
     ("d2q9_e8_8192_fp64", "tile2x32x32"): (0.565, 0.500),
     ("d2q9_e8_8192_fp64", "tile2x64x8"): (0.532, 0.500),
     ("d2q9_e8_8192_fp64", "tile2x64x16"): (0.532, 0.500),
-    ("d3q19_mrt_e8_320_fp64", "march32x16h16"): (1.639, 1.000),
-    ("d3q19_mrt_e8_320_fp64", "march32x16h32"): (1.459, 1.000),
-    ("d3q19_mrt_e8_320_fp64", "march32x8r1h32pf1"): (1.633, 1.000),
-    ("d3q19_mrt_e8_320_fp64", "march32x8r1h64pf1"): (1.560, 1.000),
-    ("d3q19_mrt_e8_320_fp64", "pmarch64x8r1h64pf1"): (3.357, 1.906),
-    ("d3q19_mrt_e8_320_fp64", "pmarch64x8r1h32pf1"): (3.357, 1.906),
-    ("d3q19_mrt_e8_320_fp64", "pmarch64x8r1h16pf1"): (3.357, 1.906),
+    ("d3q19_mrt_e8_320_fp64", "march32x16h16"): (1.646, 1.000),
+    ("d3q19_mrt_e8_320_fp64", "march32x16h32"): (1.369, 1.000),
+    ("d3q19_mrt_e8_320_fp64", "march32x8r1h32pf1"): (1.436, 1.000),
+    ("d3q19_mrt_e8_320_fp64", "march32x8r1h64pf1"): (1.321, 1.000),
+    ("d3q19_mrt_e8_320_fp64", "pmarch64x8r1h64pf1"): (3.165, 1.902),
+    ("d3q19_mrt_e8_320_fp64", "pmarch64x8r1h32pf1"): (3.165, 1.902),
+    ("d3q19_mrt_e8_320_fp64", "pmarch64x8r1h16pf1"): (3.165, 1.902),
     # the persistent 32 x 8 shapes share one grid: their mean
-    ("d3q19_mrt_e8_320_fp64", "pmarch32x8r1h64pf1"): (1.395, 1.000),
-    ("d3q19_mrt_e8_320_fp64", "pmarch32x8r1h32pf1"): (1.395, 1.000),
-    ("d3q19_mrt_e8_320_fp64", "rl64x8h64w4"): (2.538, 1.000),
-    ("d3q19_mrt_e8_320_fp64", "rl64x8h32w4"): (2.627, 1.000),
+    ("d3q19_mrt_e8_320_fp64", "pmarch32x8r1h64pf1"): (1.341, 1.000),
+    ("d3q19_mrt_e8_320_fp64", "pmarch32x8r1h32pf1"): (1.341, 1.000),
+    ("d3q19_mrt_e8_320_fp64", "rl64x8h64w4"): (2.345, 1.000),
+    ("d3q19_mrt_e8_320_fp64", "rl64x8h32w4"): (2.460, 1.000),
 }
 
 

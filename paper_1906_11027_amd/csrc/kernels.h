@@ -132,8 +132,9 @@ __device__ __forceinline__ void st_off(T* __restrict__ base, uint32_t off, T v)
 }
 // the same store marked non-temporal.  Measured per kernel: the two-step
 // kernels of one grid gain with it at 8192^2 (D2Q25 5%, D2Q13 3%, D2Q9
-// FP64 1.7%, FP32 0.3%; 256^2 unchanged); the D3Q19 marches and the
-// batched sweep lost 4%, so they keep the plain store.
+// FP64 1.7%, FP32 0.3%; 256^2 unchanged), and so do the FP64 D3Q19 marches
+// at 320^3 (3-5%); the FP32 D3Q19 marches and the batched sweep lost 4%,
+// so they keep the plain store.
 template <typename T>
 __device__ __forceinline__ void st_off_nt(T* __restrict__ base, uint32_t off, T v)
 {

@@ -171,7 +171,10 @@ __device__ __forceinline__ void march_item(const StepArgs<T>& a, int H, int nbx,
                         if (xin && yin[k] && zr < nz) {
                             const uint32_t off = (uint32_t)zr * planeb + yo[k][1] + xo[1];
 #pragma unroll
-                            for (int b = 0; b < 19; ++b) st_off(a.fout + b * n, off, g[sc][k][b]);
+                            for (int b = 0; b < 19; ++b) {
+                                if constexpr (sizeof(T) == 8) st_off_nt(a.fout + b * n, off, g[sc][k][b]);
+                                else st_off(a.fout + b * n, off, g[sc][k][b]);
+                            }
                         }
                     }
                 }
@@ -326,7 +329,10 @@ k_d3q19_march_rl(StepArgs<T> a, int H, int nbx, int nby)
             if (inxy && zr < nz) {
                 const uint32_t off = (uint32_t)zr * planeb + yo[1] + xo[1];
 #pragma unroll
-                for (int b = 0; b < 19; ++b) st_off(a.fout + b * n, off, gc[b]);
+                for (int b = 0; b < 19; ++b) {
+                    if constexpr (sizeof(T) == 8) st_off_nt(a.fout + b * n, off, gc[b]);
+                    else st_off(a.fout + b * n, off, gc[b]);
+                }
             }
         }
     }
