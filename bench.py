@@ -485,7 +485,7 @@ def main():
                     help="also run 5 device copies of 256 MiB (reference dispatches for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(a domain would shard into slabs along its slowest axis with a halo exchange per step; "
               "not built)", file=sys.stderr)
         sys.exit(2)
